@@ -1,0 +1,254 @@
+"""Quantics MPS arithmetic in FP64.  TEST INFRASTRUCTURE.
+
+Representation (Sec. 4.1, eq. 8): a field on a 2^n x 2^n grid is a tensor with
+K = 2n binary indices; sites 1..n are the bits x_{n-1} .. x_0 of the horizontal
+index (most significant first) and sites n+1..2n the bits z_{n-1} .. z_0
+(eq. 3).  This is exactly the C-order reshape of u[x, z] to [2]*K.  Core k is a
+real array G_k of shape (r_{k-1}, 2, r_k) with r_0 = r_K = 1 (the fields are
+real, so the complex cores of eq. 8 are not needed).
+
+An MPO core has shape (w_left, w_right, 2, 2) indexed [a_l, a_r, s_out, s_in].
+"""
+import numpy as np
+
+# Local operators (matrices [s_out, s_in]).
+I2 = np.eye(2)
+SIGMA_PLUS = np.array([[0.0, 0.0], [1.0, 0.0]])   # |1><0|
+SIGMA_MINUS = np.array([[0.0, 1.0], [0.0, 0.0]])  # |0><1|
+
+
+# ---------------------------------------------------------------------------
+# dense <-> cores
+# ---------------------------------------------------------------------------
+
+def to_dense(cores):
+    """Contract the chain; returns the flat vector of length 2^K."""
+    v = np.ones((1, 1))
+    for G in cores:
+        r0, d, r1 = G.shape
+        v = (v @ G.reshape(r0, d * r1)).reshape(-1, r1)
+    return v.reshape(-1)
+
+
+def bonds_of(cores):
+    return [cores[0].shape[0]] + [G.shape[2] for G in cores]
+
+
+def choose_rank(s, eps, chi_max):
+    """Truncation rule of Sec. 4.3: discard sigma_i < eps * sigma_max, cap at chi_max.
+
+    At least one singular value is kept; an all-zero matrix keeps rank 1 (its
+    kept factor is zero, so the tensor stays zero).
+    """
+    if s.size == 0:
+        return 1
+    if s[0] <= 0.0:
+        return 1
+    r = int(np.count_nonzero(s >= eps * s[0]))
+    return max(1, min(r, chi_max))
+
+
+def tt_svd(t, K, eps, chi_max, log=None):
+    """Right-to-left truncated TT-SVD of a dense tensor with 2^K entries.
+
+    Moving from the last site to the first, the current tensor is unfolded as
+    (2^{k-1}, 2 r_k), its SVD is truncated with ``choose_rank`` and the kept
+    right singular vectors become core k; U_r Sigma_r carries on to the left.
+    This is the sequential-SVD construction of Sec. 4.1 and, applied to an
+    arbitrary tensor, the definition of the rounding used below.
+    """
+    X = np.asarray(t, dtype=np.float64).reshape(-1, 1)
+    cores = [None] * K
+    rho = 1
+    for k in range(K - 1, 0, -1):
+        M = X.reshape(-1, 2 * rho)
+        U, s, Vt = np.linalg.svd(M, full_matrices=False)
+        r = choose_rank(s, eps, chi_max)
+        if log is not None:
+            log.append((k, s.copy(), r))
+        cores[k] = Vt[:r].reshape(r, 2, rho)
+        X = U[:, :r] * s[:r]
+        rho = r
+    cores[0] = X.reshape(1, 2, rho)
+    return cores
+
+
+def round_mps(cores, eps, chi_max, log=None):
+    """Compression of Sec. 4.3: left-to-right QR sweep, then right-to-left SVD sweep.
+
+    The QR sweep makes cores 1..K-1 left-orthonormal (Householder QR of the
+    (2 r_{k-1}, r_k) unfolding, R pushed into the next core).  The SVD sweep then
+    factors each (r_{k-1}, 2 r_k) unfolding, keeps the right singular vectors
+    selected by ``choose_rank`` as core k and pushes U_r Sigma_r into core k-1.
+    """
+    G = [c.copy() for c in cores]
+    K = len(G)
+    for k in range(K - 1):
+        r0, d, r1 = G[k].shape
+        Q, R = np.linalg.qr(G[k].reshape(r0 * d, r1))
+        G[k] = Q.reshape(r0, d, Q.shape[1])
+        G[k + 1] = np.tensordot(R, G[k + 1], axes=(1, 0))
+    for k in range(K - 1, 0, -1):
+        r0, d, r1 = G[k].shape
+        U, s, Vt = np.linalg.svd(G[k].reshape(r0, d * r1), full_matrices=False)
+        r = choose_rank(s, eps, chi_max)
+        if log is not None:
+            log.append((k, s.copy(), r))
+        G[k] = Vt[:r].reshape(r, d, r1)
+        G[k - 1] = np.tensordot(G[k - 1], U[:, :r] * s[:r], axes=(2, 0))
+    return G
+
+
+# ---------------------------------------------------------------------------
+# MPS algebra
+# ---------------------------------------------------------------------------
+
+def zero_mps(K):
+    return [np.zeros((1, 2, 1)) for _ in range(K)]
+
+
+def product_state(bits):
+    """Basis state |b_1 ... b_K> as a bond-1 MPS."""
+    cores = []
+    for b in bits:
+        G = np.zeros((1, 2, 1))
+        G[0, b, 0] = 1.0
+        cores.append(G)
+    return cores
+
+
+def point_state(n, ix, iz):
+    """e_(ix, iz): sites are the bits of ix (MSB first) then of iz (eq. 3)."""
+    bits = [(ix >> (n - 1 - m)) & 1 for m in range(n)] + \
+           [(iz >> (n - 1 - m)) & 1 for m in range(n)]
+    return product_state(bits)
+
+
+def scale(cores, alpha):
+    out = [c.copy() for c in cores]
+    out[0] = out[0] * alpha
+    return out
+
+
+def direct_sum(terms, coeffs):
+    """sum_t coeffs[t] * terms[t] as one MPS (block-diagonal cores)."""
+    K = len(terms[0])
+    if K == 1:
+        return [sum(a * t[0] for a, t in zip(coeffs, terms))]
+    out = []
+    for k in range(K):
+        blocks = [t[k] for t in terms]
+        if k == 0:
+            G = np.concatenate([a * b for a, b in zip(coeffs, blocks)], axis=2)
+        elif k == K - 1:
+            G = np.concatenate(blocks, axis=0)
+        else:
+            r0 = sum(b.shape[0] for b in blocks)
+            r1 = sum(b.shape[2] for b in blocks)
+            G = np.zeros((r0, 2, r1))
+            i = j = 0
+            for b in blocks:
+                G[i:i + b.shape[0], :, j:j + b.shape[2]] = b
+                i += b.shape[0]
+                j += b.shape[2]
+        out.append(G)
+    return out
+
+
+def hadamard(A, B):
+    """Elementwise product: cores C_k[(a,i), s, (b,j)] = A_k[a,s,b] B_k[i,s,j].
+
+    Applying a diagonal MPO whose diagonal is the MPS A (Sec. 4.3, the c^2
+    operator of eq. 4) is exactly this product.
+    """
+    out = []
+    for a, b in zip(A, B):
+        ra0, d, ra1 = a.shape
+        rb0, _, rb1 = b.shape
+        G = np.einsum("asb,isj->aisbj", a, b).reshape(ra0 * rb0, d, ra1 * rb1)
+        out.append(G)
+    return out
+
+
+def apply_mpo(W, cores):
+    """(W psi)_k[(a,i), s', (b,j)] = sum_s W_k[a,b,s',s] G_k[i,s,j]."""
+    out = []
+    for w, g in zip(W, cores):
+        wl, wr, _, _ = w.shape
+        r0, _, r1 = g.shape
+        G = np.einsum("abts,isj->aitbj", w, g).reshape(wl * r0, 2, wr * r1)
+        out.append(G)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Shift MPOs (Sec. 4.2)
+# ---------------------------------------------------------------------------
+
+def shift_mpo_1d(n, direction=+1, boundary="periodic"):
+    """Cores of S^+ (direction +1) or S^- (-1) on an n-bit register, in site order.
+
+    The carry bit flows from the least significant bit to the most significant
+    one.  Bulk core of eq. 9 (row = incoming carry, column = outgoing carry):
+    [[I, 0], [sigma+, sigma-]]; eq. 13 swaps sigma+ and sigma- for S^-.  The LSB
+    core is the second row of the bulk (eq. 10: carry 1 injected).  The MSB core
+    is the first column of the bulk (eq. 11) for the "open" reading; for the
+    cyclic shift (x+1 mod 2^n) the carry out of the top bit is summed instead,
+    i.e. the MSB core is the sum of both columns.
+
+    Sites are ordered MSB first, so in site order the left bond of a core is its
+    outgoing carry and the right bond its incoming carry.
+    """
+    A, B = (SIGMA_PLUS, SIGMA_MINUS) if direction > 0 else (SIGMA_MINUS, SIGMA_PLUS)
+    bulk = np.zeros((2, 2, 2, 2))          # [carry_in, carry_out, s_out, s_in]
+    bulk[0, 0] = I2
+    bulk[1, 0] = A
+    bulk[1, 1] = B
+    lsb = bulk[1]                          # [carry_out, s_out, s_in]
+    if boundary == "periodic":
+        msb = bulk[:, 0] + bulk[:, 1]      # [carry_in, s_out, s_in]
+    else:
+        msb = bulk[:, 0]
+    if n == 1:
+        op = lsb[0] + lsb[1] if boundary == "periodic" else lsb[0]
+        return [op.reshape(1, 1, 2, 2)]
+    cores = [msb.reshape(1, 2, 2, 2)]                       # [out=1, in, s', s]
+    for _ in range(n - 2):
+        cores.append(np.transpose(bulk, (1, 0, 2, 3)).copy())  # [out, in, s', s]
+    cores.append(lsb.reshape(2, 1, 2, 2))                  # [out, in=1, s', s]
+    return cores
+
+
+def identity_mpo(n):
+    return [I2.reshape(1, 1, 2, 2).copy() for _ in range(n)]
+
+
+def shift_mpo_2d(n, axis, direction, boundary="periodic"):
+    """S_x^{+-} = S^{+-} (x) I (eq. 14) and S_z^{+-} = I (x) S^{+-} (eq. 15)."""
+    s = shift_mpo_1d(n, direction, boundary)
+    if axis == 0:
+        return s + identity_mpo(n)
+    return identity_mpo(n) + s
+
+
+def mpo_to_dense(W):
+    """Dense matrix [out, in] of an MPO (small K only)."""
+    M = np.ones((1, 1, 1))                  # [a, out, in]
+    for w in W:
+        wl, wr, _, _ = w.shape
+        M = np.einsum("aoi,abts->botis", M, w)
+        b, o, t, i, s = M.shape
+        M = M.reshape(b, o * t, i * s)
+    return M[0]
+
+
+def laplacian_mps(cores, n, boundary="periodic"):
+    """L psi with L = S_x+ + S_x- + S_z+ + S_z- - 4 I (eqs. 6 and 16) as one MPS.
+
+    Each shift MPO is applied separately and the five terms are added as a
+    direct sum (bond 2chi+2chi+chi+chi+chi inside a register).
+    """
+    terms = [apply_mpo(shift_mpo_2d(n, ax, d, boundary), cores)
+             for ax in (0, 1) for d in (+1, -1)]
+    terms.append(cores)
+    return direct_sum(terms, [1.0, 1.0, 1.0, 1.0, -4.0])

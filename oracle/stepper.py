@@ -1,0 +1,126 @@
+"""The MPS time step of eq. 17, plainly.  TEST INFRASTRUCTURE.
+
+psi^{k+1} = 2 psi^k - psi^{k-1} + lambda^2 C^2 (S_x+ + S_x- + S_z+ + S_z- - 4 I) psi^k
+
+with a compression after each operator application (Sec. 4.3).  Reading used
+throughout (three roundings per step, "S1"):
+
+    y        = round(L psi^k)
+    w        = round(C^2 . y)
+    psi^{k+1} = round(2 psi^k - psi^{k-1} + lambda^2 w + s_k e_src)
+
+Each round() is the QR sweep + truncated SVD sweep with the same (eps, chi_max).
+The c^2 diagonal MPO is the TT-SVD of the dense c^2 with the same per-bond rule
+and cutoff eps_c (no bond cap).  Two implementations are given:
+
+* MPSStepper   operates on cores (shift MPOs, direct sums, Hadamard products,
+               QR/SVD sweeps) exactly as the paper describes;
+* DenseStepper keeps dense fields and replaces every round(T) by the
+               right-to-left truncated TT-SVD of dense(T).  After the QR sweep
+               the left part of the chain is orthonormal, so each SVD of the
+               sweep sees the singular values of the current tensor's
+               unfolding: the two give the same tensor in exact arithmetic.
+"""
+import numpy as np
+
+from . import mps as M
+from . import fdtd as F
+
+
+def c2_mps(c2_dense, n, eps_c):
+    """The c^2 diagonal operator as an MPS (its diagonal), TT-SVD with cutoff eps_c."""
+    return M.tt_svd(np.asarray(c2_dense, dtype=np.float64).reshape(-1), 2 * n, eps_c,
+                    chi_max=1 << 30)
+
+
+class MPSStepper:
+    def __init__(self, n, lam, eps, chi_max, c2_cores, boundary="periodic",
+                 src=None, wavelet=None):
+        self.n, self.K = n, 2 * n
+        self.lam, self.eps, self.chi = lam, eps, chi_max
+        self.c2 = c2_cores
+        self.boundary = boundary
+        self.src = src
+        self.wavelet = wavelet
+        self.k = 0
+        self.psi = M.zero_mps(self.K)
+        self.psi_prev = M.zero_mps(self.K)
+        self.log = []            # (step, rounding, site, sigma, rank)
+
+    def set_fields(self, u_prev, u):
+        """Initial fields given densely; stored as their rounded MPS."""
+        self.psi_prev = M.tt_svd(np.asarray(u_prev).reshape(-1), self.K, self.eps, self.chi)
+        self.psi = M.tt_svd(np.asarray(u).reshape(-1), self.K, self.eps, self.chi)
+
+    def _round(self, cores, which):
+        log = []
+        out = M.round_mps(cores, self.eps, self.chi, log)
+        for site, s, r in log:
+            self.log.append((self.k, which, site, s, r))
+        return out
+
+    def step(self):
+        s_k = 0.0
+        if self.wavelet is not None and self.k < len(self.wavelet):
+            s_k = float(self.wavelet[self.k])
+        y = self._round(M.laplacian_mps(self.psi, self.n, self.boundary), 0)
+        w = self._round(M.hadamard(self.c2, y), 1)
+        terms = [self.psi, self.psi_prev, w]
+        coeffs = [2.0, -1.0, self.lam * self.lam]
+        if self.src is not None:
+            terms.append(M.point_state(self.n, self.src[0], self.src[1]))
+            coeffs.append(s_k)
+        nxt = self._round(M.direct_sum(terms, coeffs), 2)
+        self.psi_prev, self.psi = self.psi, nxt
+        self.k += 1
+
+    def dense(self, which=0):
+        N = 1 << self.n
+        return M.to_dense(self.psi if which == 0 else self.psi_prev).reshape(N, N)
+
+
+class DenseStepper:
+    """Same rounded trajectory as MPSStepper, through dense TT-SVDs."""
+
+    def __init__(self, n, lam, eps, chi_max, c2_dense, boundary="periodic",
+                 src=None, wavelet=None):
+        self.n, self.K = n, 2 * n
+        self.N = 1 << n
+        self.lam, self.eps, self.chi = lam, eps, chi_max
+        self.c2 = np.asarray(c2_dense, dtype=np.float64)
+        self.boundary = boundary
+        self.src = src
+        self.wavelet = wavelet
+        self.k = 0
+        self.u = np.zeros((self.N, self.N))
+        self.u_prev = np.zeros((self.N, self.N))
+        self.log = []
+        self.ranks = []          # per step: (bonds of y, bonds of w, bonds of psi)
+
+    def _round(self, t, which):
+        log = []
+        cores = M.tt_svd(t.reshape(-1), self.K, self.eps, self.chi, log)
+        for site, s, r in log:
+            self.log.append((self.k, which, site, s, r))
+        return M.to_dense(cores).reshape(self.N, self.N), M.bonds_of(cores)
+
+    def set_fields(self, u_prev, u):
+        self.u_prev, _ = self._round(np.asarray(u_prev, dtype=np.float64), -1)
+        self.u, _ = self._round(np.asarray(u, dtype=np.float64), -1)
+
+    def step(self):
+        s_k = 0.0
+        if self.wavelet is not None and self.k < len(self.wavelet):
+            s_k = float(self.wavelet[self.k])
+        y, by = self._round(F.laplacian(self.u, self.boundary), 0)
+        w, bw = self._round(self.c2 * y, 1)
+        t = 2.0 * self.u - self.u_prev + (self.lam * self.lam) * w
+        if self.src is not None:
+            t[self.src[0], self.src[1]] += s_k
+        nxt, bp = self._round(t, 2)
+        self.ranks.append((by, bw, bp))
+        self.u_prev, self.u = self.u, nxt
+        self.k += 1
+
+    def dense(self, which=0):
+        return self.u if which == 0 else self.u_prev

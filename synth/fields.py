@@ -1,0 +1,61 @@
+"""Initial fields and random tensor-train cores (input generators only).
+
+Fields are float64 arrays u[x, z] of shape (2^n, 2^n).  The flat index of grid
+point (x, z) is x*2^n + z, i.e. the quantics sites are the bits of x (most
+significant first) followed by the bits of z (Sec. 3, eq. 3).
+"""
+import numpy as np
+
+
+def plane_wave_omega_dt(n, mx, mz, courant):
+    """omega*dt of the discrete plane wave with integer wave numbers (mx, mz).
+
+    For the second-order leapfrog / 5-point scheme on a periodic 2^n grid with
+    constant c and Courant number c*dt/dh, a discrete plane wave
+    cos(kx*x*dh + kz*z*dh - k*omega*dt) is an exact solution iff
+    sin^2(omega dt / 2) = courant^2 (sin^2(kx dh/2) + sin^2(kz dh/2)),
+    kx*dh = 2 pi mx / 2^n (and likewise for z).
+    """
+    N = 1 << n
+    sx = np.sin(np.pi * mx / N) ** 2
+    sz = np.sin(np.pi * mz / N) ** 2
+    arg = courant * np.sqrt(sx + sz)
+    if arg > 1.0:
+        raise ValueError("plane wave is unstable at this Courant number")
+    return 2.0 * np.arcsin(arg)
+
+
+def plane_wave_fields(n, mx, mz, courant, phase=0.0):
+    """(u^{-1}, u^0) such that u^k = cos(theta - k omega dt) for all k >= -1."""
+    N = 1 << n
+    wdt = plane_wave_omega_dt(n, mx, mz, courant)
+    x = np.arange(N)[:, None]
+    z = np.arange(N)[None, :]
+    theta = 2.0 * np.pi * (mx * x + mz * z) / N + phase
+    return np.cos(theta + wdt), np.cos(theta)
+
+
+def random_fields(n, seed=0, smooth=True):
+    """Two seeded smooth random fields (u^{-1}, u^0)."""
+    rng = np.random.default_rng(seed)
+    N = 1 << n
+    out = []
+    for _ in range(2):
+        f = rng.standard_normal((N, N))
+        if smooth:
+            k = np.fft.fftfreq(N)
+            filt = np.exp(-(k[:, None] ** 2 + k[None, :] ** 2) * 200.0)
+            f = np.real(np.fft.ifft2(np.fft.fft2(f) * filt))
+        out.append(f)
+    return out[0], out[1]
+
+
+def random_mps_cores(K, bonds, seed=0):
+    """Seeded random cores, core k of shape (bonds[k], 2, bonds[k+1]).
+
+    bonds has K+1 entries with bonds[0] = bonds[K] = 1.
+    """
+    assert len(bonds) == K + 1 and bonds[0] == 1 and bonds[K] == 1
+    rng = np.random.default_rng(seed)
+    return [rng.standard_normal((bonds[k], 2, bonds[k + 1])) / np.sqrt(2 * bonds[k])
+            for k in range(K)]
