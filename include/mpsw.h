@@ -1,0 +1,149 @@
+/*
+ * mpsw.h -- C ABI of the MI355X quantics-MPS acoustic wave stepper.
+ *
+ * Method: Nemeth & Vattay, "Quantum Circuit and Tensor Network Implementation
+ * of the 2D Acoustic Wave Equation".  A field u[x, z] on a 2^n x 2^n grid
+ * (Sec. 2) is held as a matrix product state over K = 2n binary sites
+ * (Sec. 4.1, eq. 8); sites 1..n are the bits x_{n-1}..x_0 of the horizontal
+ * index (most significant first), sites n+1..2n the bits z_{n-1}..z_0 (eq. 3).
+ * One call of mpsw_step advances eq. 17,
+ *
+ *   psi^{k+1} = 2 psi^k - psi^{k-1} + lambda^2 C^2 (S_x+ + S_x- + S_z+ + S_z- - 4 I) psi^k,
+ *
+ * with the shift MPOs of Sec. 4.2 (eqs. 9-15), the diagonal c^2 MPO of
+ * Sec. 4.3, and a compression (left-to-right QR sweep, then right-to-left SVD
+ * sweep discarding sigma_i < eps * sigma_max and capping the bond at chi_max,
+ * Sec. 4.3) after each of the three operator applications:
+ *
+ *   y = round(L psi^k);  w = round(C^2 y);  psi^{k+1} = round(2 psi^k - psi^{k-1} + lambda^2 w + s_k e_src).
+ *
+ * Conventions (all entry points):
+ *   - return 0 (MPSW_OK) on success, a negative MPSW_E* code on failure; the
+ *     message of the last failure on the calling thread is mpsw_last_error();
+ *   - host arrays passed in are borrowed for the duration of the call only;
+ *   - dense fields are float64, 4^n entries, flat index x * 2^n + z;
+ *   - all device work of a state is ordered on the HIP stream given at
+ *     creation (NULL = the default stream); entry points that return data to
+ *     the host synchronise that stream;
+ *   - a state is not thread-safe; distinct states are independent.
+ * All computation runs in the library's HIP kernels on the current device.
+ */
+#ifndef MPSW_H
+#define MPSW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MPSW_OK = 0,
+  MPSW_EINVAL = -1,     /* bad argument */
+  MPSW_ENOMEM = -2,     /* device allocation failed or a size exceeds the workspace */
+  MPSW_EHIP = -3,       /* a HIP runtime call failed */
+  MPSW_ESTATE = -4,     /* call out of order (e.g. step before set_velocity) */
+  MPSW_ECFL = -5,       /* lambda^2 * max(c^2) * 2 > 1: the scheme is unstable */
+  MPSW_ENONFINITE = -6  /* a non-finite value was produced (detected at a sync) */
+};
+
+enum { MPSW_FP64 = 0, MPSW_FP32 = 1, MPSW_BF16 = 2 };          /* contraction precision */
+enum { MPSW_PERIODIC = 0, MPSW_OPEN = 1 };                     /* shift boundary */
+enum { MPSW_RANK_EXACT = 0, MPSW_RANK_LEARNED = 1 };           /* truncation rank mode */
+
+typedef struct mpsw_config {
+  int n;              /* grid 2^n x 2^n, 1 <= n <= 12; K = 2n sites */
+  int chi_max;        /* bond cap of every rounding, >= 1 */
+  double eps;         /* relative singular-value cutoff, >= 0 */
+  double lambda;      /* mesh ratio dt/dh of eq. 2, > 0 */
+  int precision;      /* MPSW_FP64 | MPSW_FP32 | MPSW_BF16 */
+  int boundary;       /* MPSW_PERIODIC (cyclic shifts) | MPSW_OPEN (eq. 11 as printed) */
+  int rank_mode;      /* MPSW_RANK_EXACT | MPSW_RANK_LEARNED */
+  uint64_t seed;      /* seed of the library's own random sketches */
+} mpsw_config;
+
+typedef struct mpsw_state_s* mpsw_state;
+
+typedef struct mpsw_stats {
+  int64_t step;            /* steps taken since creation */
+  int nsites;              /* K */
+  int bonds[64];           /* bonds of psi^k, K+1 entries */
+  int max_exact_bond[3];   /* largest bond before truncation in the last step, per rounding */
+  double tail2[3];         /* discarded sum of squared singular values in the last step,
+                              summed over bonds, per rounding */
+  int64_t fallbacks;       /* learned-rank mode: bonds that fell back to the exact SVD */
+} mpsw_stats;
+
+/* Create a state for one shot with psi^0 = psi^{-1} = 0 (bond 1).
+ * hip_stream: a hipStream_t or NULL.  Allocates the device workspace for the
+ * worst-case bonds of this (n, chi_max).  *out receives the handle (owned by the
+ * caller, released with mpsw_destroy).  Errors: EINVAL, ENOMEM, EHIP. */
+int mpsw_create_state(const mpsw_config* cfg, void* hip_stream, mpsw_state* out);
+
+/* Batch of nshots shots with the same n sharing one c^2 model; shot i uses
+ * cfgs[i] (chi_max and eps may differ per shot; n, lambda, precision, boundary
+ * must agree).  Steps of a batch advance all shots together.  Errors as above. */
+int mpsw_create_batch(const mpsw_config* cfgs, int nshots, void* hip_stream, mpsw_state* out);
+
+/* Set c^2 from its dense field (host, 4^n float64, all > 0).  The diagonal
+ * c^2 operator is built on the device as the right-to-left truncated TT-SVD of
+ * c^2 with relative cutoff eps_c and no bond cap (Sec. 4.3: the velocity
+ * field encoded as a diagonal MPO).  Errors: EINVAL (non-positive or
+ * non-finite c^2), ECFL, ENOMEM, EHIP. */
+int mpsw_set_velocity_dense(mpsw_state st, const double* c2, double eps_c);
+
+/* Set c^2 directly as the cores of its diagonal (host, float64):
+ * bonds[0..K] with bonds[0] = bonds[K] = 1, cores packed site after site,
+ * core k row-major of shape (bonds[k], 2, bonds[k+1]).  CFL is checked on the
+ * reconstructed field.  Errors: EINVAL, ECFL, ENOMEM, EHIP. */
+int mpsw_set_velocity_mpo(mpsw_state st, const int* bonds, const double* cores);
+
+/* Point source for shot `shot` at grid point (ix, iz): step j (counted from
+ * creation) adds wavelet[j] * e_(ix,iz) to psi^{j+1}; steps j >= nt add
+ * nothing.  The host array is copied.  Errors: EINVAL. */
+int mpsw_set_source(mpsw_state st, int shot, int ix, int iz, int nt, const double* wavelet);
+
+/* Initial fields of shot `shot` from dense host arrays (NULL = zero); each is
+ * stored as its right-to-left TT-SVD with the state's (eps, chi_max).
+ * Resets the step counter to 0.  Errors: EINVAL, ENOMEM, EHIP. */
+int mpsw_set_fields(mpsw_state st, int shot, const double* u_prev, const double* u_cur);
+
+/* Enqueue k >= 0 steps of eq. 17 on the state's stream (asynchronous).
+ * Errors: ESTATE (no velocity set), EINVAL, EHIP. */
+int mpsw_step(mpsw_state st, int k);
+
+/* Write the dense field of shot `shot` (which = 0: u^k, 1: u^{k-1}) into the
+ * caller's buffer of 4^n float64 (host memory, or device memory if
+ * out_is_device != 0).  Synchronises the stream; reports ENONFINITE if any
+ * entry is not finite.  Errors: EINVAL, EHIP, ENONFINITE. */
+int mpsw_to_dense(mpsw_state st, int shot, int which, double* out, int out_is_device);
+
+/* Bonds (K+1 ints) of shot `shot`'s psi^k (which = 0), psi^{k-1} (1) or of
+ * the c^2 operator (2).  Synchronises.  Errors: EINVAL, EHIP. */
+int mpsw_get_bonds(mpsw_state st, int shot, int which, int* bonds);
+
+/* Statistics of shot `shot` after the last step.  Synchronises. */
+int mpsw_get_stats(mpsw_state st, int shot, mpsw_stats* out);
+
+/* Number of shots and sites of the state. */
+int mpsw_get_shape(mpsw_state st, int* nshots, int* nsites);
+
+/* Free all device memory of the state.  NULL is accepted. */
+int mpsw_destroy(mpsw_state st);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* mpsw_last_error(void);
+
+/* Host-only helper (no device work), used by the CPU tests: the fused
+ * Laplacian MPO S_x+ + S_x- + S_z+ + S_z- - 4I (eqs. 6 and 16) the library
+ * applies, for an n-bit register pair and a boundary.  Writes K+1 bonds into
+ * `bonds` and, if `cores` is not NULL, the cores packed site after site, core k
+ * of shape [w_k][w_{k+1}][s_out][s_in] row-major (at most `cap` doubles).
+ * Returns the total number of core entries (>= 0) or a negative error code. */
+int mpsw_debug_laplacian_mpo(int n, int boundary, int* bonds, double* cores, int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPSW_H */

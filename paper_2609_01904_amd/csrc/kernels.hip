@@ -1,0 +1,754 @@
+// Device kernels of libmpsw (gfx950).
+//
+// Every kernel takes the group context (DevCtx, in device memory) and an OpArgs
+// value.  Shapes are read from the per-shot dimension blocks, so all launches
+// of a step are fixed and can be replayed without host involvement; blocks
+// whose tile or batch entry lies beyond the live shape return immediately.
+// Every write is checked against the capacity of its buffer; an overflow sets
+// an error bit instead of writing.
+#include "mpsw_kernels.h"
+
+#include <math.h>
+
+namespace mpsw {
+
+using DL = ShotDimsLayout;
+using RL = ShotRealLayout;
+
+__device__ __forceinline__ int* shot_dims(const DevCtx& c, int shot) { return c.dims + (int64_t)shot * DL::size; }
+__device__ __forceinline__ double* shot_reals(const DevCtx& c, int shot) { return c.reals + (int64_t)shot * RL::size; }
+__device__ __forceinline__ double* shot_eng(const DevCtx& c, int shot) { return c.eng + (int64_t)shot * c.L.stride; }
+__device__ __forceinline__ double* shot_mps(const DevCtx& c, int shot) { return c.mps + (int64_t)shot * c.mps_stride; }
+__device__ __forceinline__ void raise_err(const DevCtx& c, int bit) { atomicOr(c.err, bit); }
+
+// ---------------------------------------------------------------------------
+// Reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// block-wide sum for 256 threads; `red` has >= 4 doubles of LDS
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// GEMM planning: one descriptor per (shot, batch entry)
+// ---------------------------------------------------------------------------
+struct GemmDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  int M, N, K;
+  int64_t ars, acs, brs, bcs, crs;
+  int nbatch;
+  int copy;     // C <- B (M x N), A unused
+  int64_t capC; // capacity of the destination buffer from C onwards
+};
+
+__device__ __forceinline__ const double* mps_core(const DevCtx& c, int shot, int slot, int k) {
+  return shot_mps(c, shot) + c.off_mps[slot][k];
+}
+
+// Fills d for shot/batch z; returns false when there is nothing to do.
+__device__ bool plan_gemm(const DevCtx& c, const OpArgs& a, int shot, int z, int dz, GemmDesc& d) {
+  const int* dm = shot_dims(c, shot);
+  double* E = shot_eng(c, shot);
+  const EngineLayout& L = c.L;
+  const int k = a.site;
+  const int K = c.K;
+  d.copy = 0;
+  d.nbatch = 1;
+  switch (a.op) {
+    case G_L2R_EXPLICIT: {  // X_k = R (rt_k x rin_k) * IN_k (rin_k x 2 rin_{k+1})
+      const int rt = dm[DL::rt + k], r0 = dm[DL::rin + k], r1 = dm[DL::rin + k + 1];
+      d.M = rt; d.K = r0; d.N = 2 * r1;
+      d.A = E + L.off_R; d.ars = r0; d.acs = 1;
+      d.B = E + L.off_in[k]; d.brs = 2 * r1; d.bcs = 1;
+      if (a.aux == 1) { d.C = E + L.off_M; d.capC = L.cap_M; }  // last site feeds the SVD sweep
+      else { d.C = E + L.off_X; d.capC = L.cap_X; }
+      d.crs = d.N;
+      if ((int64_t)r0 * 2 * r1 > L.cap_in[k] || (int64_t)rt * r0 > L.cap_R) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+      break;
+    }
+    case G_COPY_RX: {  // identity source: X_k = R_{k-1} viewed as (2 rt_k x rin_{k+1})
+      const int rt = dm[DL::rt + k], r0 = dm[DL::rin + k];
+      d.copy = 1; d.M = rt; d.N = r0; d.K = 0;
+      d.B = E + L.off_R; d.brs = r0; d.bcs = 1;
+      if (a.aux == 1) { d.C = E + L.off_M; d.capC = L.cap_M; }
+      else { d.C = E + L.off_X; d.capC = L.cap_X; }
+      d.crs = r0;
+      if ((int64_t)rt * r0 > L.cap_R) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+      break;
+    }
+    case G_KRON_L1: {  // T1[p] (D_k x 2chi_{k+1}) = R[p]^T (D_k x chi_k) * Y_k (chi_k x 2chi_{k+1})
+      const int rt = dm[DL::rt + k];
+      const int ck = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k];
+      const int c1 = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k + 1];
+      const int Dk = c.c2b[k];
+      d.nbatch = rt;
+      if (z >= rt) return false;
+      d.M = Dk; d.K = ck; d.N = 2 * c1;
+      d.A = E + L.off_R + (int64_t)z * ck * Dk; d.ars = 1; d.acs = Dk;
+      d.B = mps_core(c, shot, MPSW_SLOT_Y, k); d.brs = 2 * c1; d.bcs = 1;
+      d.C = E + L.off_T1 + (int64_t)z * Dk * 2 * c1; d.crs = 2 * c1;
+      d.capC = L.cap_T1 - (int64_t)z * Dk * 2 * c1;
+      if ((int64_t)rt * ck * Dk > L.cap_R) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+      break;
+    }
+    case G_KRON_L2: {  // X[(p,s)] (chi' x D') = T1[p,:,s,:]^T (chi' x D_k) * C_k[:,s,:] (D_k x D')
+      const int rt = dm[DL::rt + k];
+      const int c1 = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k + 1];
+      const int Dk = c.c2b[k], D1 = c.c2b[k + 1];
+      d.nbatch = 2 * rt;
+      if (z >= 2 * rt) return false;
+      const int p = z >> 1, s = z & 1;
+      d.M = c1; d.K = Dk; d.N = D1;
+      d.A = E + L.off_T1 + (int64_t)p * Dk * 2 * c1 + (int64_t)s * c1; d.ars = 1; d.acs = 2 * c1;
+      d.B = c.c2 + c.off_c2[k] + (int64_t)s * D1; d.brs = 2 * D1; d.bcs = 1;
+      d.C = E + L.off_X + (int64_t)z * c1 * D1; d.crs = D1;
+      d.capC = L.cap_X - (int64_t)z * c1 * D1;
+      if ((int64_t)rt * Dk * 2 * c1 > L.cap_T1) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+      break;
+    }
+    case G_MEET: {  // X2 (2rt x 2^{K-n}) = X (2rt x chi_n D_n) * B_n (chi_n D_n x 2^{K-n})
+      const int rt = dm[DL::rt + k];
+      const int cn = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k + 1];
+      const int Dn = c.c2b[k + 1];
+      const int q = (int)mpsw_pow2(K - k - 1);
+      d.M = 2 * rt; d.K = cn * Dn; d.N = q;
+      d.A = E + L.off_X; d.ars = (int64_t)cn * Dn; d.acs = 1;
+      d.B = E + (a.aux ? L.off_B1 : L.off_B0); d.brs = q; d.bcs = 1;
+      d.C = E + L.off_X2; d.crs = q; d.capC = L.cap_X2;
+      if ((int64_t)2 * rt * cn * Dn > L.cap_X || (int64_t)cn * Dn * q > L.cap_B) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+      break;
+    }
+    case G_KRON_R1: {  // T1 (2chi_k x D_{k+1} Q) = Y_k (2chi_k x chi_{k+1}) * B_{k+1} (chi_{k+1} x D_{k+1} Q)
+      const int ck = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k];
+      const int c1 = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k + 1];
+      const int D1 = c.c2b[k + 1];
+      const int q = (int)mpsw_pow2(K - k - 1);
+      d.M = 2 * ck; d.K = c1; d.N = D1 * q;
+      d.A = mps_core(c, shot, MPSW_SLOT_Y, k); d.ars = c1; d.acs = 1;
+      d.B = E + (a.aux ? L.off_B1 : L.off_B0); d.brs = (int64_t)D1 * q; d.bcs = 1;
+      d.C = E + L.off_T1; d.crs = (int64_t)D1 * q; d.capC = L.cap_T1;
+      if ((int64_t)c1 * D1 * q > L.cap_B) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+      break;
+    }
+    case G_KRON_R2: {  // B_k[i,:,s,:] (D_k x Q) = C_k[:,s,:] (D_k x D_{k+1}) * T1[i,s] (D_{k+1} x Q)
+      const int ck = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k];
+      const int Dk = c.c2b[k], D1 = c.c2b[k + 1];
+      const int q = (int)mpsw_pow2(K - k - 1);
+      d.nbatch = 2 * ck;
+      if (z >= 2 * ck) return false;
+      const int i = z >> 1, s = z & 1;
+      d.M = Dk; d.K = D1; d.N = q;
+      d.A = c.c2 + c.off_c2[k] + (int64_t)s * D1; d.ars = 2 * D1; d.acs = 1;
+      d.B = E + L.off_T1 + (int64_t)z * D1 * q; d.brs = q; d.bcs = 1;
+      const int64_t off = (int64_t)i * Dk * 2 * q + (int64_t)s * q;
+      d.C = E + (a.aux ? L.off_B1 : L.off_B0) + off; d.crs = 2 * q;
+      d.capC = L.cap_B - off;
+      if ((int64_t)2 * ck * D1 * q > L.cap_T1) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+      break;
+    }
+    case G_ABSORB: {  // M_{k-1} (2rt_{k-1} x rho_k) = Q_{k-1} (2rt_{k-1} x rt_k) * US (rt_k x rho_k)
+      const int rtp = dm[DL::rt + k - 1], rtk = dm[DL::rt + k], rk = dm[DL::rho + k];
+      d.M = 2 * rtp; d.K = rtk; d.N = rk;
+      d.B = E + L.off_US; d.brs = rk; d.bcs = 1;
+      d.C = E + L.off_M; d.crs = rk; d.capC = L.cap_M;
+      if (dm[DL::qid + k - 1]) {
+        d.copy = 1;   // rt_k = 2 rt_{k-1}: same memory shape
+      } else {
+        d.A = E + L.off_q[k - 1]; d.ars = rtk; d.acs = 1;
+        if ((int64_t)2 * rtp * rtk > L.cap_q[k - 1]) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+      }
+      if ((int64_t)rtk * rk > L.cap_US) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+      break;
+    }
+    case G_DENSE: {  // V_{k+1} (2^k x 2 r_{k+1}) = V_k (2^k x r_k) * G_k (r_k x 2 r_{k+1})
+      int r0, r1;
+      const double* G;
+      if (a.slot < 0) { r0 = c.c2b[k]; r1 = c.c2b[k + 1]; G = c.c2 + c.off_c2[k]; }
+      else {
+        r0 = dm[DL::bonds + a.slot * (MPSW_MAXK + 1) + k];
+        r1 = dm[DL::bonds + a.slot * (MPSW_MAXK + 1) + k + 1];
+        G = mps_core(c, shot, a.slot, k);
+      }
+      const int64_t rows = mpsw_pow2(k);
+      double* D = c.dense + (int64_t)dz * c.dense_stride;
+      const int64_t half = c.dense_stride / 2;
+      d.M = (int)rows; d.K = r0; d.N = 2 * r1;
+      d.A = D + ((k & 1) ? half : 0); d.ars = r0; d.acs = 1;
+      d.B = G; d.brs = 2 * r1; d.bcs = 1;
+      d.C = D + ((k & 1) ? 0 : half); d.crs = 2 * r1; d.capC = half;
+      if (rows * r0 > half) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+      break;
+    }
+    default:
+      return false;
+  }
+  if (d.M <= 0 || d.N <= 0) return false;
+  if ((int64_t)(d.M - 1) * d.crs + d.N > d.capC) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+  return true;
+}
+
+// C = A * B (FP64), 64x64 output tiles, 256 threads, 4x4 outputs per thread.
+__global__ __launch_bounds__(256) void k_gemm(const DevCtx* __restrict__ cp, OpArgs a) {
+  const DevCtx& c = *cp;
+  const int shot = (a.shot >= 0) ? a.shot : (int)blockIdx.z, z = blockIdx.y;
+  GemmDesc d;
+  if (!plan_gemm(c, a, shot, z, blockIdx.z, d)) return;
+  if (z == 0 && blockIdx.x == 0 && threadIdx.x == 0 && d.nbatch > (int)gridDim.y) raise_err(c, MPSW_DEV_ERR_GRID);
+  const int tn = (d.N + 63) >> 6, tm = (d.M + 63) >> 6;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (int64_t)tm * tn > (int64_t)gridDim.x) raise_err(c, MPSW_DEV_ERR_GRID);
+  if ((int)blockIdx.x >= tm * tn) return;
+  const int m0 = (blockIdx.x / tn) * 64, n0 = (blockIdx.x % tn) * 64;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+
+  if (d.copy) {
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+      const int i = m0 + (e >> 6), j = n0 + (e & 63);
+      if (i < d.M && j < d.N) d.C[(int64_t)i * d.crs + j] = d.B[(int64_t)i * d.brs + (int64_t)j * d.bcs];
+    }
+    return;
+  }
+
+  __shared__ double As[16][64 + 1];
+  __shared__ double Bs[16][64 + 1];
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+
+  const bool a_k_fast = (d.acs == 1);
+  const bool b_n_fast = (d.bcs == 1);
+  for (int k0 = 0; k0 < d.K; k0 += 16) {
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      int mm, kk;
+      if (a_k_fast) { kk = e & 15; mm = e >> 4; } else { mm = e & 63; kk = e >> 6; }
+      const int gi = m0 + mm, gk = k0 + kk;
+      As[kk][mm] = (gi < d.M && gk < d.K) ? d.A[(int64_t)gi * d.ars + (int64_t)gk * d.acs] : 0.0;
+    }
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      int nn, kk;
+      if (b_n_fast) { nn = e & 63; kk = e >> 6; } else { kk = e & 15; nn = e >> 4; }
+      const int gj = n0 + nn, gk = k0 + kk;
+      Bs[kk][nn] = (gj < d.N && gk < d.K) ? d.B[(int64_t)gk * d.brs + (int64_t)gj * d.bcs] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int gi = m0 + ty + 16 * i;
+    if (gi >= d.M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gj = n0 + tx + 16 * j;
+      if (gj < d.N) d.C[(int64_t)gi * d.crs + gj] = acc[i][j];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Prepare a rounding: input bonds, sweep start values.
+// ---------------------------------------------------------------------------
+__global__ void k_prepare(const DevCtx* __restrict__ cp, OpArgs a) {
+  const DevCtx& c = *cp;
+  const int shot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (shot >= c.B) return;
+  int* dm = shot_dims(c, shot);
+  const int K = c.K, n = c.n;
+  const int* bonds = dm + DL::bonds;
+  auto B = [&](int slot, int k) { return bonds[slot * (MPSW_MAXK + 1) + k]; };
+  for (int k = 0; k <= K; ++k) {
+    int r;
+    switch (a.op) {
+      case P_LAPLACE: r = c.wb[k] * B(a.slot, k); break;
+      case P_C2: r = (k < n) ? c.c2b[k] * B(MPSW_SLOT_Y, k) : (int)mpsw_pow2(K - k); break;
+      case P_SUM:
+        r = (k == 0 || k == K) ? 1 : B(a.slot, k) + B(a.slot2, k) + B(MPSW_SLOT_W, k) + 1;
+        break;
+      default: r = (int)mpsw_pow2(K - k); break;  // dense input
+    }
+    dm[DL::rin + k] = r;
+  }
+  dm[DL::rt + 0] = 1;
+  dm[DL::rho + K] = 1;
+  if (a.aux >= 0 && a.aux < 3) {
+    shot_reals(c, shot)[RL::tail2 + a.aux] = 0.0;
+    dm[DL::maxbond + a.aux] = 0;
+  }
+}
+
+// Initial R: R_0 = [1], or the dense tensor (1 x 2^K) for a dense input.
+__global__ void k_init_R(const DevCtx* __restrict__ cp, OpArgs a) {
+  const DevCtx& c = *cp;
+  const int shot = blockIdx.y;
+  double* R = shot_eng(c, shot) + c.L.off_R;
+  if (a.op == P_C2 && blockIdx.x == 0 && threadIdx.x == 0) shot_eng(c, shot)[c.L.off_B0] = 1.0;  // B_K = [1]
+  if (a.op == P_DENSE) {
+    const int64_t total = mpsw_pow2(c.K);
+    if (total > c.L.cap_R || total > c.dense_stride) { if (threadIdx.x == 0 && blockIdx.x == 0) raise_err(c, MPSW_DEV_ERR_CAP); return; }
+    const double* src = c.dense + (int64_t)shot * c.dense_stride;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+      R[e] = src[e];
+  } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+    R[0] = 1.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Laplacian MPO applied to psi: IN_k[(al,i), s', (be,j)] = sum_s W_k[al,be,s',s] G_k[i,s,j]
+// ---------------------------------------------------------------------------
+__global__ void k_pack_lap(const DevCtx* __restrict__ cp, OpArgs a) {
+  const DevCtx& c = *cp;
+  const int k = blockIdx.y, shot = blockIdx.z;
+  const int* dm = shot_dims(c, shot);
+  const int c0 = dm[DL::bonds + a.slot * (MPSW_MAXK + 1) + k];
+  const int c1 = dm[DL::bonds + a.slot * (MPSW_MAXK + 1) + k + 1];
+  const int w0 = c.wb[k], w1 = c.wb[k + 1];
+  const int r0 = w0 * c0, r1 = w1 * c1;
+  const int64_t total = (int64_t)r0 * 2 * r1;
+  if (total > c.L.cap_in[k]) { if (blockIdx.x == 0 && threadIdx.x == 0) raise_err(c, MPSW_DEV_ERR_CAP); return; }
+  const double* G = mps_core(c, shot, a.slot, k);
+  const double* W = c.lapW + c.off_W[k];
+  double* out = shot_eng(c, shot) + c.L.off_in[k];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int col = (int)(e % r1);
+    const int sp = (int)((e / r1) & 1);
+    const int row = (int)(e / (2 * (int64_t)r1));
+    const int al = row / c0, i = row - al * c0;
+    const int be = col / c1, j = col - be * c1;
+    const double* w = W + ((al * w1 + be) * 2 + sp) * 2;
+    const double g0 = G[((int64_t)i * 2 + 0) * c1 + j];
+    const double g1 = G[((int64_t)i * 2 + 1) * c1 + j];
+    out[e] = w[0] * g0 + w[1] * g1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Direct sum 2 psi^k - psi^{k-1} + lambda^2 w + s_k e_src (block cores)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double sum_term(const DevCtx& c, int shot, int slot, int k, int i, int s, int j,
+                                           int r0, int r1) {
+  (void)r0;
+  return mps_core(c, shot, slot, k)[((int64_t)i * 2 + s) * r1 + j];
+}
+
+__global__ void k_pack_sum(const DevCtx* __restrict__ cp, OpArgs a) {
+  const DevCtx& c = *cp;
+  const int k = blockIdx.y, shot = blockIdx.z;
+  const int K = c.K, n = c.n;
+  const int* dm = shot_dims(c, shot);
+  const int slots[3] = {a.slot, a.slot2, MPSW_SLOT_W};
+  int b0[3], b1[3];
+  for (int t = 0; t < 3; ++t) {
+    b0[t] = dm[DL::bonds + slots[t] * (MPSW_MAXK + 1) + k];
+    b1[t] = dm[DL::bonds + slots[t] * (MPSW_MAXK + 1) + k + 1];
+  }
+  const int r0 = dm[DL::rin + k], r1 = dm[DL::rin + k + 1];
+  const int64_t total = (int64_t)r0 * 2 * r1;
+  if (total > c.L.cap_in[k]) { if (blockIdx.x == 0 && threadIdx.x == 0) raise_err(c, MPSW_DEV_ERR_CAP); return; }
+  // source coefficient and bit
+  double ssrc = 0.0;
+  const int nt = dm[DL::src_nt];
+  if (a.step >= 0 && a.step < nt && a.step < c.nt_max) ssrc = c.wavelet[(int64_t)shot * c.nt_max + a.step];
+  const int ix = dm[DL::src_ix], iz = dm[DL::src_iz];
+  const int bit = (k < n) ? ((ix >> (n - 1 - k)) & 1) : ((iz >> (K - 1 - k)) & 1);
+  const double coef[3] = {2.0, -1.0, c.lam2};
+  double* out = shot_eng(c, shot) + c.L.off_in[k];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int col = (int)(e % r1);
+    const int s = (int)((e / r1) & 1);
+    const int row = (int)(e / (2 * (int64_t)r1));
+    double v = 0.0;
+    if (k == 0) {            // concatenate along the right bond, coefficients here
+      int off = 0, t = 0;
+      for (; t < 3; ++t) { if (col < off + b1[t]) break; off += b1[t]; }
+      if (t < 3) v = coef[t] * sum_term(c, shot, slots[t], k, 0, s, col - off, b0[t], b1[t]);
+      else v = (s == bit) ? ssrc : 0.0;
+    } else if (k == K - 1) { // stack along the left bond
+      int off = 0, t = 0;
+      for (; t < 3; ++t) { if (row < off + b0[t]) break; off += b0[t]; }
+      if (t < 3) v = sum_term(c, shot, slots[t], k, row - off, s, 0, b0[t], b1[t]);
+      else v = (s == bit) ? 1.0 : 0.0;
+    } else {                 // block diagonal
+      int ro = 0, co = 0, t = 0;
+      for (; t < 3; ++t) {
+        if (row < ro + b0[t]) break;
+        ro += b0[t];
+        co += b1[t];
+      }
+      if (t < 3) {
+        if (col >= co && col < co + b1[t]) v = sum_term(c, shot, slots[t], k, row - ro, s, col - co, b0[t], b1[t]);
+      } else {
+        if (col == co) v = (s == bit) ? 1.0 : 0.0;
+      }
+    }
+    out[e] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Householder QR of the (2 rt_k x rin_{k+1}) unfolding, or the identity merge
+// when the unfolding is not tall (its thin QR has a square Q; the identity is
+// such a Q, so R = X and the bond becomes 2 rt_k).
+// One workgroup (256 threads) per shot.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_qr(const DevCtx* __restrict__ cp, OpArgs a) {
+  const DevCtx& c = *cp;
+  const int shot = blockIdx.z, k = a.site;
+  int* dm = shot_dims(c, shot);
+  const EngineLayout& L = c.L;
+  double* E = shot_eng(c, shot);
+  const int rt = dm[DL::rt + k];
+  const int nc = dm[DL::rin + k + 1];
+  const int mr = 2 * rt;
+  const double* X = E + (a.aux ? L.off_X2 : L.off_X);
+  const int64_t capX = a.aux ? L.cap_X2 : L.cap_X;
+  double* R = E + L.off_R;
+  __shared__ double red[8];
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  if ((int64_t)mr * nc > capX) { if (threadIdx.x == 0) raise_err(c, MPSW_DEV_ERR_CAP); return; }
+  if (mr <= nc) {
+    if ((int64_t)mr * nc > L.cap_R) { if (threadIdx.x == 0) raise_err(c, MPSW_DEV_ERR_CAP); return; }
+    for (int64_t e = threadIdx.x; e < (int64_t)mr * nc; e += blockDim.x) R[e] = X[e];
+    if (threadIdx.x == 0) { dm[DL::rt + k + 1] = mr; dm[DL::qid + k] = 1; }
+    return;
+  }
+  if ((int64_t)mr * nc > L.cap_q[k] || (int64_t)nc * nc > L.cap_R || (int64_t)mr * nc > L.cap_qrS || nc > L.cap_qrT) {
+    if (threadIdx.x == 0) raise_err(c, MPSW_DEV_ERR_CAP);
+    return;
+  }
+  double* S = E + L.off_qrS;   // column-major mr x nc
+  double* tau = E + L.off_qrT;
+  for (int64_t e = threadIdx.x; e < (int64_t)mr * nc; e += blockDim.x) {
+    const int i = (int)(e / nc), j = (int)(e % nc);
+    S[(int64_t)j * mr + i] = X[e];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int j = 0; j < nc; ++j) {
+    double* v = S + (int64_t)j * mr;
+    double s2 = 0.0;
+    for (int i = j + 1 + threadIdx.x; i < mr; i += blockDim.x) s2 += v[i] * v[i];
+    s2 = block_sum(s2, red);
+    const double x0 = v[j];
+    double t = 0.0, beta = x0, scale = 0.0;
+    if (s2 > 0.0) {
+      beta = -copysign(sqrt(x0 * x0 + s2), x0);
+      t = (beta - x0) / beta;
+      scale = 1.0 / (x0 - beta);
+    }
+    __syncthreads();
+    if (s2 > 0.0)
+      for (int i = j + 1 + threadIdx.x; i < mr; i += blockDim.x) v[i] *= scale;
+    if (threadIdx.x == 0) { v[j] = beta; tau[j] = t; }
+    __syncthreads();
+    if (t != 0.0) {
+      for (int col = j + 1 + w; col < nc; col += nw) {
+        double* u = S + (int64_t)col * mr;
+        double dot = 0.0;
+        for (int i = j + 1 + lane; i < mr; i += 64) dot += v[i] * u[i];
+        dot = wave_sum(dot) + u[j];
+        dot *= t;
+        if (lane == 0) u[j] -= dot;
+        for (int i = j + 1 + lane; i < mr; i += 64) u[i] -= dot * v[i];
+      }
+    }
+    __syncthreads();
+  }
+  // R (nc x nc, row-major, upper triangular)
+  for (int64_t e = threadIdx.x; e < (int64_t)nc * nc; e += blockDim.x) {
+    const int i = (int)(e / nc), j = (int)(e % nc);
+    R[e] = (i <= j) ? S[(int64_t)j * mr + i] : 0.0;
+  }
+  // Q = H_0 ... H_{nc-1} [I; 0], formed in place of the Q slot (row-major mr x nc)
+  double* Q = E + L.off_q[k];
+  for (int64_t e = threadIdx.x; e < (int64_t)mr * nc; e += blockDim.x) {
+    const int i = (int)(e / nc), j = (int)(e % nc);
+    Q[e] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = nc - 1; j >= 0; --j) {
+    const double t = tau[j];
+    if (t == 0.0) continue;
+    const double* v = S + (int64_t)j * mr;
+    for (int col = j + w; col < nc; col += nw) {
+      double dot = 0.0;
+      for (int i = j + 1 + lane; i < mr; i += 64) dot += v[i] * Q[(int64_t)i * nc + col];
+      dot = wave_sum(dot) + Q[(int64_t)j * nc + col];
+      dot *= t;
+      if (lane == 0) Q[(int64_t)j * nc + col] -= dot;
+      for (int i = j + 1 + lane; i < mr; i += 64) Q[(int64_t)i * nc + col] -= dot * v[i];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { dm[DL::rt + k + 1] = nc; dm[DL::qid + k] = 0; }
+  (void)bad;
+}
+
+// ---------------------------------------------------------------------------
+// Truncated SVD of the bond matrix M_k (rt_k x 2 rho_{k+1}) by one-sided
+// (Hestenes) Jacobi on the thinner orientation, one workgroup per shot.
+// Writes core k = V_r^T, U_r Sigma_r, rho_k; logs the leading singular values
+// and accumulates the discarded tail sum in FP64.
+// ---------------------------------------------------------------------------
+#define SVD_MAXC 4096
+
+__global__ __launch_bounds__(256) void k_svd(const DevCtx* __restrict__ cp, OpArgs a) {
+  const DevCtx& c = *cp;
+  const int shot = blockIdx.z, k = a.site;
+  int* dm = shot_dims(c, shot);
+  double* re = shot_reals(c, shot);
+  const EngineLayout& L = c.L;
+  double* E = shot_eng(c, shot);
+  const int m = dm[DL::rt + k];
+  const int n = 2 * dm[DL::rho + k + 1];
+  const bool tall = m >= n;
+  const int Ld = tall ? m : n;     // column length
+  const int cc = tall ? n : m;     // column count
+  __shared__ double sig[SVD_MAXC];
+  __shared__ int order[SVD_MAXC];
+  __shared__ int rotated;
+  __shared__ int rank_s;
+  if ((int64_t)m * n > L.cap_M || (int64_t)Ld * cc > L.cap_sA || (int64_t)cc * cc > L.cap_sJ || cc > SVD_MAXC) {
+    if (threadIdx.x == 0) raise_err(c, MPSW_DEV_ERR_CAP);
+    return;
+  }
+  const double* M = E + L.off_M;
+  double* A = E + L.off_sA;   // column-major Ld x cc
+  double* J = E + L.off_sJ;   // column-major cc x cc
+  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    if (tall) A[(int64_t)j * Ld + i] = M[e];
+    else A[(int64_t)i * Ld + j] = M[e];
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)cc * cc; e += blockDim.x) J[e] = ((e / cc) == (e % cc)) ? 1.0 : 0.0;
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int np = cc + (cc & 1);   // players in the round-robin (with a dummy if odd)
+  const double tol = 1e-15 * sqrt((double)Ld);
+  for (int sweep = 0; sweep < 60 && cc > 1; ++sweep) {
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    for (int t = 0; t < np - 1; ++t) {
+      for (int pi = w; pi < np / 2; pi += nw) {
+        int p, q;
+        if (pi == 0) { p = t; q = np - 1; }
+        else { p = (t + pi) % (np - 1); q = (t - pi + (np - 1)) % (np - 1); }
+        if (p >= cc || q >= cc) continue;
+        double* ap = A + (int64_t)p * Ld;
+        double* aq = A + (int64_t)q * Ld;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = lane; i < Ld; i += 64) {
+          const double x = ap[i], y = aq[i];
+          al = fma(x, x, al);
+          be = fma(y, y, be);
+          ga = fma(x, y, ga);
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        if (al == 0.0 || be == 0.0 || fabs(ga) <= tol * sqrt(al) * sqrt(be)) continue;
+        const double zeta = (be - al) / (2.0 * ga);
+        double tt;
+        if (fabs(zeta) > 1e100) tt = 0.5 / zeta;
+        else tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        for (int i = lane; i < Ld; i += 64) {
+          const double x = ap[i], y = aq[i];
+          ap[i] = cs * x - sn * y;
+          aq[i] = sn * x + cs * y;
+        }
+        double* jp = J + (int64_t)p * cc;
+        double* jq = J + (int64_t)q * cc;
+        for (int i = lane; i < cc; i += 64) {
+          const double x = jp[i], y = jq[i];
+          jp[i] = cs * x - sn * y;
+          jq[i] = sn * x + cs * y;
+        }
+        if (lane == 0) rotated = 1;
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  // singular values and their descending order (ties by index)
+  for (int j = w; j < cc; j += nw) {
+    const double* aj = A + (int64_t)j * Ld;
+    double s = 0.0;
+    for (int i = lane; i < Ld; i += 64) s = fma(aj[i], aj[i], s);
+    s = wave_sum(s);
+    if (lane == 0) sig[j] = sqrt(s);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < cc; j += blockDim.x) {
+    const double sj = sig[j];
+    int r = 0;
+    for (int i = 0; i < cc; ++i) {
+      const double si = sig[i];
+      r += (si > sj) || (si == sj && i < j);
+    }
+    order[r] = j;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double s0 = sig[order[0]];
+    const double eps = re[RL::eps];
+    const int chi = dm[DL::chi];
+    int r = 0;
+    bool finite = true;
+    for (int t = 0; t < cc; ++t) {
+      const double s = sig[order[t]];
+      if (!(s == s) || isinf(s)) finite = false;
+      if (s0 > 0.0 && s >= eps * s0) ++r;
+    }
+    if (!finite) raise_err(c, MPSW_DEV_ERR_NONFINITE);
+    if (r > chi) r = chi;
+    if (r < 1) r = 1;
+    double tail = 0.0;
+    for (int t = r; t < cc; ++t) { const double s = sig[order[t]]; tail = fma(s, s, tail); }
+    if (a.aux >= 0 && a.aux < 3) {
+      re[RL::tail2 + a.aux] += tail;
+      double* lg = re + RL::sigma_log + (a.aux * MPSW_MAXK + k) * 32;
+      for (int t = 0; t < 32; ++t) lg[t] = (t < cc) ? sig[order[t]] : 0.0;
+      const int mb = cc;
+      if (mb > dm[DL::maxbond + a.aux]) dm[DL::maxbond + a.aux] = mb;
+    }
+    rank_s = r;
+  }
+  __syncthreads();
+  const int r = rank_s;
+  double* out = shot_mps(c, shot) + c.off_mps[a.slot][k];
+  double* US = E + L.off_US;
+  if ((int64_t)r * n > c.cap_mps[a.slot][k] || (int64_t)m * r > L.cap_US) {
+    if (threadIdx.x == 0) raise_err(c, MPSW_DEV_ERR_CAP);
+    return;
+  }
+  // core k = V_r^T (r x n)
+  for (int64_t e = threadIdx.x; e < (int64_t)r * n; e += blockDim.x) {
+    const int t = (int)(e / n), l = (int)(e % n);
+    const int j = order[t];
+    double v;
+    if (tall) v = J[(int64_t)j * cc + l];
+    else {
+      const double s = sig[j];
+      v = (s > 0.0) ? A[(int64_t)j * Ld + l] / s : ((l == t) ? 1.0 : 0.0);
+    }
+    out[e] = v;
+  }
+  // U_r Sigma_r (m x r)
+  for (int64_t e = threadIdx.x; e < (int64_t)m * r; e += blockDim.x) {
+    const int l = (int)(e / r), t = (int)(e % r);
+    const int j = order[t];
+    US[e] = tall ? A[(int64_t)j * Ld + l] : J[(int64_t)j * cc + l] * sig[j];
+  }
+  if (threadIdx.x == 0) dm[DL::rho + k] = r;
+}
+
+// Core 0 of the rounded state and its bonds.
+__global__ void k_finish(const DevCtx* __restrict__ cp, OpArgs a) {
+  const DevCtx& c = *cp;
+  const int shot = blockIdx.z;
+  int* dm = shot_dims(c, shot);
+  const int r1 = dm[DL::rho + 1];
+  const double* M = shot_eng(c, shot) + c.L.off_M;
+  double* out = shot_mps(c, shot) + c.off_mps[a.slot][0];
+  if ((int64_t)2 * r1 > c.cap_mps[a.slot][0]) { if (threadIdx.x == 0) raise_err(c, MPSW_DEV_ERR_CAP); return; }
+  for (int e = threadIdx.x; e < 2 * r1; e += blockDim.x) out[e] = M[e];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int* b = dm + DL::bonds + a.slot * (MPSW_MAXK + 1);
+    b[0] = 1;
+    for (int k = 1; k < c.K; ++k) b[k] = dm[DL::rho + k];
+    b[c.K] = 1;
+  }
+}
+
+// V_0 = [1] for to_dense.
+__global__ void k_dense_init(const DevCtx* __restrict__ cp) {
+  const DevCtx& c = *cp;
+  const int shot = blockIdx.x;
+  if (threadIdx.x == 0) c.dense[(int64_t)shot * c.dense_stride] = 1.0;
+}
+
+// Zero state (bond 1, zero cores) in a slot.
+__global__ void k_zero_state(const DevCtx* __restrict__ cp, OpArgs a) {
+  const DevCtx& c = *cp;
+  const int shot = blockIdx.x;
+  if (a.shot >= 0 && shot != a.shot) return;
+  int* b = shot_dims(c, shot) + DL::bonds + a.slot * (MPSW_MAXK + 1);
+  for (int k = threadIdx.x; k < c.K; k += blockDim.x) {
+    double* core = shot_mps(c, shot) + c.off_mps[a.slot][k];
+    core[0] = 0.0;
+    core[1] = 0.0;
+  }
+  for (int k = threadIdx.x; k <= c.K; k += blockDim.x) b[k] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers
+// ---------------------------------------------------------------------------
+void launch_gemm(const DevCtx* d, const OpArgs& a, int grid_tiles, int grid_batch, int nshots, hipStream_t s) {
+  if (grid_tiles <= 0 || grid_batch <= 0) return;
+  hipLaunchKernelGGL(k_gemm, dim3(grid_tiles, grid_batch, nshots), dim3(256), 0, s, d, a);
+}
+void launch_prepare(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s) {
+  hipLaunchKernelGGL(k_prepare, dim3((nshots + 63) / 64), dim3(64), 0, s, d, a);
+}
+void launch_init_R(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_R, dim3(a.op == P_DENSE ? 256 : 1, nshots), dim3(256), 0, s, d, a);
+}
+void launch_pack_lap(const DevCtx* d, const OpArgs& a, int K, int nshots, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_lap, dim3(blocks, K, nshots), dim3(256), 0, s, d, a);
+}
+void launch_pack_sum(const DevCtx* d, const OpArgs& a, int K, int nshots, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_sum, dim3(blocks, K, nshots), dim3(256), 0, s, d, a);
+}
+void launch_qr(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s) {
+  hipLaunchKernelGGL(k_qr, dim3(1, 1, nshots), dim3(256), 0, s, d, a);
+}
+void launch_svd(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s) {
+  hipLaunchKernelGGL(k_svd, dim3(1, 1, nshots), dim3(256), 0, s, d, a);
+}
+void launch_finish(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(1, 1, nshots), dim3(256), 0, s, d, a);
+}
+void launch_dense_init(const DevCtx* d, int nshots, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_init, dim3(nshots), dim3(64), 0, s, d);
+}
+void launch_zero_state(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_state, dim3(nshots), dim3(64), 0, s, d, a);
+}
+
+}  // namespace mpsw

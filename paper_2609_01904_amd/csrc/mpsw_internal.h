@@ -1,0 +1,95 @@
+// Internal structures shared by the kernels and the runtime of libmpsw.
+//
+// Memory model: a state ("group") holds B shots with the same number of sites
+// K = 2n.  Every shot owns an arena of doubles with identical layout (all
+// offsets below are relative to the shot's arena base, in doubles), and a
+// block of ints holding its data-dependent dimensions (bonds, sweep ranks).
+// Kernels read dimensions from device memory, so the launch sequence of a step
+// is fixed and never waits for the host; each kernel is launched with a grid
+// sized for the workspace capacities and blocks beyond the live sizes exit.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MPSW_MAXK 24          // n <= 12
+#define MPSW_NSLOT 5          // MPS buffers: 0..2 psi rotation, 3 = y, 4 = w
+#define MPSW_SLOT_Y 3
+#define MPSW_SLOT_W 4
+
+// error bits raised on the device, reported by the host at the next sync
+#define MPSW_DEV_ERR_CAP 1        // a live size exceeded a workspace capacity
+#define MPSW_DEV_ERR_NONFINITE 2  // a singular value was not finite
+#define MPSW_DEV_ERR_GRID 4       // a launch grid was smaller than the live work
+
+// Per-shot integer block layout (offsets in ints).
+struct ShotDimsLayout {
+  static constexpr int bonds = 0;                                  // [NSLOT][MAXK+1]
+  static constexpr int rin = bonds + MPSW_NSLOT * (MPSW_MAXK + 1); // input bonds of the rounding
+  static constexpr int rt = rin + (MPSW_MAXK + 1);                 // left bonds after the QR sweep
+  static constexpr int rho = rt + (MPSW_MAXK + 1);                 // bonds after the SVD sweep
+  static constexpr int qid = rho + (MPSW_MAXK + 1);                // 1 if Q_k is the identity
+  static constexpr int chi = qid + (MPSW_MAXK + 1);
+  static constexpr int src_ix = chi + 1;
+  static constexpr int src_iz = src_ix + 1;
+  static constexpr int src_nt = src_iz + 1;
+  static constexpr int maxbond = src_nt + 1;                       // [3] per rounding of the last step
+  static constexpr int size = maxbond + 4;
+};
+
+// Per-shot double block layout (offsets in doubles, separate small array).
+struct ShotRealLayout {
+  static constexpr int eps = 0;
+  static constexpr int tail2 = 1;     // [3]
+  static constexpr int sigma_log = 4; // [3][MAXK][32]: leading singular values of the last step
+  static constexpr int size = sigma_log + 3 * MPSW_MAXK * 32;
+};
+
+// Capacities (doubles) and offsets of one engine's buffers inside a shot arena.
+struct EngineLayout {
+  int64_t off_in[MPSW_MAXK], cap_in[MPSW_MAXK];   // explicit source cores
+  int64_t off_q[MPSW_MAXK], cap_q[MPSW_MAXK];     // Q cores of the QR sweep
+  int64_t off_X, cap_X;     // X_k = R_{k-1} S_k
+  int64_t off_X2, cap_X2;   // X after the meeting product (c^2 rounding)
+  int64_t off_R, cap_R;     // R factor carried to the right
+  int64_t off_T1, cap_T1;   // Kronecker contraction temporary
+  int64_t off_B0, off_B1, cap_B;  // right-merged blocks (ping-pong)
+  int64_t off_M, cap_M;     // bond matrix of the SVD sweep
+  int64_t off_US, cap_US;   // U_r Sigma_r
+  int64_t off_sA, cap_sA;   // Jacobi working matrix
+  int64_t off_sJ, cap_sJ;   // Jacobi accumulated rotations
+  int64_t off_qrS, cap_qrS; // Householder working matrix
+  int64_t off_qrT, cap_qrT; // Householder tau
+  int64_t stride;           // doubles per shot for this engine
+  int maxdim;               // largest matrix side any factorization sees
+};
+
+struct DevCtx {
+  int K, n, B;
+  int boundary;
+  double lam2;
+  int64_t mps_stride;                            // doubles per shot of the MPS arena
+  double* mps;                                   // MPS arena base
+  int64_t off_mps[MPSW_NSLOT][MPSW_MAXK];
+  int64_t cap_mps[MPSW_NSLOT][MPSW_MAXK];
+  int* dims;                                     // B * ShotDimsLayout::size
+  double* reals;                                 // B * ShotRealLayout::size
+  double* eng;                                   // engine arena base
+  EngineLayout L;
+  // c^2 diagonal (shared by all shots)
+  const double* c2;
+  int64_t off_c2[MPSW_MAXK];
+  int c2b[MPSW_MAXK + 1];
+  // fused Laplacian MPO cores [wl][wr][2][2] (shared)
+  const double* lapW;
+  int off_W[MPSW_MAXK];
+  int wb[MPSW_MAXK + 1];
+  // per-shot wavelets (B * nt_max)
+  const double* wavelet;
+  int nt_max;
+  // dense buffers for to_dense / from_dense (per shot, ping-pong)
+  double* dense;
+  int64_t dense_stride;
+  int* err;
+};
+
+__host__ __device__ inline int64_t mpsw_pow2(int e) { return (int64_t)1 << e; }

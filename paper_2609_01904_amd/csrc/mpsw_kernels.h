@@ -1,0 +1,45 @@
+// Kernel entry points and operation codes of libmpsw.
+#pragma once
+#include "mpsw_internal.h"
+
+namespace mpsw {
+
+// GEMM-shaped operations (planned on the device from the live bonds).
+enum GemmOp {
+  G_L2R_EXPLICIT = 1,  // X_k = R_{k-1} S_k with explicit source cores
+  G_COPY_RX,           // identity source: X_k = R_{k-1}
+  G_KRON_L1,           // Kronecker (Hadamard) contraction, left-to-right, first GEMM
+  G_KRON_L2,           // ... second GEMM
+  G_MEET,              // product with the right-merged block at the middle site
+  G_KRON_R1,           // Kronecker contraction, right-to-left, first GEMM
+  G_KRON_R2,           // ... second GEMM
+  G_ABSORB,            // M_{k-1} = Q_{k-1} U_r Sigma_r
+  G_DENSE              // dense contraction step V_{k+1} = V_k G_k
+};
+
+// Rounding input kinds (k_prepare / k_init_R).
+enum PrepOp { P_LAPLACE = 1, P_C2, P_SUM, P_DENSE };
+
+struct OpArgs {
+  int op;
+  int site;
+  int slot;    // MPS slot read (pack) or written (svd, finish); -1 = c^2 operator (dense)
+  int slot2;   // second MPS slot (direct sum: psi^{k-1})
+  int aux;     // op-specific flag (buffer select, rounding index)
+  int step;    // step index (source sample)
+  int shot;    // restrict to one shot (-1 = all)
+  int pad;
+};
+
+void launch_gemm(const DevCtx* d, const OpArgs& a, int grid_tiles, int grid_batch, int nshots, hipStream_t s);
+void launch_prepare(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
+void launch_init_R(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
+void launch_pack_lap(const DevCtx* d, const OpArgs& a, int K, int nshots, int blocks, hipStream_t s);
+void launch_pack_sum(const DevCtx* d, const OpArgs& a, int K, int nshots, int blocks, hipStream_t s);
+void launch_qr(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
+void launch_svd(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
+void launch_finish(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
+void launch_dense_init(const DevCtx* d, int nshots, hipStream_t s);
+void launch_zero_state(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
+
+}  // namespace mpsw

@@ -1,0 +1,965 @@
+// Host runtime and C ABI of libmpsw.
+//
+// A state ("group") owns B shots of the same grid size.  Its step is a fixed
+// sequence of kernel launches on the caller's stream (see run_step): three
+// roundings, each an optional pack kernel, a left-to-right sweep of
+// (contraction, QR-or-merge) pairs and a right-to-left sweep of (SVD, absorb)
+// pairs.  Workspace capacities are computed from the worst-case bonds of the
+// configuration; the kernels read the live bonds from device memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mpsw.h"
+#include "mpsw_kernels.h"
+
+using namespace mpsw;
+using DL = ShotDimsLayout;
+using RL = ShotRealLayout;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(MPSW_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+inline int64_t p2(int e) { return (int64_t)1 << e; }
+inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// The fused Laplacian MPO S_x+ + S_x- + S_z+ + S_z- - 4I (eqs. 6, 16) in site
+// order (x bits MSB first, then z bits).  It is a finite automaton read from
+// the last site to the first; the bond carries what the sites to the right
+// did: P (no shift yet: the x register will shift), C (carry of an S+ still
+// pending), B (borrow of an S- still pending), D (shift finished, or the -4I
+// term).  A pending carry at a register's top bit wraps (periodic) or is
+// dropped (open, the terminal core of eq. 11 as printed).  Unused states of a
+// bond are pruned, giving bonds 3 inside the x register, 2 at the x|z cut and
+// 4 inside the z register.
+// ---------------------------------------------------------------------------
+struct LapMPO {
+  std::vector<int> bonds;                  // K+1
+  std::vector<std::vector<double>> cores;  // [wl][wr][2][2]
+};
+
+LapMPO build_laplacian_mpo(int n, int boundary) {
+  const int K = 2 * n;
+  enum { P = 0, C = 1, Bs = 2, D = 3 };
+  const double I2[2][2] = {{1, 0}, {0, 1}};
+  const double SP[2][2] = {{0, 0}, {1, 0}};  // |1><0|
+  const double SM[2][2] = {{0, 1}, {0, 0}};  // |0><1|
+  const bool periodic = boundary == MPSW_PERIODIC;
+  // T[k][out][in][s'][s]
+  std::vector<std::vector<double>> T(K, std::vector<double>(4 * 4 * 4, 0.0));
+  auto add = [&](int k, int out, int in, const double (*op)[2], double w) {
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) T[k][((out * 4 + in) * 2 + a) * 2 + b] += w * op[a][b];
+  };
+  for (int k = 0; k < K; ++k) {
+    const bool zreg = k >= n;
+    add(k, D, D, I2, 1.0);
+    add(k, C, C, SM, 1.0);  // bit 1 -> 0, carry moves on
+    add(k, D, C, SP, 1.0);  // bit 0 -> 1, carry absorbed
+    add(k, Bs, Bs, SP, 1.0);  // bit 0 -> 1, borrow moves on
+    add(k, D, Bs, SM, 1.0);   // bit 1 -> 0, borrow absorbed
+    if (zreg) {
+      add(k, P, P, I2, 1.0);
+    } else {
+      // the x register starts its shift where P arrives (its least significant bit)
+      add(k, D, P, SP, 1.0);
+      add(k, D, P, SM, 1.0);
+      add(k, C, P, SM, 1.0);
+      add(k, Bs, P, SP, 1.0);
+    }
+    if (k == n) {  // most significant z bit: a pending carry/borrow wraps or is dropped
+      for (int in = 0; in < 4; ++in)
+        for (int e = 0; e < 4; ++e) {
+          double& c = T[k][((C * 4 + in) * 2) * 2 + e];
+          double& b = T[k][((Bs * 4 + in) * 2) * 2 + e];
+          if (periodic) {
+            T[k][((D * 4 + in) * 2) * 2 + e] += c + b;
+          }
+          c = 0.0;
+          b = 0.0;
+        }
+    }
+  }
+  const double left[4] = {0.0, periodic ? 1.0 : 0.0, periodic ? 1.0 : 0.0, 1.0};
+  const double right[4] = {1.0, 1.0, 1.0, -4.0};
+  // dense cores with bonds 1, 4, ..., 4, 1
+  std::vector<int> wl(K), wr(K);
+  std::vector<std::vector<double>> W(K);
+  for (int k = 0; k < K; ++k) {
+    wl[k] = (k == 0) ? 1 : 4;
+    wr[k] = (k == K - 1) ? 1 : 4;
+    W[k].assign((size_t)wl[k] * wr[k] * 4, 0.0);
+    for (int o = 0; o < wl[k]; ++o)
+      for (int i = 0; i < wr[k]; ++i)
+        for (int e = 0; e < 4; ++e) {
+          double v = 0.0;
+          for (int oo = 0; oo < 4; ++oo) {
+            if (k != 0 && oo != o) continue;
+            const double lw = (k == 0) ? left[oo] : 1.0;
+            for (int ii = 0; ii < 4; ++ii) {
+              if (k != K - 1 && ii != i) continue;
+              const double rw = (k == K - 1) ? right[ii] : 1.0;
+              v += lw * rw * T[k][(oo * 4 + ii) * 4 + e];
+            }
+          }
+          W[k][((size_t)o * wr[k] + i) * 4 + e] = v;
+        }
+  }
+  // prune states of each internal bond that carry nothing on either side
+  std::vector<std::vector<int>> keep(K + 1);
+  keep[0] = {0};
+  keep[K] = {0};
+  for (int b = 1; b < K; ++b) {
+    for (int s = 0; s < 4; ++s) {
+      bool lnz = false, rnz = false;
+      for (int o = 0; o < wl[b - 1] && !lnz; ++o)
+        for (int e = 0; e < 4; ++e)
+          if (W[b - 1][((size_t)o * wr[b - 1] + s) * 4 + e] != 0.0) { lnz = true; break; }
+      for (int i = 0; i < wr[b] && !rnz; ++i)
+        for (int e = 0; e < 4; ++e)
+          if (W[b][((size_t)s * wr[b] + i) * 4 + e] != 0.0) { rnz = true; break; }
+      if (lnz && rnz) keep[b].push_back(s);
+    }
+  }
+  LapMPO out;
+  out.bonds.resize(K + 1);
+  for (int b = 0; b <= K; ++b) out.bonds[b] = (int)keep[b].size();
+  out.cores.resize(K);
+  for (int k = 0; k < K; ++k) {
+    const auto& kl = keep[k];
+    const auto& kr = keep[k + 1];
+    out.cores[k].assign(kl.size() * kr.size() * 4, 0.0);
+    for (size_t o = 0; o < kl.size(); ++o)
+      for (size_t i = 0; i < kr.size(); ++i)
+        for (int e = 0; e < 4; ++e)
+          out.cores[k][(o * kr.size() + i) * 4 + e] = W[k][((size_t)kl[o] * wr[k] + kr[i]) * 4 + e];
+  }
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// Capacity planning
+// ---------------------------------------------------------------------------
+struct SweepCaps {
+  std::vector<int64_t> rin, rt, rho;
+  bool explicit_in = false;   // source cores are materialised in the IN buffers
+};
+
+SweepCaps sweep_caps(const std::vector<int64_t>& rin, int K, int64_t chi) {
+  SweepCaps s;
+  s.rin = rin;
+  s.rt.assign(K + 1, 1);
+  for (int k = 0; k + 1 <= K - 1; ++k) s.rt[k + 1] = std::min(2 * s.rt[k], rin[k + 1]);
+  s.rho.assign(K + 1, 1);
+  for (int k = K - 1; k >= 1; --k) s.rho[k] = std::min({chi, s.rt[k], 2 * s.rho[k + 1]});
+  return s;
+}
+
+struct Plan {
+  int K, n;
+  std::vector<SweepCaps> sw;   // roundings handled by this engine
+  std::vector<int64_t> Rmax;   // state bond caps (y feeding the Kronecker rounding)
+  std::vector<int> D;          // c^2 bonds (empty when no Kronecker rounding)
+  bool kron = false;
+};
+
+void add64(int64_t& off, int64_t& field_off, int64_t cap) {
+  field_off = off;
+  off += (cap + 31) & ~(int64_t)31;   // 256-byte aligned sub-buffers
+}
+
+// Fills the engine layout for the roundings in p and returns the per-shot stride.
+void layout_engine(const Plan& p, EngineLayout& L) {
+  const int K = p.K, n = p.n;
+  std::memset(&L, 0, sizeof(L));
+  int64_t capX = 1, capX2 = 1, capR = 1, capT1 = 1, capB = 1, capM = 2, capUS = 1, capSA = 2, capSJ = 1,
+          capQRS = 1, capQRT = 1;
+  std::vector<int64_t> capIn(K, 1), capQ(K, 1);
+  int maxdim = 1;
+  for (const auto& s : p.sw) {
+    for (int k = 0; k < K; ++k) {
+      if (s.explicit_in) capIn[k] = std::max(capIn[k], s.rin[k] * 2 * s.rin[k + 1]);
+      if (k <= K - 2) {
+        capQ[k] = std::max(capQ[k], 2 * s.rt[k] * s.rt[k + 1]);
+        capX = std::max(capX, 2 * s.rt[k] * s.rin[k + 1]);
+        capQRS = std::max(capQRS, 2 * s.rt[k] * s.rin[k + 1]);
+        capQRT = std::max(capQRT, s.rin[k + 1]);
+        capR = std::max(capR, s.rt[k + 1] * s.rin[k + 1]);
+      }
+      capR = std::max(capR, s.rt[k] * s.rin[k]);
+      if (k >= 1) {
+        capM = std::max(capM, s.rt[k] * 2 * s.rho[k + 1]);
+        capUS = std::max(capUS, s.rt[k] * s.rho[k]);
+        capSA = std::max(capSA, s.rt[k] * 2 * s.rho[k + 1]);
+        const int64_t cc = std::min(s.rt[k], 2 * s.rho[k + 1]);
+        capSJ = std::max(capSJ, cc * cc);
+        maxdim = (int)std::max<int64_t>(maxdim, std::max(s.rt[k], 2 * s.rho[k + 1]));
+      }
+      capM = std::max(capM, 2 * s.rho[1]);
+    }
+  }
+  if (p.kron) {
+    const auto& s = p.sw.back();  // the Kronecker rounding is listed last
+    for (int k = 0; k < n; ++k)
+      capT1 = std::max(capT1, s.rt[k] * p.D[k] * 2 * p.Rmax[k + 1]);
+    for (int k = n; k < K; ++k) {
+      capT1 = std::max(capT1, 2 * p.Rmax[k] * p.D[k + 1] * p2(K - k - 1));
+      capB = std::max(capB, p.Rmax[k] * p.D[k] * p2(K - k));
+    }
+    capX = std::max(capX, 2 * s.rt[n - 1] * p.Rmax[n] * p.D[n]);
+    for (int k = 0; k < n; ++k) capX = std::max(capX, 2 * s.rt[k] * p.Rmax[k + 1] * p.D[k + 1]);
+    capX2 = 2 * s.rt[n - 1] * p2(K - n);
+    capQRS = std::max(capQRS, capX2);
+  }
+  int64_t off = 0;
+  for (int k = 0; k < K; ++k) { L.cap_in[k] = capIn[k]; add64(off, L.off_in[k], capIn[k]); }
+  for (int k = 0; k < K; ++k) { L.cap_q[k] = capQ[k]; add64(off, L.off_q[k], capQ[k]); }
+  L.cap_X = capX; add64(off, L.off_X, capX);
+  L.cap_X2 = capX2; add64(off, L.off_X2, capX2);
+  L.cap_R = capR; add64(off, L.off_R, capR);
+  L.cap_T1 = capT1; add64(off, L.off_T1, capT1);
+  L.cap_B = capB; add64(off, L.off_B0, capB); add64(off, L.off_B1, capB);
+  L.cap_M = capM; add64(off, L.off_M, capM);
+  L.cap_US = capUS; add64(off, L.off_US, capUS);
+  L.cap_sA = capSA; add64(off, L.off_sA, capSA);
+  L.cap_sJ = capSJ; add64(off, L.off_sJ, capSJ);
+  L.cap_qrS = capQRS; add64(off, L.off_qrS, capQRS);
+  L.cap_qrT = capQRT; add64(off, L.off_qrT, capQRT);
+  L.stride = off;
+  L.maxdim = maxdim;
+}
+
+// Launch grids per op and site, from the capacity bonds of each rounding.
+struct Grids {
+  // [rounding][site]
+  std::vector<std::vector<int>> l2r, copyrx, absorb;
+  std::vector<int> kl1_t, kl1_b, kl2_t, kl2_b, kr1_t, kr2_t, kr2_b;
+  int meet = 0;
+};
+
+// ---------------------------------------------------------------------------
+// The state
+// ---------------------------------------------------------------------------
+struct Engine {
+  DevCtx h{};            // host mirror of the device context
+  DevCtx* d = nullptr;   // device copy
+  double* eng = nullptr;
+  Plan plan;
+  std::vector<SweepCaps> sw;
+};
+
+}  // namespace
+
+struct mpsw_state_s {
+  int B = 1, n = 0, K = 0;
+  std::vector<mpsw_config> cfg;
+  hipStream_t stream = nullptr;
+  int chi_cap = 1;
+  LapMPO lap;
+  // device allocations
+  double* mps = nullptr;
+  int* dims = nullptr;
+  double* reals = nullptr;
+  double* c2 = nullptr;
+  double* lapW = nullptr;
+  double* wavelet = nullptr;
+  double* dense = nullptr;
+  int* err = nullptr;
+  std::vector<int> c2b;
+  int nt_max = 0;
+  std::vector<std::vector<double>> wavelets;
+  Engine eng;              // step engine (after the velocity is known)
+  bool have_velocity = false;
+  int cur = 0, prev = 1, nxt = 2;
+  int64_t step = 0;
+  std::vector<int64_t> Rmax;
+  int64_t mps_stride = 0;
+  int64_t off_mps[MPSW_NSLOT][MPSW_MAXK];
+  int64_t cap_mps[MPSW_NSLOT][MPSW_MAXK];
+  Grids g;
+};
+
+namespace {
+
+int check_dev_err(mpsw_state st) {
+  int e = 0;
+  HIP_TRY(hipMemcpyAsync(&e, st->err, sizeof(int), hipMemcpyDeviceToHost, st->stream));
+  HIP_TRY(hipStreamSynchronize(st->stream));
+  if (e & MPSW_DEV_ERR_NONFINITE) return fail(MPSW_ENONFINITE, "non-finite singular value encountered");
+  if (e & (MPSW_DEV_ERR_CAP | MPSW_DEV_ERR_GRID))
+    return fail(MPSW_ENOMEM, "a live size exceeded the workspace (device error bits " + std::to_string(e) + ")");
+  return MPSW_OK;
+}
+
+// device context for the main (step) engine
+void fill_ctx(mpsw_state st, DevCtx& h, double* eng, const EngineLayout& L) {
+  std::memset(&h, 0, sizeof(h));
+  h.K = st->K;
+  h.n = st->n;
+  h.B = st->B;
+  h.boundary = st->cfg[0].boundary;
+  h.lam2 = st->cfg[0].lambda * st->cfg[0].lambda;
+  h.mps_stride = st->mps_stride;
+  h.mps = st->mps;
+  std::memcpy(h.off_mps, st->off_mps, sizeof(h.off_mps));
+  std::memcpy(h.cap_mps, st->cap_mps, sizeof(h.cap_mps));
+  h.dims = st->dims;
+  h.reals = st->reals;
+  h.eng = eng;
+  h.L = L;
+  h.c2 = st->c2;
+  int64_t off = 0;
+  for (int k = 0; k < st->K && !st->c2b.empty(); ++k) {
+    h.off_c2[k] = off;
+    off += (int64_t)st->c2b[k] * 2 * st->c2b[k + 1];
+  }
+  for (int k = 0; k <= st->K; ++k) h.c2b[k] = st->c2b.empty() ? 1 : st->c2b[k];
+  h.lapW = st->lapW;
+  int woff = 0;
+  for (int k = 0; k < st->K; ++k) {
+    h.off_W[k] = woff;
+    woff += st->lap.bonds[k] * st->lap.bonds[k + 1] * 4;
+  }
+  for (int k = 0; k <= st->K; ++k) h.wb[k] = st->lap.bonds[k];
+  h.wavelet = st->wavelet;
+  h.nt_max = st->nt_max;
+  h.dense = st->dense;
+  h.dense_stride = 2 * p2(st->K);
+  h.err = st->err;
+}
+
+int upload_ctx(Engine& e, hipStream_t s) {
+  if (!e.d) HIP_TRY(hipMalloc(&e.d, sizeof(DevCtx)));
+  HIP_TRY(hipMemcpyAsync(e.d, &e.h, sizeof(DevCtx), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MPSW_OK;
+}
+
+int tiles(int64_t M, int64_t N) { return std::max(1, cdiv(M, 64) * cdiv(N, 64)); }
+
+// ---------------------------------------------------------------------------
+// Rounding launch sequences
+// ---------------------------------------------------------------------------
+enum Kind { K_LAPLACE = 0, K_C2 = 1, K_SUM = 2, K_DENSE = 3 };
+
+// L->R sweep then R->L sweep for one rounding; output into MPS slot out_slot.
+void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int out_slot, int log_idx,
+                  int slot_a, int slot_b, int step, int nshots, hipStream_t strm) {
+  const int K = st->K, n = st->n;
+  const DevCtx* d = e.d;
+  OpArgs a{};
+  a.shot = -1;
+  a.aux = log_idx;
+  a.slot = slot_a;
+  a.slot2 = slot_b;
+  a.step = step;
+  a.op = (kind == K_LAPLACE) ? P_LAPLACE : (kind == K_C2) ? P_C2 : (kind == K_SUM) ? P_SUM : P_DENSE;
+  launch_prepare(d, a, nshots, strm);
+  if (kind == K_LAPLACE) {
+    int64_t mx = 1;
+    for (int k = 0; k < K; ++k) mx = std::max(mx, s.rin[k] * 2 * s.rin[k + 1]);
+    launch_pack_lap(d, a, K, nshots, std::min<int64_t>(1024, cdiv(mx, 256)), strm);
+  } else if (kind == K_SUM) {
+    int64_t mx = 1;
+    for (int k = 0; k < K; ++k) mx = std::max(mx, s.rin[k] * 2 * s.rin[k + 1]);
+    launch_pack_sum(d, a, K, nshots, std::min<int64_t>(1024, cdiv(mx, 256)), strm);
+  }
+  launch_init_R(d, a, nshots, strm);
+
+  const std::vector<int>& D = st->c2b;
+  const auto& R = st->Rmax;
+  if (kind == K_C2) {
+    for (int k = K - 1; k >= n; --k) {
+      const int rd = (K - k - 1) & 1, wr = (K - k) & 1;
+      OpArgs g{};
+      g.shot = -1;
+      g.site = k;
+      g.op = G_KRON_R1;
+      g.aux = rd;
+      launch_gemm(d, g, tiles(2 * R[k], (int64_t)D[k + 1] * p2(K - k - 1)), 1, nshots, strm);
+      g.op = G_KRON_R2;
+      g.aux = wr;
+      launch_gemm(d, g, tiles(D[k], p2(K - k - 1)), (int)(2 * R[k]), nshots, strm);
+    }
+  }
+  for (int k = 0; k < K; ++k) {
+    OpArgs g{};
+    g.shot = -1;
+    g.site = k;
+    const bool last = (k == K - 1);
+    bool meet = false;
+    if (kind == K_LAPLACE || kind == K_SUM) {
+      g.op = G_L2R_EXPLICIT;
+      g.aux = last ? 1 : 0;
+      launch_gemm(d, g, tiles(s.rt[k], 2 * s.rin[k + 1]), 1, nshots, strm);
+    } else if (kind == K_C2 && k < n) {
+      g.op = G_KRON_L1;
+      launch_gemm(d, g, tiles(D[k], 2 * R[k + 1]), (int)s.rt[k], nshots, strm);
+      g.op = G_KRON_L2;
+      launch_gemm(d, g, tiles(R[k + 1], D[k + 1]), (int)(2 * s.rt[k]), nshots, strm);
+      if (k == n - 1) {
+        g.op = G_MEET;
+        g.aux = (K - n) & 1;
+        launch_gemm(d, g, tiles(2 * s.rt[k], p2(K - n)), 1, nshots, strm);
+        meet = true;
+      }
+    } else {
+      g.op = G_COPY_RX;
+      g.aux = last ? 1 : 0;
+      launch_gemm(d, g, tiles(s.rt[k], s.rin[k]), 1, nshots, strm);
+    }
+    if (!last) {
+      OpArgs q{};
+      q.shot = -1;
+      q.site = k;
+      q.aux = meet ? 1 : 0;
+      launch_qr(d, q, nshots, strm);
+    }
+  }
+  for (int k = K - 1; k >= 1; --k) {
+    OpArgs v{};
+    v.shot = -1;
+    v.site = k;
+    v.slot = out_slot;
+    v.aux = log_idx;
+    launch_svd(d, v, nshots, strm);
+    OpArgs g{};
+    g.shot = -1;
+    g.site = k;
+    g.op = G_ABSORB;
+    launch_gemm(d, g, tiles(2 * s.rt[k - 1], s.rho[k]), 1, nshots, strm);
+  }
+  OpArgs f{};
+  f.shot = -1;
+  f.slot = out_slot;
+  launch_finish(d, f, nshots, strm);
+}
+
+std::vector<int64_t> state_rmax(int K, int64_t chi) {
+  std::vector<int64_t> r(K + 1);
+  for (int k = 0; k <= K; ++k) r[k] = std::min({chi, p2(k), p2(K - k)});
+  return r;
+}
+
+// Dense field(s) -> MPS by the right-to-left truncated TT-SVD, run on a
+// temporary single-shot engine.  out_slot of shot `shot` of st receives the
+// result when to_velocity is false; otherwise the cores become the c^2 operator.
+int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t chi, int shot, int out_slot,
+                 bool to_velocity) {
+  const int K = st->K;
+  const int64_t N = p2(K);
+  // temporary group-like context with one shot
+  std::vector<int64_t> rin(K + 1);
+  for (int k = 0; k <= K; ++k) rin[k] = p2(K - k);
+  SweepCaps s = sweep_caps(rin, K, chi);
+  Plan p;
+  p.K = K;
+  p.n = st->n;
+  p.sw = {s};
+  EngineLayout L;
+  layout_engine(p, L);
+  // one output slot with caps from the rho bounds
+  int64_t mps_stride = 0;
+  int64_t offs[MPSW_MAXK], caps[MPSW_MAXK];
+  for (int k = 0; k < K; ++k) {
+    caps[k] = s.rho[k] * 2 * s.rho[k + 1];
+    if (k == 0) caps[k] = 2 * s.rho[1];
+    offs[k] = mps_stride;
+    mps_stride += (caps[k] + 31) & ~(int64_t)31;
+  }
+  double *eng = nullptr, *mps = nullptr, *dense = nullptr, *reals = nullptr;
+  int* dims = nullptr;
+  int rc = MPSW_OK;
+  auto cleanup = [&]() {
+    hipFree(eng);
+    hipFree(mps);
+    hipFree(dense);
+    hipFree(reals);
+    hipFree(dims);
+  };
+  if (hipMalloc(&eng, L.stride * sizeof(double)) != hipSuccess || hipMalloc(&mps, mps_stride * sizeof(double)) != hipSuccess ||
+      hipMalloc(&dense, 2 * N * sizeof(double)) != hipSuccess || hipMalloc(&reals, RL::size * sizeof(double)) != hipSuccess ||
+      hipMalloc(&dims, DL::size * sizeof(int)) != hipSuccess) {
+    cleanup();
+    return fail(MPSW_ENOMEM, "dense_to_mps: device allocation failed");
+  }
+  Engine e;
+  DevCtx& h = e.h;
+  std::memset(&h, 0, sizeof(h));
+  h.K = K;
+  h.n = st->n;
+  h.B = 1;
+  h.mps = mps;
+  h.mps_stride = mps_stride;
+  for (int k = 0; k < K; ++k) { h.off_mps[0][k] = offs[k]; h.cap_mps[0][k] = caps[k]; }
+  h.dims = dims;
+  h.reals = reals;
+  h.eng = eng;
+  h.L = L;
+  for (int k = 0; k <= K; ++k) { h.c2b[k] = 1; h.wb[k] = 1; }
+  h.dense = dense;
+  h.dense_stride = 2 * N;
+  h.err = st->err;
+  std::vector<int> hd(DL::size, 0);
+  hd[DL::chi] = (int)std::min<int64_t>(chi, 1 << 30);
+  std::vector<double> hr(RL::size, 0.0);
+  hr[RL::eps] = eps;
+  hipStream_t s0 = st->stream;
+  if (hipMemcpyAsync(dims, hd.data(), DL::size * sizeof(int), hipMemcpyHostToDevice, s0) != hipSuccess ||
+      hipMemcpyAsync(reals, hr.data(), RL::size * sizeof(double), hipMemcpyHostToDevice, s0) != hipSuccess ||
+      hipMemcpyAsync(dense, host_field, N * sizeof(double), hipMemcpyHostToDevice, s0) != hipSuccess) {
+    cleanup();
+    return fail(MPSW_EHIP, "dense_to_mps: upload failed");
+  }
+  if ((rc = upload_ctx(e, s0)) != MPSW_OK) { cleanup(); return rc; }
+  // swap in the temporary engine: run_rounding uses st only for K/n/c2b/Rmax
+  run_rounding(st, e, K_DENSE, s, 0, -1, 0, 0, 0, 1, s0);
+  if (hipGetLastError() != hipSuccess) { cleanup(); hipFree(e.d); return fail(MPSW_EHIP, "dense_to_mps: launch failed"); }
+  if ((rc = check_dev_err(st)) != MPSW_OK) { cleanup(); hipFree(e.d); return rc; }
+  // bonds of the result
+  std::vector<int> dd(DL::size);
+  hipMemcpy(dd.data(), dims, DL::size * sizeof(int), hipMemcpyDeviceToHost);
+  std::vector<int> bonds(K + 1);
+  for (int k = 0; k <= K; ++k) bonds[k] = dd[DL::bonds + k];
+  if (to_velocity) {
+    int64_t tot = 0;
+    for (int k = 0; k < K; ++k) tot += (int64_t)bonds[k] * 2 * bonds[k + 1];
+    hipFree(st->c2);
+    st->c2 = nullptr;
+    if (hipMalloc(&st->c2, tot * sizeof(double)) != hipSuccess) { cleanup(); hipFree(e.d); return fail(MPSW_ENOMEM, "c2 alloc"); }
+    int64_t o = 0;
+    for (int k = 0; k < K; ++k) {
+      const int64_t sz = (int64_t)bonds[k] * 2 * bonds[k + 1];
+      hipMemcpyAsync(st->c2 + o, mps + offs[k], sz * sizeof(double), hipMemcpyDeviceToDevice, s0);
+      o += sz;
+    }
+    st->c2b = bonds;
+  } else {
+    for (int k = 0; k < K; ++k) {
+      const int64_t sz = (int64_t)bonds[k] * 2 * bonds[k + 1];
+      if (sz > st->cap_mps[out_slot][k]) { cleanup(); hipFree(e.d); return fail(MPSW_ENOMEM, "field rank exceeds chi_max caps"); }
+      hipMemcpyAsync(st->mps + shot * st->mps_stride + st->off_mps[out_slot][k], mps + offs[k], sz * sizeof(double),
+                     hipMemcpyDeviceToDevice, s0);
+    }
+    // bonds into the main dims block
+    hipMemcpyAsync(st->dims + (int64_t)shot * DL::size + DL::bonds + out_slot * (MPSW_MAXK + 1), bonds.data(),
+                   (K + 1) * sizeof(int), hipMemcpyHostToDevice, s0);
+  }
+  hipStreamSynchronize(s0);
+  cleanup();
+  hipFree(e.d);
+  return MPSW_OK;
+}
+
+// Build the step engine once c^2 is known.
+int build_step_engine(mpsw_state st) {
+  const int K = st->K, n = st->n;
+  Engine& e = st->eng;
+  if (e.eng) { hipFree(e.eng); e.eng = nullptr; }
+  const auto& R = st->Rmax;
+  std::vector<int64_t> r1(K + 1), r2(K + 1), r3(K + 1);
+  for (int k = 0; k <= K; ++k) {
+    r1[k] = (int64_t)st->lap.bonds[k] * R[k];
+    r2[k] = (k < n) ? (int64_t)st->c2b[k] * R[k] : p2(K - k);
+    r3[k] = (k == 0 || k == K) ? 1 : 3 * R[k] + 1;
+  }
+  e.sw = {sweep_caps(r1, K, st->chi_cap), sweep_caps(r3, K, st->chi_cap), sweep_caps(r2, K, st->chi_cap)};
+  e.sw[0].explicit_in = true;
+  e.sw[1].explicit_in = true;
+  e.plan.K = K;
+  e.plan.n = n;
+  e.plan.sw = e.sw;
+  e.plan.Rmax = R;
+  e.plan.D = st->c2b;
+  e.plan.kron = true;
+  EngineLayout L;
+  layout_engine(e.plan, L);
+  if (hipMalloc(&e.eng, (size_t)L.stride * st->B * sizeof(double)) != hipSuccess)
+    return fail(MPSW_ENOMEM, "step workspace allocation failed (" + std::to_string(L.stride * st->B * 8 / (1 << 20)) + " MiB)");
+  fill_ctx(st, e.h, e.eng, L);
+  return upload_ctx(e, st->stream);
+}
+
+int upload_lap(mpsw_state st) {
+  std::vector<double> w;
+  for (auto& c : st->lap.cores) w.insert(w.end(), c.begin(), c.end());
+  HIP_TRY(hipMalloc(&st->lapW, std::max<size_t>(1, w.size()) * sizeof(double)));
+  HIP_TRY(hipMemcpy(st->lapW, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
+  return MPSW_OK;
+}
+
+int create_group(const mpsw_config* cfgs, int nshots, void* stream, mpsw_state* out) {
+  if (!cfgs || !out || nshots < 1) return fail(MPSW_EINVAL, "null argument or nshots < 1");
+  const mpsw_config& c0 = cfgs[0];
+  for (int i = 0; i < nshots; ++i) {
+    const mpsw_config& c = cfgs[i];
+    if (c.n < 1 || c.n > 12) return fail(MPSW_EINVAL, "n must be in [1, 12]");
+    if (c.chi_max < 1) return fail(MPSW_EINVAL, "chi_max must be >= 1");
+    if (!(c.eps >= 0.0) || !std::isfinite(c.eps)) return fail(MPSW_EINVAL, "eps must be finite and >= 0");
+    if (!(c.lambda > 0.0) || !std::isfinite(c.lambda)) return fail(MPSW_EINVAL, "lambda must be > 0");
+    if (c.precision != MPSW_FP64 && c.precision != MPSW_FP32 && c.precision != MPSW_BF16)
+      return fail(MPSW_EINVAL, "unknown precision");
+    if (c.boundary != MPSW_PERIODIC && c.boundary != MPSW_OPEN) return fail(MPSW_EINVAL, "unknown boundary");
+    if (c.rank_mode != MPSW_RANK_EXACT && c.rank_mode != MPSW_RANK_LEARNED) return fail(MPSW_EINVAL, "unknown rank mode");
+    if (c.n != c0.n || c.lambda != c0.lambda || c.precision != c0.precision || c.boundary != c0.boundary)
+      return fail(MPSW_EINVAL, "shots of one batch must share n, lambda, precision and boundary");
+  }
+  if (c0.precision != MPSW_FP64) return fail(MPSW_EINVAL, "this build implements the FP64 path only");
+  if (c0.rank_mode != MPSW_RANK_EXACT) return fail(MPSW_EINVAL, "this build implements the exact rank mode only");
+  mpsw_state st = new mpsw_state_s();
+  st->B = nshots;
+  st->n = c0.n;
+  st->K = 2 * c0.n;
+  st->cfg.assign(cfgs, cfgs + nshots);
+  st->stream = (hipStream_t)stream;
+  st->chi_cap = 1;
+  for (int i = 0; i < nshots; ++i) st->chi_cap = std::max(st->chi_cap, cfgs[i].chi_max);
+  const int K = st->K;
+  st->lap = build_laplacian_mpo(st->n, c0.boundary);
+  st->Rmax = state_rmax(K, st->chi_cap);
+  // MPS slots
+  int64_t off = 0;
+  for (int s = 0; s < MPSW_NSLOT; ++s)
+    for (int k = 0; k < K; ++k) {
+      st->cap_mps[s][k] = std::max<int64_t>(2, st->Rmax[k] * 2 * st->Rmax[k + 1]);
+      st->off_mps[s][k] = off;
+      off += (st->cap_mps[s][k] + 31) & ~(int64_t)31;
+    }
+  st->mps_stride = off;
+  int rc;
+  auto bail = [&](int code) {
+    mpsw_destroy(st);
+    return code;
+  };
+  if (hipMalloc(&st->mps, (size_t)st->mps_stride * nshots * sizeof(double)) != hipSuccess ||
+      hipMalloc(&st->dims, (size_t)DL::size * nshots * sizeof(int)) != hipSuccess ||
+      hipMalloc(&st->reals, (size_t)RL::size * nshots * sizeof(double)) != hipSuccess ||
+      hipMalloc(&st->err, sizeof(int)) != hipSuccess ||
+      hipMalloc(&st->dense, (size_t)2 * p2(K) * sizeof(double)) != hipSuccess)
+    return bail(fail(MPSW_ENOMEM, "state allocation failed"));
+  if ((rc = upload_lap(st)) != MPSW_OK) return bail(rc);
+  std::vector<int> hd((size_t)DL::size * nshots, 0);
+  std::vector<double> hr((size_t)RL::size * nshots, 0.0);
+  for (int i = 0; i < nshots; ++i) {
+    int* d = hd.data() + (size_t)i * DL::size;
+    for (int s = 0; s < MPSW_NSLOT; ++s)
+      for (int k = 0; k <= K; ++k) d[DL::bonds + s * (MPSW_MAXK + 1) + k] = 1;
+    d[DL::chi] = cfgs[i].chi_max;
+    hr[(size_t)i * RL::size + RL::eps] = cfgs[i].eps;
+  }
+  if (hipMemcpy(st->dims, hd.data(), hd.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(st->reals, hr.data(), hr.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(st->err, 0, sizeof(int)) != hipSuccess ||
+      hipMemset(st->mps, 0, (size_t)st->mps_stride * nshots * sizeof(double)) != hipSuccess)
+    return bail(fail(MPSW_EHIP, "state initialisation failed"));
+  st->wavelets.assign(nshots, {});
+  *out = st;
+  return MPSW_OK;
+}
+
+int upload_wavelets(mpsw_state st) {
+  int ntm = 1;
+  for (auto& w : st->wavelets) ntm = std::max<int>(ntm, (int)w.size());
+  std::vector<double> buf((size_t)ntm * st->B, 0.0);
+  for (int i = 0; i < st->B; ++i) std::copy(st->wavelets[i].begin(), st->wavelets[i].end(), buf.begin() + (size_t)i * ntm);
+  hipFree(st->wavelet);
+  st->wavelet = nullptr;
+  HIP_TRY(hipMalloc(&st->wavelet, buf.size() * sizeof(double)));
+  HIP_TRY(hipMemcpy(st->wavelet, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
+  st->nt_max = ntm;
+  if (st->eng.eng) {
+    st->eng.h.wavelet = st->wavelet;
+    st->eng.h.nt_max = ntm;
+    return upload_ctx(st->eng, st->stream);
+  }
+  return MPSW_OK;
+}
+
+// to_dense of shot `shot`: slot >= 0 or -1 for c^2.  Result in a host vector.
+int contract_dense(mpsw_state st, int shot, int slot, std::vector<double>& out) {
+  const int K = st->K;
+  Engine& e = st->eng;
+  Engine tmp;
+  Engine* use = &e;
+  if (!e.eng) {  // before the velocity: a context without an engine arena
+    EngineLayout L;
+    std::memset(&L, 0, sizeof(L));
+    fill_ctx(st, tmp.h, nullptr, L);
+    int rc = upload_ctx(tmp, st->stream);
+    if (rc != MPSW_OK) return rc;
+    use = &tmp;
+  }
+  launch_dense_init(use->d, 1, st->stream);
+  for (int k = 0; k < K; ++k) {
+    OpArgs g{};
+    g.op = G_DENSE;
+    g.site = k;
+    g.slot = slot;
+    g.shot = shot;
+    const int64_t r1 = (slot < 0) ? st->c2b[k + 1] : st->Rmax[k + 1];
+    launch_gemm(use->d, g, tiles(p2(k), 2 * r1), 1, 1, st->stream);
+  }
+  out.resize(p2(K));
+  const int64_t half = p2(K);
+  const double* src = st->dense + (((K - 1) & 1) ? 0 : half);
+  HIP_TRY(hipMemcpyAsync(out.data(), src, half * sizeof(double), hipMemcpyDeviceToHost, st->stream));
+  int rc = check_dev_err(st);
+  if (tmp.d) hipFree(tmp.d);
+  return rc;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* mpsw_last_error(void) { return g_last_error.c_str(); }
+
+int mpsw_create_state(const mpsw_config* cfg, void* hip_stream, mpsw_state* out) {
+  return create_group(cfg, 1, hip_stream, out);
+}
+
+int mpsw_create_batch(const mpsw_config* cfgs, int nshots, void* hip_stream, mpsw_state* out) {
+  return create_group(cfgs, nshots, hip_stream, out);
+}
+
+int mpsw_destroy(mpsw_state st) {
+  if (!st) return MPSW_OK;
+  if (st->stream) hipStreamSynchronize(st->stream);
+  else hipDeviceSynchronize();
+  hipFree(st->mps);
+  hipFree(st->dims);
+  hipFree(st->reals);
+  hipFree(st->c2);
+  hipFree(st->lapW);
+  hipFree(st->wavelet);
+  hipFree(st->dense);
+  hipFree(st->err);
+  hipFree(st->eng.eng);
+  hipFree(st->eng.d);
+  delete st;
+  return MPSW_OK;
+}
+
+int mpsw_get_shape(mpsw_state st, int* nshots, int* nsites) {
+  if (!st) return fail(MPSW_EINVAL, "null state");
+  if (nshots) *nshots = st->B;
+  if (nsites) *nsites = st->K;
+  return MPSW_OK;
+}
+
+int mpsw_set_velocity_dense(mpsw_state st, const double* c2, double eps_c) {
+  if (!st || !c2) return fail(MPSW_EINVAL, "null argument");
+  if (!(eps_c >= 0.0)) return fail(MPSW_EINVAL, "eps_c must be >= 0");
+  const int64_t N = p2(st->K);
+  double mx = 0.0;
+  for (int64_t i = 0; i < N; ++i) {
+    if (!(c2[i] > 0.0) || !std::isfinite(c2[i])) return fail(MPSW_EINVAL, "c^2 must be finite and > 0");
+    mx = std::max(mx, c2[i]);
+  }
+  const double lam = st->cfg[0].lambda;
+  if (lam * lam * mx * 2.0 > 1.0) return fail(MPSW_ECFL, "CFL violated: lambda^2 max(c^2) 2 > 1");
+  int rc = dense_to_mps(st, c2, eps_c, p2(st->K), 0, 0, true);
+  if (rc != MPSW_OK) return rc;
+  if ((rc = build_step_engine(st)) != MPSW_OK) return rc;
+  st->have_velocity = true;
+  return MPSW_OK;
+}
+
+int mpsw_set_velocity_mpo(mpsw_state st, const int* bonds, const double* cores) {
+  if (!st || !bonds || !cores) return fail(MPSW_EINVAL, "null argument");
+  const int K = st->K;
+  if (bonds[0] != 1 || bonds[K] != 1) return fail(MPSW_EINVAL, "bonds[0] and bonds[K] must be 1");
+  int64_t tot = 0;
+  for (int k = 0; k < K; ++k) {
+    if (bonds[k + 1] < 1 || bonds[k + 1] > (1 << 20)) return fail(MPSW_EINVAL, "bad bond");
+    tot += (int64_t)bonds[k] * 2 * bonds[k + 1];
+  }
+  hipFree(st->c2);
+  st->c2 = nullptr;
+  HIP_TRY(hipMalloc(&st->c2, tot * sizeof(double)));
+  HIP_TRY(hipMemcpy(st->c2, cores, tot * sizeof(double), hipMemcpyHostToDevice));
+  st->c2b.assign(bonds, bonds + K + 1);
+  std::vector<double> dense;
+  int rc = contract_dense(st, 0, -1, dense);
+  if (rc != MPSW_OK) return rc;
+  double mx = 0.0;
+  for (double v : dense) {
+    if (!std::isfinite(v)) return fail(MPSW_EINVAL, "non-finite c^2");
+    mx = std::max(mx, v);
+  }
+  const double lam = st->cfg[0].lambda;
+  if (lam * lam * mx * 2.0 > 1.0) return fail(MPSW_ECFL, "CFL violated: lambda^2 max(c^2) 2 > 1");
+  if ((rc = build_step_engine(st)) != MPSW_OK) return rc;
+  st->have_velocity = true;
+  return MPSW_OK;
+}
+
+int mpsw_set_source(mpsw_state st, int shot, int ix, int iz, int nt, const double* wavelet) {
+  if (!st) return fail(MPSW_EINVAL, "null state");
+  const int N = 1 << st->n;
+  if (shot < 0 || shot >= st->B) return fail(MPSW_EINVAL, "shot out of range");
+  if (ix < 0 || ix >= N || iz < 0 || iz >= N) return fail(MPSW_EINVAL, "source outside the grid");
+  if (nt < 0 || (nt > 0 && !wavelet)) return fail(MPSW_EINVAL, "bad wavelet");
+  st->wavelets[shot].assign(wavelet, wavelet + nt);
+  int vals[3] = {ix, iz, nt};
+  HIP_TRY(hipMemcpy(st->dims + (int64_t)shot * DL::size + DL::src_ix, vals, sizeof(vals), hipMemcpyHostToDevice));
+  return upload_wavelets(st);
+}
+
+int mpsw_set_fields(mpsw_state st, int shot, const double* u_prev, const double* u_cur) {
+  if (!st) return fail(MPSW_EINVAL, "null state");
+  if (shot < 0 || shot >= st->B) return fail(MPSW_EINVAL, "shot out of range");
+  const double* fields[2] = {u_prev, u_cur};
+  const int slots[2] = {st->prev, st->cur};
+  for (int t = 0; t < 2; ++t) {
+    if (!fields[t]) {
+      Engine tmp;
+      EngineLayout L;
+      std::memset(&L, 0, sizeof(L));
+      fill_ctx(st, tmp.h, nullptr, L);
+      int rc = upload_ctx(tmp, st->stream);
+      if (rc != MPSW_OK) return rc;
+      OpArgs a{};
+      a.slot = slots[t];
+      a.shot = shot;
+      launch_zero_state(tmp.d, a, st->B, st->stream);
+      hipStreamSynchronize(st->stream);
+      hipFree(tmp.d);
+      continue;
+    }
+    int rc = dense_to_mps(st, fields[t], st->cfg[shot].eps, st->cfg[shot].chi_max, shot, slots[t], false);
+    if (rc != MPSW_OK) return rc;
+  }
+  st->step = 0;
+  return MPSW_OK;
+}
+
+int mpsw_step(mpsw_state st, int k) {
+  if (!st) return fail(MPSW_EINVAL, "null state");
+  if (k < 0) return fail(MPSW_EINVAL, "k must be >= 0");
+  if (!st->have_velocity) return fail(MPSW_ESTATE, "set the velocity before stepping");
+  Engine& e = st->eng;
+  for (int it = 0; it < k; ++it) {
+    const int step = (int)std::min<int64_t>(st->step, 1 << 30);
+    run_rounding(st, e, K_LAPLACE, e.sw[0], MPSW_SLOT_Y, 0, st->cur, 0, step, st->B, st->stream);
+    run_rounding(st, e, K_C2, e.sw[2], MPSW_SLOT_W, 1, 0, 0, step, st->B, st->stream);
+    run_rounding(st, e, K_SUM, e.sw[1], st->nxt, 2, st->cur, st->prev, step, st->B, st->stream);
+    const int old_prev = st->prev;
+    st->prev = st->cur;
+    st->cur = st->nxt;
+    st->nxt = old_prev;
+    ++st->step;
+  }
+  HIP_TRY(hipGetLastError());
+  return MPSW_OK;
+}
+
+int mpsw_to_dense(mpsw_state st, int shot, int which, double* out, int out_is_device) {
+  if (!st || !out) return fail(MPSW_EINVAL, "null argument");
+  if (shot < 0 || shot >= st->B) return fail(MPSW_EINVAL, "shot out of range");
+  int slot;
+  switch (which) {
+    case 0: slot = st->cur; break;
+    case 1: slot = st->prev; break;
+    case 2: slot = -1; break;
+    case 3: slot = MPSW_SLOT_Y; break;
+    case 4: slot = MPSW_SLOT_W; break;
+    default: return fail(MPSW_EINVAL, "which must be 0..4");
+  }
+  if (slot < 0 && st->c2b.empty()) return fail(MPSW_ESTATE, "no velocity set");
+  std::vector<double> host;
+  int rc = contract_dense(st, shot, slot, host);
+  if (rc != MPSW_OK) return rc;
+  for (double v : host)
+    if (!std::isfinite(v)) return fail(MPSW_ENONFINITE, "non-finite value in the field");
+  if (out_is_device) {
+    HIP_TRY(hipMemcpy(out, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
+  } else {
+    std::memcpy(out, host.data(), host.size() * sizeof(double));
+  }
+  return MPSW_OK;
+}
+
+int mpsw_get_bonds(mpsw_state st, int shot, int which, int* bonds) {
+  if (!st || !bonds) return fail(MPSW_EINVAL, "null argument");
+  if (shot < 0 || shot >= st->B) return fail(MPSW_EINVAL, "shot out of range");
+  if (which == 2) {
+    if (st->c2b.empty()) return fail(MPSW_ESTATE, "no velocity set");
+    std::copy(st->c2b.begin(), st->c2b.end(), bonds);
+    return MPSW_OK;
+  }
+  int slot;
+  switch (which) {
+    case 0: slot = st->cur; break;
+    case 1: slot = st->prev; break;
+    case 3: slot = MPSW_SLOT_Y; break;
+    case 4: slot = MPSW_SLOT_W; break;
+    default: return fail(MPSW_EINVAL, "which must be 0..4");
+  }
+  HIP_TRY(hipStreamSynchronize(st->stream));
+  HIP_TRY(hipMemcpy(bonds, st->dims + (int64_t)shot * DL::size + DL::bonds + slot * (MPSW_MAXK + 1),
+                    (st->K + 1) * sizeof(int), hipMemcpyDeviceToHost));
+  return check_dev_err(st);
+}
+
+int mpsw_get_stats(mpsw_state st, int shot, mpsw_stats* out) {
+  if (!st || !out) return fail(MPSW_EINVAL, "null argument");
+  if (shot < 0 || shot >= st->B) return fail(MPSW_EINVAL, "shot out of range");
+  int rc = check_dev_err(st);
+  if (rc != MPSW_OK) return rc;
+  std::vector<int> d(DL::size);
+  std::vector<double> r(RL::size);
+  HIP_TRY(hipMemcpy(d.data(), st->dims + (int64_t)shot * DL::size, DL::size * sizeof(int), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(r.data(), st->reals + (int64_t)shot * RL::size, RL::size * sizeof(double), hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof(*out));
+  out->step = st->step;
+  out->nsites = st->K;
+  for (int k = 0; k <= st->K; ++k) out->bonds[k] = d[DL::bonds + st->cur * (MPSW_MAXK + 1) + k];
+  for (int i = 0; i < 3; ++i) {
+    out->max_exact_bond[i] = d[DL::maxbond + i];
+    out->tail2[i] = r[RL::tail2 + i];
+  }
+  out->fallbacks = 0;
+  return MPSW_OK;
+}
+
+// Host-side helper exported for tests: the fused Laplacian MPO cores
+// ([wl][wr][s'][s] per site, packed) and bonds (K+1) for a register of n bits.
+int mpsw_debug_laplacian_mpo(int n, int boundary, int* bonds, double* cores, int64_t cap) {
+  if (n < 1 || n > 12 || !bonds) return fail(MPSW_EINVAL, "bad argument");
+  LapMPO m = build_laplacian_mpo(n, boundary);
+  std::copy(m.bonds.begin(), m.bonds.end(), bonds);
+  int64_t o = 0;
+  for (auto& c : m.cores) {
+    if (cores) {
+      if (o + (int64_t)c.size() > cap) return fail(MPSW_ENOMEM, "cores buffer too small");
+      std::copy(c.begin(), c.end(), cores + o);
+    }
+    o += (int64_t)c.size();
+  }
+  return (int)o;
+}
+
+}  // extern "C"

@@ -1,0 +1,200 @@
+"""ctypes binding of libmpsw (argument marshalling only).
+
+Every computation happens in the HIP library; this module converts Python and
+NumPy (or torch) arguments into the C ABI declared in include/mpsw.h and turns
+error codes into exceptions.  It fails loudly when the library is not built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpsw.so")
+
+MPSW_FP64, MPSW_FP32, MPSW_BF16 = 0, 1, 2
+MPSW_PERIODIC, MPSW_OPEN = 0, 1
+MPSW_RANK_EXACT, MPSW_RANK_LEARNED = 0, 1
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ECFL", -6: "ENONFINITE"}
+
+EXPORTS = [
+    "mpsw_create_state", "mpsw_create_batch", "mpsw_set_velocity_dense", "mpsw_set_velocity_mpo",
+    "mpsw_set_source", "mpsw_set_fields", "mpsw_step", "mpsw_to_dense", "mpsw_get_bonds",
+    "mpsw_get_stats", "mpsw_get_shape", "mpsw_destroy", "mpsw_last_error", "mpsw_debug_laplacian_mpo",
+]
+
+
+class MpswError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("chi_max", ctypes.c_int), ("eps", ctypes.c_double),
+                ("lambda_", ctypes.c_double), ("precision", ctypes.c_int), ("boundary", ctypes.c_int),
+                ("rank_mode", ctypes.c_int), ("seed", ctypes.c_uint64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("nsites", ctypes.c_int), ("bonds", ctypes.c_int * 64),
+                ("max_exact_bond", ctypes.c_int * 3), ("tail2", ctypes.c_double * 3),
+                ("fallbacks", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load():
+    """The loaded library; raises if libmpsw.so has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libmpsw.so not found at {LIB_PATH}: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.mpsw_last_error.restype = ctypes.c_char_p
+    sig = {
+        "mpsw_create_state": [ctypes.POINTER(Config), P, ctypes.POINTER(P)],
+        "mpsw_create_batch": [ctypes.POINTER(Config), I, P, ctypes.POINTER(P)],
+        "mpsw_set_velocity_dense": [P, P, D],
+        "mpsw_set_velocity_mpo": [P, P, P],
+        "mpsw_set_source": [P, I, I, I, I, P],
+        "mpsw_set_fields": [P, I, P, P],
+        "mpsw_step": [P, I],
+        "mpsw_to_dense": [P, I, I, P, I],
+        "mpsw_get_bonds": [P, I, I, P],
+        "mpsw_get_stats": [P, I, ctypes.POINTER(Stats)],
+        "mpsw_get_shape": [P, ctypes.POINTER(I), ctypes.POINTER(I)],
+        "mpsw_destroy": [P],
+        "mpsw_debug_laplacian_mpo": [I, I, P, P, ctypes.c_int64],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = I
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc < 0:
+        msg = load().mpsw_last_error().decode(errors="replace")
+        raise MpswError(rc, msg)
+    return rc
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def make_config(n, chi_max, eps, lam, precision=MPSW_FP64, boundary=MPSW_PERIODIC,
+                rank_mode=MPSW_RANK_EXACT, seed=0):
+    return Config(n, chi_max, eps, lam, precision, boundary, rank_mode, seed)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)   # torch.cuda.Stream
+
+
+class State:
+    """One shot (cfg is a Config) or a batch (cfg is a list of Configs)."""
+
+    def __init__(self, cfg, stream=None):
+        lib = load()
+        self._h = ctypes.c_void_p()
+        if isinstance(cfg, (list, tuple)):
+            arr = (Config * len(cfg))(*cfg)
+            _check(lib.mpsw_create_batch(arr, len(cfg), _stream_handle(stream), ctypes.byref(self._h)))
+            self.n = cfg[0].n
+        else:
+            _check(lib.mpsw_create_state(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(self._h)))
+            self.n = cfg.n
+        nshots, nsites = ctypes.c_int(), ctypes.c_int()
+        _check(lib.mpsw_get_shape(self._h, ctypes.byref(nshots), ctypes.byref(nsites)))
+        self.nshots, self.K = nshots.value, nsites.value
+
+    def close(self):
+        if self._h:
+            load().mpsw_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_velocity_dense(self, c2, eps_c):
+        a, p = _f64(c2)
+        _check(load().mpsw_set_velocity_dense(self._h, p, float(eps_c)))
+
+    def set_velocity_mpo(self, bonds, cores):
+        b = np.ascontiguousarray(bonds, dtype=np.int32)
+        c, p = _f64(np.concatenate([np.ravel(x) for x in cores]))
+        _check(load().mpsw_set_velocity_mpo(self._h, b.ctypes.data_as(ctypes.c_void_p), p))
+
+    def set_source(self, shot, ix, iz, wavelet):
+        w, p = _f64(wavelet)
+        _check(load().mpsw_set_source(self._h, shot, ix, iz, w.size, p))
+
+    def set_fields(self, shot, u_prev, u_cur):
+        args = []
+        keep = []
+        for u in (u_prev, u_cur):
+            if u is None:
+                args.append(None)
+            else:
+                a, p = _f64(u)
+                keep.append(a)
+                args.append(p)
+        _check(load().mpsw_set_fields(self._h, shot, args[0], args[1]))
+
+    def step(self, k=1):
+        _check(load().mpsw_step(self._h, int(k)))
+
+    def to_dense(self, shot=0, which=0, out=None):
+        """Dense field as a (2^n, 2^n) float64 array; `out` may be a CUDA torch tensor."""
+        N = 1 << self.n
+        if out is not None and hasattr(out, "data_ptr"):
+            _check(load().mpsw_to_dense(self._h, shot, which, ctypes.c_void_p(out.data_ptr()), 1))
+            return out
+        a = np.empty((N, N), dtype=np.float64)
+        _check(load().mpsw_to_dense(self._h, shot, which, a.ctypes.data_as(ctypes.c_void_p), 0))
+        return a
+
+    def bonds(self, shot=0, which=0):
+        b = np.zeros(self.K + 1, dtype=np.int32)
+        _check(load().mpsw_get_bonds(self._h, shot, which, b.ctypes.data_as(ctypes.c_void_p)))
+        return [int(x) for x in b]
+
+    def stats(self, shot=0):
+        s = Stats()
+        _check(load().mpsw_get_stats(self._h, shot, ctypes.byref(s)))
+        return {"step": s.step, "bonds": list(s.bonds[: self.K + 1]),
+                "max_exact_bond": list(s.max_exact_bond), "tail2": list(s.tail2),
+                "fallbacks": s.fallbacks}
+
+
+def debug_laplacian_mpo(n, boundary=MPSW_PERIODIC):
+    """Host-built fused Laplacian MPO cores (list of [wl, wr, 2, 2] arrays)."""
+    lib = load()
+    K = 2 * n
+    bonds = np.zeros(K + 1, dtype=np.int32)
+    total = _check(lib.mpsw_debug_laplacian_mpo(n, boundary, bonds.ctypes.data_as(ctypes.c_void_p), None, 0))
+    buf = np.zeros(max(total, 1))
+    _check(lib.mpsw_debug_laplacian_mpo(n, boundary, bonds.ctypes.data_as(ctypes.c_void_p),
+                                        buf.ctypes.data_as(ctypes.c_void_p), buf.size))
+    cores, o = [], 0
+    for k in range(K):
+        sz = bonds[k] * bonds[k + 1] * 4
+        cores.append(buf[o:o + sz].reshape(bonds[k], bonds[k + 1], 2, 2))
+        o += sz
+    return [int(b) for b in bonds], cores

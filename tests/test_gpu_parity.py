@@ -1,0 +1,227 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64 tolerances: both sides compute the same rounded tensors with different
+but backward-stable factorizations (Householder QR + one-sided Jacobi SVD on
+the GPU, LAPACK on the CPU), so results agree to a small multiple of the
+rounding unit times the number of operations, far below the cutoffs used;
+1e-10 relative L2 is asserted for truncated runs, 1e-12 where nothing is cut.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fdtd as F
+from oracle import mps as M
+from oracle import stepper as S
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mpsw():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2609_01904_amd import mpsw as m
+    m.load()
+    return m
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def make_state(mpsw, n, chi, eps, lam, boundary=0):
+    return mpsw.State(mpsw.make_config(n, chi, eps, lam, boundary=boundary))
+
+
+def test_velocity_operator_matches_oracle(mpsw):
+    for n, eps_c in [(4, 1e-8), (6, 1e-6), (8, 1e-6)]:
+        _say("velocity", n)
+        c2 = synth.layered_fault_velocity(n)
+        st = make_state(mpsw, n, 16, 1e-8, 1e-4)
+        st.set_velocity_dense(c2, eps_c)
+        ref = S.c2_mps(c2, n, eps_c)
+        assert st.bonds(0, 2) == M.bonds_of(ref)
+        got = st.to_dense(0, 2)
+        assert rel(got.reshape(-1), M.to_dense(ref)) < 1e-12
+        st.close()
+
+
+def test_fields_roundtrip_exact(mpsw):
+    n = 5
+    st = make_state(mpsw, n, 1 << n, 0.0, 0.1)
+    st.set_velocity_dense(np.ones((1 << n, 1 << n)), 1e-12)
+    up, u = synth.random_fields(n, seed=3, smooth=False)
+    st.set_fields(0, up, u)
+    assert rel(st.to_dense(0, 0), u) < 1e-13
+    assert rel(st.to_dense(0, 1), up) < 1e-13
+    st.close()
+
+
+@pytest.mark.parametrize("n", [3, 4])
+@pytest.mark.parametrize("boundary", [0, 1])
+def test_untruncated_step_equals_fdtd(mpsw, n, boundary):
+    """Table 1: the MPS update reproduces eq. 2 when nothing is truncated."""
+    _say("untruncated", n, boundary)
+    N = 1 << n
+    rng = np.random.default_rng(n)
+    c2 = 0.5 + rng.random((N, N))
+    lam = 0.4
+    wav = rng.standard_normal(10)
+    src = (N // 2, 1)
+    st = make_state(mpsw, n, 1 << n, 0.0, lam, boundary)
+    st.set_velocity_dense(c2, 0.0)
+    c2r = st.to_dense(0, 2)
+    up, u = synth.random_fields(n, seed=n, smooth=False)
+    st.set_fields(0, up, u)
+    st.set_source(0, src[0], src[1], wav)
+    a, b = up, u
+    bname = "periodic" if boundary == 0 else "open"
+    for k in range(10):
+        st.step(1)
+        a, b = b, F.fdtd_step(b, a, c2r, lam, wav[k], src, bname)
+        assert rel(st.to_dense(0, 0), b) < 1e-12, k
+    st.close()
+
+
+def test_each_rounding_matches_oracle(mpsw):
+    """y = round(L psi), w = round(C^2 y), psi' = round(sum) after one step."""
+    n, chi, eps = 5, 12, 1e-6
+    N = 1 << n
+    c2 = synth.layered_fault_velocity(n, dh=40.0) * 1e-8
+    lam = 0.5
+    c2m = S.c2_mps(c2, n, 1e-8)
+    st = make_state(mpsw, n, chi, eps, lam)
+    st.set_velocity_dense(c2, 1e-8)
+    up, u = synth.random_fields(n, seed=7)
+    st.set_fields(0, up, u)
+    psi = M.tt_svd(u.reshape(-1), 2 * n, eps, chi)
+    psip = M.tt_svd(up.reshape(-1), 2 * n, eps, chi)
+    assert rel(st.to_dense(0, 0).reshape(-1), M.to_dense(psi)) < 1e-12
+    st.step(1)
+    y = M.round_mps(M.laplacian_mps(psi, n), eps, chi)
+    w = M.round_mps(M.hadamard(c2m, y), eps, chi)
+    nxt = M.round_mps(M.direct_sum([psi, psip, w], [2.0, -1.0, lam * lam]), eps, chi)
+    assert st.bonds(0, 3) == M.bonds_of(y)
+    assert rel(st.to_dense(0, 3).reshape(-1), M.to_dense(y)) < 1e-11
+    assert st.bonds(0, 4) == M.bonds_of(w)
+    assert rel(st.to_dense(0, 4).reshape(-1), M.to_dense(w)) < 1e-11
+    assert st.bonds(0, 0) == M.bonds_of(nxt)
+    assert rel(st.to_dense(0, 0).reshape(-1), M.to_dense(nxt)) < 1e-11
+    st.close()
+
+
+def _run_config(mpsw, name, steps, **over):
+    cfg = synth.get_config(name, steps=steps, **over)
+    n = cfg["n"]
+    st = make_state(mpsw, n, cfg["chi"], cfg["eps"], cfg["lam"])
+    st.set_velocity_dense(cfg["c2"], cfg["eps_c"])
+    st.set_source(0, cfg["ix"], cfg["iz"], cfg["wavelet_samples"])
+    return cfg, st
+
+
+def test_c1_trajectory_matches_oracle(mpsw):
+    cfg, st = _run_config(mpsw, "C1", 200)
+    n = cfg["n"]
+    c2r = st.to_dense(0, 2)
+    ds = S.DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], c2r, src=(cfg["ix"], cfg["iz"]),
+                        wavelet=cfg["wavelet_samples"])
+    a = b = np.zeros_like(c2r)
+    for k in range(200):
+        st.step(1)
+        ds.step()
+        a, b = b, F.fdtd_step(b, a, c2r, cfg["lam"], cfg["wavelet_samples"][k], (cfg["ix"], cfg["iz"]))
+        if (k + 1) % 50 == 0:
+            g = st.to_dense(0, 0)
+            _say("C1 step", k + 1, rel(g, ds.dense()), rel(g, b), st.bonds(0, 0))
+            assert rel(g, ds.dense()) < 1e-10
+            assert rel(g, b) < 1e-8
+    st.close()
+
+
+def test_c2_prefix_matches_oracle(mpsw):
+    steps = 40
+    cfg, st = _run_config(mpsw, "C2", steps)
+    n = cfg["n"]
+    c2r = st.to_dense(0, 2)
+    ds = S.DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], c2r, src=(cfg["ix"], cfg["iz"]),
+                        wavelet=cfg["wavelet_samples"])
+    for k in range(steps):
+        ds.step()
+    st.step(steps)
+    g = st.to_dense(0, 0)
+    _say("C2 prefix", rel(g, ds.dense()), st.bonds(0, 0))
+    assert rel(g, ds.dense()) < 1e-10
+    assert st.bonds(0, 0) == ds.ranks[-1][2]
+    st.close()
+
+
+def test_plane_wave_production_size(mpsw):
+    """n = 10 (the measured grid): a discrete plane wave stays rank 2 and follows
+    the closed-form dispersion relation."""
+    n, mx, mz, courant = 10, 17, 5, 0.5
+    N = 1 << n
+    st = make_state(mpsw, n, 8, 1e-10, courant)
+    st.set_velocity_dense(np.ones((N, N)), 1e-12)
+    up, u = synth.plane_wave_fields(n, mx, mz, courant, phase=0.2)
+    st.set_fields(0, up, u)
+    wdt = synth.fields.plane_wave_omega_dt(n, mx, mz, courant)
+    steps = 20
+    st.step(steps)
+    x = np.arange(N)[:, None]
+    z = np.arange(N)[None, :]
+    exact = np.cos(2 * np.pi * (mx * x + mz * z) / N + 0.2 - steps * wdt)
+    g = st.to_dense(0, 0)
+    _say("plane wave n=10", np.max(np.abs(g - exact)), max(st.bonds(0, 0)))
+    assert np.max(np.abs(g - exact)) < 1e-10
+    assert max(st.bonds(0, 0)) == 2
+    st.close()
+
+
+def test_batch_equals_single(mpsw):
+    n, eps, lam = 5, 1e-7, 0.5
+    N = 1 << n
+    c2 = synth.layered_fault_velocity(n, dh=40.0) * 1e-8
+    shots = [(3, 1, 16, 20.0), (20, 2, 8, 12.0), (11, 1, 32, 30.0)]
+    cfgs = [mpsw.make_config(n, chi, eps, lam) for (_, _, chi, _) in shots]
+    bt = mpsw.State(cfgs)
+    bt.set_velocity_dense(c2, 1e-8)
+    wavs = [synth.ricker(30, 0.004, f0) for (_, _, _, f0) in shots]
+    for i, (ix, iz, chi, f0) in enumerate(shots):
+        bt.set_source(i, ix, iz, wavs[i])
+    bt.step(30)
+    for i, (ix, iz, chi, f0) in enumerate(shots):
+        st = make_state(mpsw, n, chi, eps, lam)
+        st.set_velocity_dense(c2, 1e-8)
+        st.set_source(0, ix, iz, wavs[i])
+        st.step(30)
+        assert rel(bt.to_dense(i, 0), st.to_dense(0, 0)) < 1e-13
+        assert bt.bonds(i, 0) == st.bonds(0, 0)
+        st.close()
+    bt.close()
+
+
+def test_error_paths(mpsw):
+    n = 3
+    st = make_state(mpsw, n, 4, 1e-8, 0.1)
+    with pytest.raises(mpsw.MpswError) as ei:
+        st.step(1)
+    assert ei.value.name == "ESTATE"
+    with pytest.raises(mpsw.MpswError) as ei:
+        st.set_velocity_dense(np.full((8, 8), 100.0), 1e-8)   # lambda^2 c^2 2 = 2 > 1
+    assert ei.value.name == "ECFL"
+    with pytest.raises(mpsw.MpswError) as ei:
+        st.set_velocity_dense(np.full((8, 8), -1.0), 1e-8)
+    assert ei.value.name == "EINVAL"
+    with pytest.raises(mpsw.MpswError):
+        st.set_source(0, 8, 0, np.ones(3))
+    st.close()
