@@ -143,6 +143,16 @@ const char* mpsw_last_error(void);
  * Returns the total number of core entries (>= 0) or a negative error code. */
 int mpsw_debug_laplacian_mpo(int n, int boundary, int* bonds, double* cores, int64_t cap);
 
+/* Test helper (device work on the current device, default stream): runs the
+ * factorisation kernels of a rounding on one host matrix A (m x n row-major).
+ * op 0: QR (m even); out1 receives Q (m x q, row-major), out2 R (q x n), where
+ *       q = n for a tall A and q = m (Q = I, R = A) otherwise.
+ * op 1: SVD without truncation (n even); out1 receives V^T (r x n), out2
+ *       U Sigma (m x r), r = min(m, n), columns ordered by decreasing sigma.
+ * Buffers are caller-owned host memory of at least m*n and max(m,n)^2 doubles.
+ * Returns q (op 0) or r (op 1), or a negative error code. */
+int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, double* out2);
+
 #ifdef __cplusplus
 }
 #endif

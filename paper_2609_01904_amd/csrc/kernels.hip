@@ -6,42 +6,11 @@
 // whose tile or batch entry lies beyond the live shape return immediately.
 // Every write is checked against the capacity of its buffer; an overflow sets
 // an error bit instead of writing.
-#include "mpsw_kernels.h"
+#include "mpsw_device.h"
 
 #include <math.h>
 
 namespace mpsw {
-
-using DL = ShotDimsLayout;
-using RL = ShotRealLayout;
-
-__device__ __forceinline__ int* shot_dims(const DevCtx& c, int shot) { return c.dims + (int64_t)shot * DL::size; }
-__device__ __forceinline__ double* shot_reals(const DevCtx& c, int shot) { return c.reals + (int64_t)shot * RL::size; }
-__device__ __forceinline__ double* shot_eng(const DevCtx& c, int shot) { return c.eng + (int64_t)shot * c.L.stride; }
-__device__ __forceinline__ double* shot_mps(const DevCtx& c, int shot) { return c.mps + (int64_t)shot * c.mps_stride; }
-__device__ __forceinline__ void raise_err(const DevCtx& c, int bit) { atomicOr(c.err, bit); }
-
-// ---------------------------------------------------------------------------
-// Reductions
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// block-wide sum for 256 threads; `red` has >= 4 doubles of LDS
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  const int nw = blockDim.x >> 6;
-  for (int i = 0; i < nw; ++i) s += red[i];
-  return s;
-}
 
 // ---------------------------------------------------------------------------
 // GEMM planning: one descriptor per (shot, batch entry)
@@ -162,18 +131,13 @@ __device__ bool plan_gemm(const DevCtx& c, const OpArgs& a, int shot, int z, int
       if ((int64_t)2 * ck * D1 * q > L.cap_T1) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
       break;
     }
-    case G_ABSORB: {  // M_{k-1} (2rt_{k-1} x rho_k) = Q_{k-1} (2rt_{k-1} x rt_k) * US (rt_k x rho_k)
-      const int rtp = dm[DL::rt + k - 1], rtk = dm[DL::rt + k], rk = dm[DL::rho + k];
-      d.M = 2 * rtp; d.K = rtk; d.N = rk;
-      d.B = E + L.off_US; d.brs = rk; d.bcs = 1;
-      d.C = E + L.off_M; d.crs = rk; d.capC = L.cap_M;
-      if (dm[DL::qid + k - 1]) {
-        d.copy = 1;   // rt_k = 2 rt_{k-1}: same memory shape
-      } else {
-        d.A = E + L.off_q[k - 1]; d.ars = rtk; d.acs = 1;
-        if ((int64_t)2 * rtp * rtk > L.cap_q[k - 1]) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
-      }
-      if ((int64_t)rtk * rk > L.cap_US) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+    case G_US: {  // U_r Sigma_r (rt_k x rho_k) = M_k (rt_k x 2rho_{k+1}) * core_k^T
+      const int m = dm[DL::rt + k], nn = 2 * dm[DL::rho + k + 1], r = dm[DL::rho + k];
+      d.M = m; d.K = nn; d.N = r;
+      d.A = E + L.off_M; d.ars = nn; d.acs = 1;
+      d.B = mps_core(c, shot, a.slot, k); d.brs = 1; d.bcs = nn;
+      d.C = E + L.off_US; d.crs = r; d.capC = L.cap_US;
+      if ((int64_t)m * nn > L.cap_M || (int64_t)r * nn > c.cap_mps[a.slot][k]) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
       break;
     }
     case G_DENSE: {  // V_{k+1} (2^k x 2 r_{k+1}) = V_k (2^k x r_k) * G_k (r_k x 2 r_{k+1})
@@ -414,268 +378,6 @@ __global__ void k_pack_sum(const DevCtx* __restrict__ cp, OpArgs a) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// Householder QR of the (2 rt_k x rin_{k+1}) unfolding, or the identity merge
-// when the unfolding is not tall (its thin QR has a square Q; the identity is
-// such a Q, so R = X and the bond becomes 2 rt_k).
-// One workgroup (256 threads) per shot.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_qr(const DevCtx* __restrict__ cp, OpArgs a) {
-  const DevCtx& c = *cp;
-  const int shot = blockIdx.z, k = a.site;
-  int* dm = shot_dims(c, shot);
-  const EngineLayout& L = c.L;
-  double* E = shot_eng(c, shot);
-  const int rt = dm[DL::rt + k];
-  const int nc = dm[DL::rin + k + 1];
-  const int mr = 2 * rt;
-  const double* X = E + (a.aux ? L.off_X2 : L.off_X);
-  const int64_t capX = a.aux ? L.cap_X2 : L.cap_X;
-  double* R = E + L.off_R;
-  __shared__ double red[8];
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  if ((int64_t)mr * nc > capX) { if (threadIdx.x == 0) raise_err(c, MPSW_DEV_ERR_CAP); return; }
-  if (mr <= nc) {
-    if ((int64_t)mr * nc > L.cap_R) { if (threadIdx.x == 0) raise_err(c, MPSW_DEV_ERR_CAP); return; }
-    for (int64_t e = threadIdx.x; e < (int64_t)mr * nc; e += blockDim.x) R[e] = X[e];
-    if (threadIdx.x == 0) { dm[DL::rt + k + 1] = mr; dm[DL::qid + k] = 1; }
-    return;
-  }
-  if ((int64_t)mr * nc > L.cap_q[k] || (int64_t)nc * nc > L.cap_R || (int64_t)mr * nc > L.cap_qrS || nc > L.cap_qrT) {
-    if (threadIdx.x == 0) raise_err(c, MPSW_DEV_ERR_CAP);
-    return;
-  }
-  double* S = E + L.off_qrS;   // column-major mr x nc
-  double* tau = E + L.off_qrT;
-  for (int64_t e = threadIdx.x; e < (int64_t)mr * nc; e += blockDim.x) {
-    const int i = (int)(e / nc), j = (int)(e % nc);
-    S[(int64_t)j * mr + i] = X[e];
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int j = 0; j < nc; ++j) {
-    double* v = S + (int64_t)j * mr;
-    double s2 = 0.0;
-    for (int i = j + 1 + threadIdx.x; i < mr; i += blockDim.x) s2 += v[i] * v[i];
-    s2 = block_sum(s2, red);
-    const double x0 = v[j];
-    double t = 0.0, beta = x0, scale = 0.0;
-    if (s2 > 0.0) {
-      beta = -copysign(sqrt(x0 * x0 + s2), x0);
-      t = (beta - x0) / beta;
-      scale = 1.0 / (x0 - beta);
-    }
-    __syncthreads();
-    if (s2 > 0.0)
-      for (int i = j + 1 + threadIdx.x; i < mr; i += blockDim.x) v[i] *= scale;
-    if (threadIdx.x == 0) { v[j] = beta; tau[j] = t; }
-    __syncthreads();
-    if (t != 0.0) {
-      for (int col = j + 1 + w; col < nc; col += nw) {
-        double* u = S + (int64_t)col * mr;
-        double dot = 0.0;
-        for (int i = j + 1 + lane; i < mr; i += 64) dot += v[i] * u[i];
-        dot = wave_sum(dot) + u[j];
-        dot *= t;
-        if (lane == 0) u[j] -= dot;
-        for (int i = j + 1 + lane; i < mr; i += 64) u[i] -= dot * v[i];
-      }
-    }
-    __syncthreads();
-  }
-  // R (nc x nc, row-major, upper triangular)
-  for (int64_t e = threadIdx.x; e < (int64_t)nc * nc; e += blockDim.x) {
-    const int i = (int)(e / nc), j = (int)(e % nc);
-    R[e] = (i <= j) ? S[(int64_t)j * mr + i] : 0.0;
-  }
-  // Q = H_0 ... H_{nc-1} [I; 0], formed in place of the Q slot (row-major mr x nc)
-  double* Q = E + L.off_q[k];
-  for (int64_t e = threadIdx.x; e < (int64_t)mr * nc; e += blockDim.x) {
-    const int i = (int)(e / nc), j = (int)(e % nc);
-    Q[e] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int j = nc - 1; j >= 0; --j) {
-    const double t = tau[j];
-    if (t == 0.0) continue;
-    const double* v = S + (int64_t)j * mr;
-    for (int col = j + w; col < nc; col += nw) {
-      double dot = 0.0;
-      for (int i = j + 1 + lane; i < mr; i += 64) dot += v[i] * Q[(int64_t)i * nc + col];
-      dot = wave_sum(dot) + Q[(int64_t)j * nc + col];
-      dot *= t;
-      if (lane == 0) Q[(int64_t)j * nc + col] -= dot;
-      for (int i = j + 1 + lane; i < mr; i += 64) Q[(int64_t)i * nc + col] -= dot * v[i];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) { dm[DL::rt + k + 1] = nc; dm[DL::qid + k] = 0; }
-  (void)bad;
-}
-
-// ---------------------------------------------------------------------------
-// Truncated SVD of the bond matrix M_k (rt_k x 2 rho_{k+1}) by one-sided
-// (Hestenes) Jacobi on the thinner orientation, one workgroup per shot.
-// Writes core k = V_r^T, U_r Sigma_r, rho_k; logs the leading singular values
-// and accumulates the discarded tail sum in FP64.
-// ---------------------------------------------------------------------------
-#define SVD_MAXC 4096
-
-__global__ __launch_bounds__(256) void k_svd(const DevCtx* __restrict__ cp, OpArgs a) {
-  const DevCtx& c = *cp;
-  const int shot = blockIdx.z, k = a.site;
-  int* dm = shot_dims(c, shot);
-  double* re = shot_reals(c, shot);
-  const EngineLayout& L = c.L;
-  double* E = shot_eng(c, shot);
-  const int m = dm[DL::rt + k];
-  const int n = 2 * dm[DL::rho + k + 1];
-  const bool tall = m >= n;
-  const int Ld = tall ? m : n;     // column length
-  const int cc = tall ? n : m;     // column count
-  __shared__ double sig[SVD_MAXC];
-  __shared__ int order[SVD_MAXC];
-  __shared__ int rotated;
-  __shared__ int rank_s;
-  if ((int64_t)m * n > L.cap_M || (int64_t)Ld * cc > L.cap_sA || (int64_t)cc * cc > L.cap_sJ || cc > SVD_MAXC) {
-    if (threadIdx.x == 0) raise_err(c, MPSW_DEV_ERR_CAP);
-    return;
-  }
-  const double* M = E + L.off_M;
-  double* A = E + L.off_sA;   // column-major Ld x cc
-  double* J = E + L.off_sJ;   // column-major cc x cc
-  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += blockDim.x) {
-    const int i = (int)(e / n), j = (int)(e % n);
-    if (tall) A[(int64_t)j * Ld + i] = M[e];
-    else A[(int64_t)i * Ld + j] = M[e];
-  }
-  for (int64_t e = threadIdx.x; e < (int64_t)cc * cc; e += blockDim.x) J[e] = ((e / cc) == (e % cc)) ? 1.0 : 0.0;
-  __syncthreads();
-
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int np = cc + (cc & 1);   // players in the round-robin (with a dummy if odd)
-  const double tol = 1e-15 * sqrt((double)Ld);
-  for (int sweep = 0; sweep < 60 && cc > 1; ++sweep) {
-    if (threadIdx.x == 0) rotated = 0;
-    __syncthreads();
-    for (int t = 0; t < np - 1; ++t) {
-      for (int pi = w; pi < np / 2; pi += nw) {
-        int p, q;
-        if (pi == 0) { p = t; q = np - 1; }
-        else { p = (t + pi) % (np - 1); q = (t - pi + (np - 1)) % (np - 1); }
-        if (p >= cc || q >= cc) continue;
-        double* ap = A + (int64_t)p * Ld;
-        double* aq = A + (int64_t)q * Ld;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = lane; i < Ld; i += 64) {
-          const double x = ap[i], y = aq[i];
-          al = fma(x, x, al);
-          be = fma(y, y, be);
-          ga = fma(x, y, ga);
-        }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        if (al == 0.0 || be == 0.0 || fabs(ga) <= tol * sqrt(al) * sqrt(be)) continue;
-        const double zeta = (be - al) / (2.0 * ga);
-        double tt;
-        if (fabs(zeta) > 1e100) tt = 0.5 / zeta;
-        else tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-        for (int i = lane; i < Ld; i += 64) {
-          const double x = ap[i], y = aq[i];
-          ap[i] = cs * x - sn * y;
-          aq[i] = sn * x + cs * y;
-        }
-        double* jp = J + (int64_t)p * cc;
-        double* jq = J + (int64_t)q * cc;
-        for (int i = lane; i < cc; i += 64) {
-          const double x = jp[i], y = jq[i];
-          jp[i] = cs * x - sn * y;
-          jq[i] = sn * x + cs * y;
-        }
-        if (lane == 0) rotated = 1;
-      }
-      __syncthreads();
-    }
-    if (!rotated) break;
-    __syncthreads();
-  }
-  // singular values and their descending order (ties by index)
-  for (int j = w; j < cc; j += nw) {
-    const double* aj = A + (int64_t)j * Ld;
-    double s = 0.0;
-    for (int i = lane; i < Ld; i += 64) s = fma(aj[i], aj[i], s);
-    s = wave_sum(s);
-    if (lane == 0) sig[j] = sqrt(s);
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j < cc; j += blockDim.x) {
-    const double sj = sig[j];
-    int r = 0;
-    for (int i = 0; i < cc; ++i) {
-      const double si = sig[i];
-      r += (si > sj) || (si == sj && i < j);
-    }
-    order[r] = j;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double s0 = sig[order[0]];
-    const double eps = re[RL::eps];
-    const int chi = dm[DL::chi];
-    int r = 0;
-    bool finite = true;
-    for (int t = 0; t < cc; ++t) {
-      const double s = sig[order[t]];
-      if (!(s == s) || isinf(s)) finite = false;
-      if (s0 > 0.0 && s >= eps * s0) ++r;
-    }
-    if (!finite) raise_err(c, MPSW_DEV_ERR_NONFINITE);
-    if (r > chi) r = chi;
-    if (r < 1) r = 1;
-    double tail = 0.0;
-    for (int t = r; t < cc; ++t) { const double s = sig[order[t]]; tail = fma(s, s, tail); }
-    if (a.aux >= 0 && a.aux < 3) {
-      re[RL::tail2 + a.aux] += tail;
-      double* lg = re + RL::sigma_log + (a.aux * MPSW_MAXK + k) * 32;
-      for (int t = 0; t < 32; ++t) lg[t] = (t < cc) ? sig[order[t]] : 0.0;
-      const int mb = cc;
-      if (mb > dm[DL::maxbond + a.aux]) dm[DL::maxbond + a.aux] = mb;
-    }
-    rank_s = r;
-  }
-  __syncthreads();
-  const int r = rank_s;
-  double* out = shot_mps(c, shot) + c.off_mps[a.slot][k];
-  double* US = E + L.off_US;
-  if ((int64_t)r * n > c.cap_mps[a.slot][k] || (int64_t)m * r > L.cap_US) {
-    if (threadIdx.x == 0) raise_err(c, MPSW_DEV_ERR_CAP);
-    return;
-  }
-  // core k = V_r^T (r x n)
-  for (int64_t e = threadIdx.x; e < (int64_t)r * n; e += blockDim.x) {
-    const int t = (int)(e / n), l = (int)(e % n);
-    const int j = order[t];
-    double v;
-    if (tall) v = J[(int64_t)j * cc + l];
-    else {
-      const double s = sig[j];
-      v = (s > 0.0) ? A[(int64_t)j * Ld + l] / s : ((l == t) ? 1.0 : 0.0);
-    }
-    out[e] = v;
-  }
-  // U_r Sigma_r (m x r)
-  for (int64_t e = threadIdx.x; e < (int64_t)m * r; e += blockDim.x) {
-    const int l = (int)(e / r), t = (int)(e % r);
-    const int j = order[t];
-    US[e] = tall ? A[(int64_t)j * Ld + l] : J[(int64_t)j * cc + l] * sig[j];
-  }
-  if (threadIdx.x == 0) dm[DL::rho + k] = r;
-}
-
 // Core 0 of the rounded state and its bonds.
 __global__ void k_finish(const DevCtx* __restrict__ cp, OpArgs a) {
   const DevCtx& c = *cp;
@@ -734,12 +436,6 @@ void launch_pack_lap(const DevCtx* d, const OpArgs& a, int K, int nshots, int bl
 }
 void launch_pack_sum(const DevCtx* d, const OpArgs& a, int K, int nshots, int blocks, hipStream_t s) {
   hipLaunchKernelGGL(k_pack_sum, dim3(blocks, K, nshots), dim3(256), 0, s, d, a);
-}
-void launch_qr(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s) {
-  hipLaunchKernelGGL(k_qr, dim3(1, 1, nshots), dim3(256), 0, s, d, a);
-}
-void launch_svd(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s) {
-  hipLaunchKernelGGL(k_svd, dim3(1, 1, nshots), dim3(256), 0, s, d, a);
 }
 void launch_finish(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s) {
   hipLaunchKernelGGL(k_finish, dim3(1, 1, nshots), dim3(256), 0, s, d, a);

@@ -20,6 +20,14 @@
 #define MPSW_DEV_ERR_CAP 1        // a live size exceeded a workspace capacity
 #define MPSW_DEV_ERR_NONFINITE 2  // a singular value was not finite
 #define MPSW_DEV_ERR_GRID 4       // a launch grid was smaller than the live work
+#define MPSW_DEV_ERR_TIMEOUT 8    // a bounded inter-workgroup wait gave up
+
+// Per-shot synchronisation area (ints) used by the multi-workgroup kernels.
+#define MPSW_SYNC_STRIDE 1024
+#define MPSW_SYNC_BARRIER 0       // barrier arrival counter
+#define MPSW_SYNC_ROT 8           // [64] rotations seen per Jacobi sweep
+#define MPSW_SYNC_FLAGS 128       // [<= 896] panel-ready flags of the QR factorisation
+#define MPSW_MAX_SWEEPS 60
 
 // Per-shot integer block layout (offsets in ints).
 struct ShotDimsLayout {
@@ -47,7 +55,8 @@ struct ShotRealLayout {
 // Capacities (doubles) and offsets of one engine's buffers inside a shot arena.
 struct EngineLayout {
   int64_t off_in[MPSW_MAXK], cap_in[MPSW_MAXK];   // explicit source cores
-  int64_t off_q[MPSW_MAXK], cap_q[MPSW_MAXK];     // Q cores of the QR sweep
+  int64_t off_q[MPSW_MAXK], cap_q[MPSW_MAXK];     // Householder vectors + R of the QR sweep
+  int64_t off_qt[MPSW_MAXK], cap_qt[MPSW_MAXK];   // compact-WY T factors per panel
   int64_t off_X, cap_X;     // X_k = R_{k-1} S_k
   int64_t off_X2, cap_X2;   // X after the meeting product (c^2 rounding)
   int64_t off_R, cap_R;     // R factor carried to the right
@@ -56,6 +65,10 @@ struct EngineLayout {
   int64_t off_M, cap_M;     // bond matrix of the SVD sweep
   int64_t off_US, cap_US;   // U_r Sigma_r
   int64_t off_sA, cap_sA;   // Jacobi working matrix
+  int64_t off_sA2, cap_sA2; // R1^T of a wide bond matrix
+  int64_t off_qrS2, cap_qrS2, off_qrT2, cap_qrT2;  // second QR of a wide bond matrix
+  int64_t off_Vp, cap_Vp;   // V'^T of a wide bond matrix
+  int64_t off_Yv, cap_Yv;   // V = Q1 [V'; 0] work
   int64_t off_sJ, cap_sJ;   // Jacobi accumulated rotations
   int64_t off_qrS, cap_qrS; // Householder working matrix
   int64_t off_qrT, cap_qrT; // Householder tau
@@ -90,6 +103,7 @@ struct DevCtx {
   double* dense;
   int64_t dense_stride;
   int* err;
+  int* sync;                                     // B * MPSW_SYNC_STRIDE
 };
 
 __host__ __device__ inline int64_t mpsw_pow2(int e) { return (int64_t)1 << e; }

@@ -13,8 +13,8 @@ enum GemmOp {
   G_MEET,              // product with the right-merged block at the middle site
   G_KRON_R1,           // Kronecker contraction, right-to-left, first GEMM
   G_KRON_R2,           // ... second GEMM
-  G_ABSORB,            // M_{k-1} = Q_{k-1} U_r Sigma_r
-  G_DENSE              // dense contraction step V_{k+1} = V_k G_k
+  G_DENSE,             // dense contraction step V_{k+1} = V_k G_k
+  G_US                 // U_r Sigma_r = M_k V_r
 };
 
 // Rounding input kinds (k_prepare / k_init_R).
@@ -36,8 +36,13 @@ void launch_prepare(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s)
 void launch_init_R(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
 void launch_pack_lap(const DevCtx* d, const OpArgs& a, int K, int nshots, int blocks, hipStream_t s);
 void launch_pack_sum(const DevCtx* d, const OpArgs& a, int K, int nshots, int blocks, hipStream_t s);
-void launch_qr(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
-void launch_svd(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
+void launch_sync_reset(const DevCtx* d, int nshots, hipStream_t s);
+void launch_qrf(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, size_t lds, hipStream_t s);
+void launch_applyq(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, hipStream_t s);
+void launch_applyv(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, hipStream_t s);
+void launch_jac(const DevCtx* d, const OpArgs& a, int b, int nwg, int nshots, size_t lds, hipStream_t s);
+void launch_jacfin(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
+void set_lds_limits(size_t bytes);
 void launch_finish(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
 void launch_dense_init(const DevCtx* d, int nshots, hipStream_t s);
 void launch_zero_state(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);

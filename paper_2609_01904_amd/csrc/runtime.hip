@@ -192,17 +192,16 @@ void layout_engine(const Plan& p, EngineLayout& L) {
   const int K = p.K, n = p.n;
   std::memset(&L, 0, sizeof(L));
   int64_t capX = 1, capX2 = 1, capR = 1, capT1 = 1, capB = 1, capM = 2, capUS = 1, capSA = 2, capSJ = 1,
-          capQRS = 1, capQRT = 1;
-  std::vector<int64_t> capIn(K, 1), capQ(K, 1);
+          capQRS = 1, capQRT = 1, capSA2 = 1, capQRS2 = 1, capQRT2 = 1, capVp = 1, capYv = 1;
+  std::vector<int64_t> capIn(K, 1), capQ(K, 1), capQT(K, 1);
   int maxdim = 1;
   for (const auto& s : p.sw) {
     for (int k = 0; k < K; ++k) {
       if (s.explicit_in) capIn[k] = std::max(capIn[k], s.rin[k] * 2 * s.rin[k + 1]);
       if (k <= K - 2) {
-        capQ[k] = std::max(capQ[k], 2 * s.rt[k] * s.rt[k + 1]);
+        capQ[k] = std::max(capQ[k], 2 * s.rt[k] * s.rin[k + 1]);
+        capQT[k] = std::max(capQT[k], (s.rin[k + 1] + 16) * 16);
         capX = std::max(capX, 2 * s.rt[k] * s.rin[k + 1]);
-        capQRS = std::max(capQRS, 2 * s.rt[k] * s.rin[k + 1]);
-        capQRT = std::max(capQRT, s.rin[k + 1]);
         capR = std::max(capR, s.rt[k + 1] * s.rin[k + 1]);
       }
       capR = std::max(capR, s.rt[k] * s.rin[k]);
@@ -210,8 +209,14 @@ void layout_engine(const Plan& p, EngineLayout& L) {
         capM = std::max(capM, s.rt[k] * 2 * s.rho[k + 1]);
         capUS = std::max(capUS, s.rt[k] * s.rho[k]);
         capSA = std::max(capSA, s.rt[k] * 2 * s.rho[k + 1]);
+        capQRS = std::max(capQRS, s.rt[k] * 2 * s.rho[k + 1]);
+        capQRT = std::max(capQRT, (2 * s.rho[k + 1] + 16) * 16);
         const int64_t cc = std::min(s.rt[k], 2 * s.rho[k + 1]);
-        capSJ = std::max(capSJ, cc * cc);
+        capSA2 = std::max(capSA2, cc * cc);
+        capQRS2 = std::max(capQRS2, cc * cc);
+        capQRT2 = std::max(capQRT2, (cc + 16) * 16);
+        capVp = std::max(capVp, s.rho[k] * cc);
+        capYv = std::max(capYv, 2 * s.rho[k + 1] * s.rho[k]);
         maxdim = (int)std::max<int64_t>(maxdim, std::max(s.rt[k], 2 * s.rho[k + 1]));
       }
       capM = std::max(capM, 2 * s.rho[1]);
@@ -228,11 +233,11 @@ void layout_engine(const Plan& p, EngineLayout& L) {
     capX = std::max(capX, 2 * s.rt[n - 1] * p.Rmax[n] * p.D[n]);
     for (int k = 0; k < n; ++k) capX = std::max(capX, 2 * s.rt[k] * p.Rmax[k + 1] * p.D[k + 1]);
     capX2 = 2 * s.rt[n - 1] * p2(K - n);
-    capQRS = std::max(capQRS, capX2);
   }
   int64_t off = 0;
   for (int k = 0; k < K; ++k) { L.cap_in[k] = capIn[k]; add64(off, L.off_in[k], capIn[k]); }
   for (int k = 0; k < K; ++k) { L.cap_q[k] = capQ[k]; add64(off, L.off_q[k], capQ[k]); }
+  for (int k = 0; k < K; ++k) { L.cap_qt[k] = capQT[k]; add64(off, L.off_qt[k], capQT[k]); }
   L.cap_X = capX; add64(off, L.off_X, capX);
   L.cap_X2 = capX2; add64(off, L.off_X2, capX2);
   L.cap_R = capR; add64(off, L.off_R, capR);
@@ -242,6 +247,11 @@ void layout_engine(const Plan& p, EngineLayout& L) {
   L.cap_US = capUS; add64(off, L.off_US, capUS);
   L.cap_sA = capSA; add64(off, L.off_sA, capSA);
   L.cap_sJ = capSJ; add64(off, L.off_sJ, capSJ);
+  L.cap_sA2 = capSA2; add64(off, L.off_sA2, capSA2);
+  L.cap_qrS2 = capQRS2; add64(off, L.off_qrS2, capQRS2);
+  L.cap_qrT2 = capQRT2; add64(off, L.off_qrT2, capQRT2);
+  L.cap_Vp = capVp; add64(off, L.off_Vp, capVp);
+  L.cap_Yv = capYv; add64(off, L.off_Yv, capYv);
   L.cap_qrS = capQRS; add64(off, L.off_qrS, capQRS);
   L.cap_qrT = capQRT; add64(off, L.off_qrT, capQRT);
   L.stride = off;
@@ -284,6 +294,7 @@ struct mpsw_state_s {
   double* wavelet = nullptr;
   double* dense = nullptr;
   int* err = nullptr;
+  int* sync = nullptr;
   std::vector<int> c2b;
   int nt_max = 0;
   std::vector<std::vector<double>> wavelets;
@@ -345,6 +356,7 @@ void fill_ctx(mpsw_state st, DevCtx& h, double* eng, const EngineLayout& L) {
   h.dense = st->dense;
   h.dense_stride = 2 * p2(st->K);
   h.err = st->err;
+  h.sync = st->sync;
 }
 
 int upload_ctx(Engine& e, hipStream_t s) {
@@ -356,10 +368,56 @@ int upload_ctx(Engine& e, hipStream_t s) {
 
 int tiles(int64_t M, int64_t N) { return std::max(1, cdiv(M, 64) * cdiv(N, 64)); }
 
+size_t g_lds_limit = 0;   // bytes of LDS a workgroup may allocate on this device
+
+size_t lds_limit() {
+  if (g_lds_limit == 0) {
+    int dev = 0, v = 0;
+    hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) v = 65536;
+    g_lds_limit = (size_t)v;
+    set_lds_limits(g_lds_limit);
+    (void)hipGetLastError();   // the attribute is advisory on this platform; clear any status it left
+  }
+  return g_lds_limit;
+}
+
+// Householder panel width for a QR whose row count is at most mcap: the panel
+// (mcap x bw doubles) lives in LDS.
+int qr_panel(int64_t mcap) {
+  const size_t lim = lds_limit() - 8192;   // static LDS of the kernel
+  for (int bw = 16; bw >= 4; bw >>= 1)
+    if ((size_t)mcap * bw * 8 <= lim) return bw;
+  return 0;
+}
+
+// Jacobi block width for columns of length at most lcap: a block pair
+// (2 bw columns of lcap+1 doubles) lives in LDS.
+int jac_block(int64_t lcap) {
+  const size_t lim = lds_limit() - 1024;   // static LDS of the kernel
+  for (int b = 16; b >= 1; b >>= 1)
+    if ((size_t)2 * b * (lcap + 1) * 8 <= lim) return b;
+  return 0;
+}
+
 // ---------------------------------------------------------------------------
 // Rounding launch sequences
 // ---------------------------------------------------------------------------
 enum Kind { K_LAPLACE = 0, K_C2 = 1, K_SUM = 2, K_DENSE = 3 };
+
+// Every factorisation of a rounding with these capacities fits the LDS of
+// one workgroup (panel of the QR, block pair of the Jacobi sweep).
+int check_fits(const SweepCaps& s, int K) {
+  for (int k = 0; k + 1 < K; ++k)
+    if (qr_panel(2 * s.rt[k]) == 0) return fail(MPSW_ENOMEM, "QR panel exceeds the LDS of a workgroup");
+  for (int k = K - 1; k >= 1; --k) {
+    if (qr_panel(std::max(s.rt[k], 2 * s.rho[k + 1])) == 0 || qr_panel(std::min(s.rt[k], 2 * s.rho[k + 1])) == 0)
+      return fail(MPSW_ENOMEM, "QR panel exceeds the LDS of a workgroup");
+    if (jac_block(std::min(s.rt[k], 2 * s.rho[k + 1])) == 0)
+      return fail(MPSW_ENOMEM, "Jacobi block exceeds the LDS of a workgroup");
+  }
+  return MPSW_OK;
+}
 
 // L->R sweep then R->L sweep for one rounding; output into MPS slot out_slot.
 void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int out_slot, int log_idx,
@@ -428,25 +486,51 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
       launch_gemm(d, g, tiles(s.rt[k], s.rin[k]), 1, nshots, strm);
     }
     if (!last) {
+      const int64_t mcap = 2 * s.rt[k], ncap = s.rin[k + 1];
+      const int bw = qr_panel(mcap);
+      const int nwg = (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(ncap, bw)));
       OpArgs q{};
       q.shot = -1;
       q.site = k;
+      q.op = 0;
       q.aux = meet ? 1 : 0;
-      launch_qr(d, q, nshots, strm);
+      launch_sync_reset(d, nshots, strm);
+      launch_qrf(d, q, bw, nwg, nshots, (size_t)mcap * bw * 8, strm);
     }
   }
   for (int k = K - 1; k >= 1; --k) {
+    const int64_t rows = std::max(s.rt[k], 2 * s.rho[k + 1]);   // rows of the factored orientation
+    const int64_t ccap = std::min(s.rt[k], 2 * s.rho[k + 1]);
     OpArgs v{};
     v.shot = -1;
     v.site = k;
     v.slot = out_slot;
     v.aux = log_idx;
-    launch_svd(d, v, nshots, strm);
+    launch_sync_reset(d, nshots, strm);
+    const int bw1 = qr_panel(rows), bw2 = qr_panel(ccap);
+    OpArgs q = v;
+    q.op = 1;
+    launch_qrf(d, q, bw1, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(ccap, bw1))), nshots,
+               (size_t)rows * bw1 * 8, strm);
+    q.op = 2;
+    launch_qrf(d, q, bw2, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(ccap, bw2))), nshots,
+               (size_t)ccap * bw2 * 8, strm);
+    const int b = jac_block(ccap);
+    const int64_t nb = cdiv(ccap, b);
+    launch_jac(d, v, b, (int)std::max<int64_t>(1, (nb + (nb & 1)) / 2), nshots, (size_t)2 * b * (ccap + 1) * 8, strm);
+    launch_jacfin(d, v, nshots, strm);
+    launch_applyv(d, v, bw1, std::max(1, cdiv(s.rho[k], bw1)), nshots, strm);
     OpArgs g{};
     g.shot = -1;
     g.site = k;
-    g.op = G_ABSORB;
-    launch_gemm(d, g, tiles(2 * s.rt[k - 1], s.rho[k]), 1, nshots, strm);
+    g.slot = out_slot;
+    g.op = G_US;
+    launch_gemm(d, g, tiles(s.rt[k], s.rho[k]), 1, nshots, strm);
+    OpArgs ap{};
+    ap.shot = -1;
+    ap.site = k;
+    const int bwq = qr_panel(2 * s.rt[k - 1]);
+    launch_applyq(d, ap, bwq, std::max(1, cdiv(s.rho[k], bwq)), nshots, strm);
   }
   OpArgs f{};
   f.shot = -1;
@@ -519,6 +603,7 @@ int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t ch
   h.dense = dense;
   h.dense_stride = 2 * N;
   h.err = st->err;
+  h.sync = st->sync;
   std::vector<int> hd(DL::size, 0);
   hd[DL::chi] = (int)std::min<int64_t>(chi, 1 << 30);
   std::vector<double> hr(RL::size, 0.0);
@@ -531,9 +616,18 @@ int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t ch
     return fail(MPSW_EHIP, "dense_to_mps: upload failed");
   }
   if ((rc = upload_ctx(e, s0)) != MPSW_OK) { cleanup(); return rc; }
+  if ((rc = check_fits(s, K)) != MPSW_OK) { cleanup(); hipFree(e.d); return rc; }
   // swap in the temporary engine: run_rounding uses st only for K/n/c2b/Rmax
   run_rounding(st, e, K_DENSE, s, 0, -1, 0, 0, 0, 1, s0);
-  if (hipGetLastError() != hipSuccess) { cleanup(); hipFree(e.d); return fail(MPSW_EHIP, "dense_to_mps: launch failed"); }
+  {
+    const hipError_t le = hipGetLastError();
+    if (le != hipSuccess) {
+      cleanup();
+      hipFree(e.d);
+      return fail(MPSW_EHIP, std::string("dense_to_mps: launch failed: ") + hipGetErrorString(le) +
+                                 " (LDS limit " + std::to_string(lds_limit()) + ")");
+    }
+  }
   if ((rc = check_dev_err(st)) != MPSW_OK) { cleanup(); hipFree(e.d); return rc; }
   // bonds of the result
   std::vector<int> dd(DL::size);
@@ -585,6 +679,10 @@ int build_step_engine(mpsw_state st) {
   e.sw = {sweep_caps(r1, K, st->chi_cap), sweep_caps(r3, K, st->chi_cap), sweep_caps(r2, K, st->chi_cap)};
   e.sw[0].explicit_in = true;
   e.sw[1].explicit_in = true;
+  for (auto& s : e.sw) {
+    const int rc = check_fits(s, K);
+    if (rc != MPSW_OK) return rc;
+  }
   e.plan.K = K;
   e.plan.n = n;
   e.plan.sw = e.sw;
@@ -654,6 +752,7 @@ int create_group(const mpsw_config* cfgs, int nshots, void* stream, mpsw_state* 
       hipMalloc(&st->dims, (size_t)DL::size * nshots * sizeof(int)) != hipSuccess ||
       hipMalloc(&st->reals, (size_t)RL::size * nshots * sizeof(double)) != hipSuccess ||
       hipMalloc(&st->err, sizeof(int)) != hipSuccess ||
+      hipMalloc(&st->sync, (size_t)MPSW_SYNC_STRIDE * nshots * sizeof(int)) != hipSuccess ||
       hipMalloc(&st->dense, (size_t)2 * p2(K) * sizeof(double)) != hipSuccess)
     return bail(fail(MPSW_ENOMEM, "state allocation failed"));
   if ((rc = upload_lap(st)) != MPSW_OK) return bail(rc);
@@ -756,6 +855,7 @@ int mpsw_destroy(mpsw_state st) {
   hipFree(st->wavelet);
   hipFree(st->dense);
   hipFree(st->err);
+  hipFree(st->sync);
   hipFree(st->eng.eng);
   hipFree(st->eng.d);
   delete st;
@@ -943,6 +1043,151 @@ int mpsw_get_stats(mpsw_state st, int shot, mpsw_stats* out) {
   }
   out->fallbacks = 0;
   return MPSW_OK;
+}
+
+// Test hook: run the factorisation kernels of a rounding on one matrix.
+//   op 0: QR of A (m x n, m even): Q (m x q) into out1, R (q x n) into out2, q = min(m, n)
+//         (the identity merge when m <= n: Q = I, R = A);
+//   op 1: SVD of A (m x n, n even): out1 = V^T (r x n), out2 = U Sigma (m x r),
+//         r = min(m, n) (no truncation); returns r.
+int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, double* out2) {
+  if (!A || !out1 || !out2 || m < 1 || n < 1 || m > 4096 || n > 4096) return fail(MPSW_EINVAL, "bad argument");
+  if (op == 0 && (m & 1)) return fail(MPSW_EINVAL, "QR test needs an even row count");
+  if (op == 1 && (n & 1)) return fail(MPSW_EINVAL, "SVD test needs an even column count");
+  if (op != 0 && op != 1) return fail(MPSW_EINVAL, "op must be 0 or 1");
+  const int K = 4;
+  // capacities: one rounding whose site 0 (QR) / site 1 (SVD) sees the matrix
+  SweepCaps s;
+  s.rin.assign(K + 1, 1);
+  s.rt.assign(K + 1, 1);
+  s.rho.assign(K + 1, 1);
+  const int64_t q = std::min(m, n);
+  if (op == 0) {
+    s.rt[0] = m / 2; s.rin[1] = n; s.rt[1] = std::max<int64_t>(q, m / 2); s.rho[1] = n;
+  } else {
+    s.rt[1] = m; s.rho[2] = n / 2; s.rho[1] = q; s.rt[0] = std::max<int64_t>(1, m / 2);
+  }
+  Plan p;
+  p.K = K;
+  p.n = 2;
+  p.sw = {s};
+  EngineLayout L;
+  layout_engine(p, L);
+  L.cap_X = std::max<int64_t>(L.cap_X, (int64_t)m * n);
+  L.cap_M = std::max<int64_t>(L.cap_M, (int64_t)m * std::max(n, m));
+  L.cap_R = std::max<int64_t>(L.cap_R, (int64_t)m * n);
+  L.cap_US = std::max<int64_t>(L.cap_US, (int64_t)m * std::max(n, m));
+  L.cap_sA = std::max<int64_t>(L.cap_sA, (int64_t)m * n);
+  L.cap_qrS = std::max<int64_t>(L.cap_qrS, (int64_t)m * n);
+  L.cap_qrT = std::max<int64_t>(L.cap_qrT, (int64_t)(std::max(m, n) + 16) * 16);
+  L.cap_sA2 = std::max<int64_t>(L.cap_sA2, q * q);
+  L.cap_qrS2 = std::max<int64_t>(L.cap_qrS2, q * q);
+  L.cap_qrT2 = std::max<int64_t>(L.cap_qrT2, (q + 16) * 16);
+  L.cap_Vp = std::max<int64_t>(L.cap_Vp, q * q);
+  L.cap_Yv = std::max<int64_t>(L.cap_Yv, (int64_t)std::max(m, n) * q);
+  L.cap_q[0] = std::max<int64_t>(L.cap_q[0], (int64_t)m * n);
+  L.cap_qt[0] = std::max<int64_t>(L.cap_qt[0], (int64_t)(n + 16) * 16);
+  int64_t off = 0;
+  auto place = [&](int64_t& o, int64_t cap) { o = off; off += (cap + 31) & ~(int64_t)31; };
+  for (int k = 0; k < K; ++k) { place(L.off_in[k], L.cap_in[k]); place(L.off_q[k], L.cap_q[k]); place(L.off_qt[k], L.cap_qt[k]); }
+  place(L.off_X, L.cap_X); place(L.off_X2, L.cap_X2); place(L.off_R, L.cap_R); place(L.off_T1, L.cap_T1);
+  place(L.off_B0, L.cap_B); place(L.off_B1, L.cap_B); place(L.off_M, L.cap_M); place(L.off_US, L.cap_US);
+  place(L.off_sA, L.cap_sA); place(L.off_sJ, L.cap_sJ); place(L.off_qrS, L.cap_qrS); place(L.off_qrT, L.cap_qrT);
+  place(L.off_sA2, L.cap_sA2); place(L.off_qrS2, L.cap_qrS2); place(L.off_qrT2, L.cap_qrT2);
+  place(L.off_Vp, L.cap_Vp); place(L.off_Yv, L.cap_Yv);
+  L.stride = off;
+  const int64_t core_cap = (int64_t)q * n + 2;
+  double *eng = nullptr, *mps = nullptr, *reals = nullptr;
+  int *dims = nullptr, *err = nullptr, *sync = nullptr;
+  auto cleanup = [&]() { hipFree(eng); hipFree(mps); hipFree(reals); hipFree(dims); hipFree(err); hipFree(sync); };
+  if (hipMalloc(&eng, L.stride * 8) || hipMalloc(&mps, core_cap * 8) || hipMalloc(&reals, RL::size * 8) ||
+      hipMalloc(&dims, DL::size * 4) || hipMalloc(&err, 4) || hipMalloc(&sync, MPSW_SYNC_STRIDE * 4)) {
+    cleanup();
+    return fail(MPSW_ENOMEM, "debug_factor: allocation failed");
+  }
+  Engine e;
+  DevCtx& h = e.h;
+  std::memset(&h, 0, sizeof(h));
+  h.K = K; h.n = 2; h.B = 1;
+  h.mps = mps; h.mps_stride = core_cap;
+  for (int k = 0; k < K; ++k) { h.off_mps[0][k] = 0; h.cap_mps[0][k] = core_cap; }
+  h.dims = dims; h.reals = reals; h.eng = eng; h.L = L; h.err = err; h.sync = sync;
+  for (int k = 0; k <= K; ++k) { h.c2b[k] = 1; h.wb[k] = 1; }
+  std::vector<int> hd(DL::size, 0);
+  std::vector<double> hr(RL::size, 0.0);
+  hd[DL::chi] = 1 << 30;
+  hr[RL::eps] = 0.0;
+  if (op == 0) { hd[DL::rt + 0] = m / 2; hd[DL::rin + 1] = n; }
+  else { hd[DL::rt + 1] = m; hd[DL::rho + 2] = n / 2; }
+  hipMemcpy(dims, hd.data(), DL::size * 4, hipMemcpyHostToDevice);
+  hipMemcpy(reals, hr.data(), RL::size * 8, hipMemcpyHostToDevice);
+  hipMemset(err, 0, 4);
+  hipMemcpy(eng + (op == 0 ? L.off_X : L.off_M), A, (size_t)m * n * 8, hipMemcpyHostToDevice);
+  int rc = upload_ctx(e, nullptr);
+  if (rc != MPSW_OK) { cleanup(); return rc; }
+  hipStream_t s0 = nullptr;
+  int ret = 0;
+  if (op == 0) {
+    const int bw = qr_panel(m);
+    if (bw == 0) { cleanup(); hipFree(e.d); return fail(MPSW_ENOMEM, "matrix too tall for LDS"); }
+    OpArgs a{};
+    a.shot = -1; a.site = 0; a.op = 0;
+    launch_sync_reset(e.d, 1, s0);
+    launch_qrf(e.d, a, bw, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(n, bw))), 1, (size_t)m * bw * 8, s0);
+    // Q = Q_0 [I_q; 0] through the absorb kernel: US = I (q x q), rho_1 = q
+    std::vector<int> d1(DL::size);
+    hipMemcpy(d1.data(), dims, DL::size * 4, hipMemcpyDeviceToHost);
+    const int rt1 = d1[DL::rt + 1];
+    std::vector<double> I((size_t)rt1 * rt1, 0.0);
+    for (int i = 0; i < rt1; ++i) I[(size_t)i * rt1 + i] = 1.0;
+    hipMemcpy(eng + L.off_US, I.data(), I.size() * 8, hipMemcpyHostToDevice);
+    d1[DL::rho + 1] = rt1;
+    hipMemcpy(dims, d1.data(), DL::size * 4, hipMemcpyHostToDevice);
+    OpArgs ap{};
+    ap.shot = -1; ap.site = 1;
+    launch_applyq(e.d, ap, bw, std::max(1, cdiv(rt1, bw)), 1, s0);
+    hipDeviceSynchronize();
+    hipMemcpy(out1, eng + L.off_M, (size_t)m * rt1 * 8, hipMemcpyDeviceToHost);
+    hipMemcpy(out2, eng + L.off_R, (size_t)rt1 * n * 8, hipMemcpyDeviceToHost);
+    ret = rt1;
+  } else {
+    OpArgs v{};
+    v.shot = -1; v.site = 1; v.slot = 0; v.aux = -1;
+    launch_sync_reset(e.d, 1, s0);
+    const int rows = std::max(m, n);
+    const int bw = qr_panel(rows);
+    if (bw == 0) { cleanup(); hipFree(e.d); return fail(MPSW_ENOMEM, "matrix too tall for LDS"); }
+    OpArgs qa = v;
+    qa.op = 1;
+    launch_qrf(e.d, qa, bw, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(q, bw))), 1, (size_t)rows * bw * 8, s0);
+    const int bw2 = qr_panel(q);
+    qa.op = 2;
+    launch_qrf(e.d, qa, bw2, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(q, bw2))), 1, (size_t)q * bw2 * 8, s0);
+    const int b = jac_block(q);
+    if (b == 0) { cleanup(); hipFree(e.d); return fail(MPSW_ENOMEM, "columns too long for LDS"); }
+    const int64_t nb = cdiv(q, b);
+    launch_jac(e.d, v, b, (int)std::max<int64_t>(1, (nb + (nb & 1)) / 2), 1, (size_t)2 * b * (q + 1) * 8, s0);
+    launch_jacfin(e.d, v, 1, s0);
+    launch_applyv(e.d, v, bw, std::max<int>(1, cdiv(q, bw)), 1, s0);
+    OpArgs g{};
+    g.shot = -1; g.site = 1; g.slot = 0; g.op = G_US;
+    launch_gemm(e.d, g, tiles(m, q), 1, 1, s0);
+    hipDeviceSynchronize();
+    std::vector<int> d1(DL::size);
+    hipMemcpy(d1.data(), dims, DL::size * 4, hipMemcpyDeviceToHost);
+    const int r = d1[DL::rho + 1];
+    hipMemcpy(out1, mps, (size_t)r * n * 8, hipMemcpyDeviceToHost);
+    hipMemcpy(out2, eng + L.off_US, (size_t)m * r * 8, hipMemcpyDeviceToHost);
+    ret = r;
+  }
+  int he = 0;
+  hipMemcpy(&he, err, 4, hipMemcpyDeviceToHost);
+  const hipError_t le = hipGetLastError();
+  cleanup();
+  hipFree(e.d);
+  if (le != hipSuccess) return fail(MPSW_EHIP, std::string("debug_factor: ") + hipGetErrorString(le));
+  if (he) return fail(MPSW_ENOMEM, "debug_factor: device error bits " + std::to_string(he));
+  return ret;
 }
 
 // Host-side helper exported for tests: the fused Laplacian MPO cores

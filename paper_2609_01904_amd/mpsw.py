@@ -21,6 +21,7 @@ EXPORTS = [
     "mpsw_create_state", "mpsw_create_batch", "mpsw_set_velocity_dense", "mpsw_set_velocity_mpo",
     "mpsw_set_source", "mpsw_set_fields", "mpsw_step", "mpsw_to_dense", "mpsw_get_bonds",
     "mpsw_get_stats", "mpsw_get_shape", "mpsw_destroy", "mpsw_last_error", "mpsw_debug_laplacian_mpo",
+    "mpsw_debug_factor",
 ]
 
 
@@ -70,6 +71,7 @@ def load():
         "mpsw_get_shape": [P, ctypes.POINTER(I), ctypes.POINTER(I)],
         "mpsw_destroy": [P],
         "mpsw_debug_laplacian_mpo": [I, I, P, P, ctypes.c_int64],
+        "mpsw_debug_factor": [I, I, I, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -198,3 +200,18 @@ def debug_laplacian_mpo(n, boundary=MPSW_PERIODIC):
         cores.append(buf[o:o + sz].reshape(bonds[k], bonds[k + 1], 2, 2))
         o += sz
     return [int(b) for b in bonds], cores
+
+
+def debug_factor(op, A):
+    """Run the library's QR (op 0) or SVD (op 1) kernels on one matrix."""
+    lib = load()
+    a, p = _f64(A)
+    m, n = a.shape
+    big = max(m, n)
+    o1 = np.zeros(big * big + m * n)
+    o2 = np.zeros(big * big + m * n)
+    q = _check(lib.mpsw_debug_factor(op, m, n, p, o1.ctypes.data_as(ctypes.c_void_p),
+                                     o2.ctypes.data_as(ctypes.c_void_p)))
+    if op == 0:
+        return o1[: m * q].reshape(m, q), o2[: q * n].reshape(q, n)
+    return o1[: q * n].reshape(q, n), o2[: m * q].reshape(m, q)
