@@ -73,6 +73,7 @@ typedef struct mpsw_stats {
   double tail2[3];         /* discarded sum of squared singular values in the last step,
                               summed over bonds, per rounding */
   int64_t fallbacks;       /* learned-rank mode: bonds that fell back to the exact SVD */
+  int max_jacobi_sweeps;   /* most one-sided Jacobi sweeps any bond needed since creation */
 } mpsw_stats;
 
 /* Create a state for one shot with psi^0 = psi^{-1} = 0 (bond 1).

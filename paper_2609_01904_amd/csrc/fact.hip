@@ -17,6 +17,8 @@
 namespace mpsw {
 
 #define MPSW_SPIN_LIMIT (1 << 22)
+#define MPSW_PERM_MAX 1024
+#define QNT 1024   // threads of the QR-family kernels
 
 __device__ __forceinline__ int ld_acquire(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -38,16 +40,17 @@ __device__ void wait_geq(const DevCtx& c, const int* p, int v) {
 }
 
 // Barrier of the nwg workgroups of one shot (arrival counter, monotone).
+// __syncthreads completes every wave's stores within the workgroup; the one
+// agent-scope release (arrival) and acquire (wait) of thread 0 then publish
+// them to, and pick up those of, the other workgroups.
 __device__ void shot_barrier(const DevCtx& c, int* ctr, int nwg, int& epoch) {
-  __threadfence();
   __syncthreads();
   ++epoch;
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(ctr, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     wait_geq(c, ctr, epoch * nwg);
   }
   __syncthreads();
-  __threadfence();
 }
 
 __global__ void k_sync_reset(const DevCtx* __restrict__ cp) {
@@ -61,13 +64,14 @@ __global__ void k_sync_reset(const DevCtx* __restrict__ cp) {
 // V: unit lower trapezoidal (mj x bw), element (r, p) at V[r + ldv * p] for r > p.
 // C: mj x bwc, element (r, q) at C[r * crs + q * ccs].
 // C <- C - V op(T) V^T C with op(T) = T^T (trans) or T; T is bw x bw upper, row-major ld BW.
-// Thread layout: t = q * RS + rs (RS = 256 / BW rows slices per column).
+// Thread layout: t = q * RS + rs (RS = NT / BW row slices per column; a slice
+// group never straddles a wave).
 // ---------------------------------------------------------------------------
-template <int BW>
+template <int BW, int NT>
 __device__ void apply_reflector(const double* __restrict__ V, int64_t ldv, double* C, int64_t crs, int64_t ccs,
                                 int mj, int bw, int bwc, const double* __restrict__ T, bool trans,
-                                double* red /* LDS >= 2*BW*BW */) {
-  constexpr int RS = 256 / BW;
+                                double* red /* LDS >= BW*(NT/64) + BW*BW */) {
+  constexpr int RS = NT / BW;
   const int t = threadIdx.x;
   const int q = t / RS, rs = t % RS;
   double acc[BW];
@@ -84,27 +88,32 @@ __device__ void apply_reflector(const double* __restrict__ V, int64_t ldv, doubl
       }
     }
   }
-  // reduce over the RS row slices (RS lanes of one wave share q)
+  // reduce over the RS row slices: whole waves per column, then the WPC
+  // wave partials of a column in a fixed order (bitwise reproducible)
+  static_assert(RS % 64 == 0, "row slices of a column must fill whole waves");
+  constexpr int WPC = RS / 64;
+  double* Wp = red;            // [BW][BW][WPC] wave partials
+  double* W2 = red + BW * BW * WPC;
+  const int wq = rs >> 6;
 #pragma unroll
   for (int p = 0; p < BW; ++p) {
-    double v = acc[p];
-    for (int off = RS / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    acc[p] = v;
-  }
-  double* W = red;           // BW x BW
-  double* W2 = red + BW * BW;
-  if (rs == 0) {
-#pragma unroll
-    for (int p = 0; p < BW; ++p) W[p * BW + q] = acc[p];
+    const double v = wave_sum64(acc[p]);
+    if ((t & 63) == 0) Wp[(p * BW + q) * WPC + wq] = v;
   }
   __syncthreads();
   if (t < BW * BW) {
     const int p = t / BW, qq = t % BW;
+    auto Wv = [&](int s2) {
+      double x = 0.0;
+#pragma unroll
+      for (int u = 0; u < WPC; ++u) x += Wp[(s2 * BW + qq) * WPC + u];
+      return x;
+    };
     double s = 0.0;
     if (trans) {   // (T^T W)[p][q] = sum_{s<=p} T[s][p] W[s][q]
-      for (int s2 = 0; s2 <= p && s2 < bw; ++s2) s = fma(T[s2 * BW + p], W[s2 * BW + qq], s);
+      for (int s2 = 0; s2 <= p && s2 < bw; ++s2) s = fma(T[s2 * BW + p], Wv(s2), s);
     } else {       // (T W)[p][q] = sum_{s>=p} T[p][s] W[s][q]
-      for (int s2 = p; s2 < bw; ++s2) s = fma(T[p * BW + s2], W[s2 * BW + qq], s);
+      for (int s2 = p; s2 < bw; ++s2) s = fma(T[p * BW + s2], Wv(s2), s);
     }
     W2[p * BW + qq] = s;
   }
@@ -136,31 +145,43 @@ __device__ void apply_reflector(const double* __restrict__ V, int64_t ldv, doubl
 // the square R1^T = Q2 R2 (R2^T -> Jacobi buffer).  The Jacobi sweep then
 // always runs on the transposed triangular factor of a tall-or-square matrix.
 // ---------------------------------------------------------------------------
-template <int BW>
+template <int BW, int NT>
 __device__ void factor_panel(const DevCtx& c, double* S, int m, int n, int j, double* T, double* lds,
                              double* red) {
-  constexpr int RS = 256 / BW;
+  constexpr int RS = NT / BW;   // rows slices per column (RS >= 64: one or more waves per column)
   const int r0 = j * BW, mj = m - r0, c0 = j * BW;
   const int bw = min(BW, n - c0);
   const int t = threadIdx.x;
   double* Pn = lds;  // mj x bw, ld mj
-  for (int e = t; e < mj * bw; e += 256) {
+  for (int e = t; e < mj * bw; e += NT) {
     const int qq = e / mj, r = e % mj;
     Pn[r + (int64_t)mj * qq] = S[r0 + r + (int64_t)m * (c0 + qq)];
   }
-  __shared__ double taus[16];
+  __shared__ double taus[16], betas[16], scales[16];
+  __shared__ double part[NT / 64];
   __syncthreads();
   const int q = t / RS, rs = t % RS;
+  const int lane = t & 63, wq = rs >> 6;   // wave index within the column group
+  constexpr int WPC = RS / 64;             // waves per column
+  // Column i: its Householder vector is kept unscaled in Pn until the panel
+  // is done (v_r = scale_i * x_r); the update of columns q > i uses x_r * scale_i.
+  __shared__ double wrow[16];   // deferred update of row i-1 of the trailing panel columns
   for (int i = 0; i < bw; ++i) {
-    // d_q = sum_{r>i} x_r P[r][q] for q >= i (d_i is the squared norm below the diagonal)
+    if (i > 0 && rs == 0 && q >= i && q < bw) Pn[(i - 1) + (int64_t)mj * q] -= wrow[q];
     double d = 0.0;
     if (q >= i && q < bw) {
-      for (int r = i + 1 + rs; r < mj; r += RS) d = fma(Pn[r + (int64_t)mj * i], Pn[r + (int64_t)mj * q], d);
+      const double* xi = Pn + (int64_t)mj * i;
+      const double* xq = Pn + (int64_t)mj * q;
+      for (int r = i + 1 + rs; r < mj; r += RS) d = fma(xi[r], xq[r], d);
     }
-    for (int off = RS / 2; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
-    if (rs == 0) red[q] = d;
+    d = wave_sum64(d);
+    if (lane == 0) part[q * WPC + wq] = d;
     __syncthreads();
-    const double s2 = red[i];
+    double s2 = 0.0, dq = 0.0;
+    for (int u = 0; u < WPC; ++u) {
+      s2 += part[i * WPC + u];
+      dq += part[q * WPC + u];
+    }
     const double x0 = Pn[i + (int64_t)mj * i];
     double tau = 0.0, beta = x0, scale = 0.0;
     if (s2 > 0.0) {
@@ -168,26 +189,32 @@ __device__ void factor_panel(const DevCtx& c, double* S, int m, int n, int j, do
       tau = (beta - x0) / beta;
       scale = 1.0 / (x0 - beta);
     }
-    double wq = 0.0;
-    if (q > i && q < bw) wq = tau * (Pn[i + (int64_t)mj * q] + scale * red[q]);
-    __syncthreads();
-    // column i -> Householder vector, columns q > i updated
-    if (q == i) {
-      for (int r = i + 1 + rs; r < mj; r += RS) Pn[r + (int64_t)mj * i] *= scale;
-    }
-    __syncthreads();
+    double wqv = 0.0;
     if (q > i && q < bw && tau != 0.0) {
-      for (int r = i + 1 + rs; r < mj; r += RS) Pn[r + (int64_t)mj * q] -= wq * Pn[r + (int64_t)mj * i];
-      if (rs == 0) Pn[i + (int64_t)mj * q] -= wq;
+      double* xq = Pn + (int64_t)mj * q;
+      const double* xi = Pn + (int64_t)mj * i;
+      wqv = tau * (xq[i] + scale * dq);
+      const double f = wqv * scale;
+      for (int r = i + 1 + rs; r < mj; r += RS) xq[r] -= f * xi[r];
     }
+    if (rs == 0 && q < 16) wrow[q] = wqv;   // row i of column q is read by the whole group above
     if (t == 0) {
-      Pn[i + (int64_t)mj * i] = beta;
       taus[i] = tau;
+      betas[i] = beta;
+      scales[i] = scale;
     }
     __syncthreads();
   }
+  // (row bw-1 has no trailing panel columns, so nothing is pending here)
+  // scale the vectors, put the diagonal of R in place
+  for (int e = t; e < mj * bw; e += NT) {
+    const int qq = e / mj, r = e % mj;
+    if (r > qq) Pn[r + (int64_t)mj * qq] *= scales[qq];
+  }
+  __syncthreads();
+  if (t < bw) Pn[t + (int64_t)mj * t] = betas[t];
+  __syncthreads();
   // T (compact WY): T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] z, z_p = V[:,p]^T v_i
-  // z for all p < i via the same slice layout: thread (q = i, rs) sums rows > i.
   double zp[BW];
 #pragma unroll
   for (int p = 0; p < BW; ++p) zp[p] = 0.0;
@@ -200,32 +227,50 @@ __device__ void factor_panel(const DevCtx& c, double* S, int m, int n, int j, do
         if (p < i) zp[p] = fma(Pn[r + (int64_t)mj * p], vi, zp[p]);
     }
   }
+  __shared__ double Zp[16 * (NT / 64)];   // [BW][BW][WPC] wave partials of z
 #pragma unroll
   for (int p = 0; p < BW; ++p) {
-    double v = zp[p];
-    for (int off = RS / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    zp[p] = v;
-  }
-  __shared__ double Z[16 * 16];
-  if (rs == 0 && q < bw) {
-#pragma unroll
-    for (int p = 0; p < BW; ++p) Z[p * BW + q] = (p < q) ? zp[p] + Pn[q + (int64_t)mj * p] : 0.0;
+    const double v = wave_sum64(zp[p]);
+    if (lane == 0) Zp[(p * BW + q) * WPC + wq] = v;
   }
   __syncthreads();
-  if (t == 0) {
-    double Tl[BW * BW];
-    for (int e = 0; e < BW * BW; ++e) Tl[e] = 0.0;
-    for (int i = 0; i < bw; ++i) {
-      Tl[i * BW + i] = taus[i];
-      for (int p = 0; p < i; ++p) {
-        double s = 0.0;
-        for (int s2 = p; s2 < i; ++s2) s = fma(Tl[p * BW + s2], Z[s2 * BW + i], s);
-        Tl[p * BW + i] = -taus[i] * s;
-      }
+  // T = U^{-1} with U upper triangular, U_ii = 1/tau_i, U_pi = v_p^T v_i:
+  // thread i solves U t = e_i for column i by back substitution, written with
+  // the factor tau_p instead of a division so a zero tau yields a zero row.
+  __shared__ double Us[16 * 16];
+  if (t < BW * BW) {
+    const int p = t / BW, i = t % BW;
+    double x = 0.0;
+    if (p < i && i < bw) {
+      for (int u = 0; u < WPC; ++u) x += Zp[(p * BW + i) * WPC + u];
+      x += Pn[i + (int64_t)mj * p];
     }
-    for (int e = 0; e < BW * BW; ++e) T[(int64_t)j * BW * BW + e] = Tl[e];
+    Us[t] = x;
   }
-  for (int e = t; e < mj * bw; e += 256) {
+  __syncthreads();
+  if (t < bw) {
+    const int i = t;
+    double tc[BW];
+#pragma unroll
+    for (int p = BW - 1; p >= 0; --p) {
+      double v = 0.0;
+      if (p == i) {
+        v = taus[p];
+      } else if (p < i) {
+        double s = 0.0;
+#pragma unroll
+        for (int s2 = p + 1; s2 < BW; ++s2)
+          if (s2 <= i) s = fma(Us[p * BW + s2], tc[s2], s);
+        v = -taus[p] * s;
+      }
+      tc[p] = v;
+    }
+#pragma unroll
+    for (int p = 0; p < BW; ++p) T[(int64_t)j * BW * BW + p * BW + i] = tc[p];
+  }
+  for (int e = bw + t; e < BW; e += NT)   // unused columns of a ragged panel
+    for (int p = 0; p < BW; ++p) T[(int64_t)j * BW * BW + p * BW + e] = 0.0;
+  for (int e = t; e < mj * bw; e += NT) {
     const int qq = e / mj, r = e % mj;
     S[r0 + r + (int64_t)m * (c0 + qq)] = Pn[r + (int64_t)mj * qq];
   }
@@ -233,7 +278,7 @@ __device__ void factor_panel(const DevCtx& c, double* S, int m, int n, int j, do
 }
 
 template <int BW>
-__global__ __launch_bounds__(256) void k_qrf(const DevCtx* __restrict__ cp, OpArgs a) {
+__global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpArgs a) {
   const DevCtx& c = *cp;
   const int shot = blockIdx.z, w = blockIdx.x, P = gridDim.x;
   int* dm = shot_dims(c, shot);
@@ -300,7 +345,7 @@ __global__ __launch_bounds__(256) void k_qrf(const DevCtx* __restrict__ cp, OpAr
       if (w == 0 && t == 0) raise_err(c, MPSW_DEV_ERR_CAP);
       return;
     }
-    for (int64_t e = (int64_t)w * 256 + t; e < (int64_t)m * n; e += (int64_t)P * 256) R[e] = X[e];
+    for (int64_t e = (int64_t)w * QNT + t; e < (int64_t)m * n; e += (int64_t)P * QNT) R[e] = X[e];
     if (w == 0 && t == 0) {
       dm[DL::rt + k + 1] = m;
       dm[DL::qid + k] = 1;
@@ -317,48 +362,100 @@ __global__ __launch_bounds__(256) void k_qrf(const DevCtx* __restrict__ cp, OpAr
   int* flags = shot_sync(c, shot) + MPSW_SYNC_FLAGS + (a.op == 2 ? (MPSW_SYNC_STRIDE - MPSW_SYNC_FLAGS) / 2 : 0);
   extern __shared__ double lds[];
   __shared__ double red[2 * 16 * 16];
+  // For the SVD the columns enter in order of decreasing norm (a one-shot
+  // column pivoting): the Jacobi sweep on the transposed triangular factor
+  // then converges in a few passes.  Every workgroup derives the same order;
+  // workgroup 0 records it for k_jacfin.
+  __shared__ double cnorm[MPSW_PERM_MAX];
+  __shared__ int perm[MPSW_PERM_MAX];
+  const bool pivot = !sweep && n <= MPSW_PERM_MAX;
+  if (pivot) {
+    if (xr == 1) {          // columns contiguous: one wave per column
+      const int lane = t & 63, wv = t >> 6;
+      for (int j = wv; j < n; j += QNT / 64) {
+        double s = 0.0;
+        for (int r = lane; r < m; r += 64) {
+          const double x = X[r + (int64_t)j * xc];
+          s = fma(x, x, s);
+        }
+        s = wave_sum64(s);
+        if (lane == 0) cnorm[j] = s;
+      }
+    } else {                // rows contiguous: 32 columns x 32 row slices per pass
+      const int jj = t & 31, rsl = (t >> 6) * 2 + ((t >> 5) & 1), wv = t >> 6;
+      for (int j0 = 0; j0 < n; j0 += 32) {
+        const int j = j0 + jj;
+        double s = 0.0;
+        if (j < n)
+          for (int r = rsl; r < m; r += 32) {
+            const double x = X[(int64_t)r * xr + j];
+            s = fma(x, x, s);
+          }
+        s += __shfl_xor(s, 32, 64);
+        if ((t & 32) == 0) red[wv * 32 + jj] = s;
+        __syncthreads();
+        if (t < 32 && j0 + t < n) {
+          double x = 0.0;
+          for (int u = 0; u < QNT / 64; ++u) x += red[u * 32 + t];
+          cnorm[j0 + t] = x;
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+    for (int j = t; j < n; j += QNT) {
+      const double sj = cnorm[j];
+      int rank = 0;
+      for (int i = 0; i < n; ++i) rank += (cnorm[i] > sj) || (cnorm[i] == sj && i < j);
+      perm[rank] = j;
+    }
+    __syncthreads();
+    if (w == 0) {
+      double* pout = E + L.off_perm;
+      for (int j = t; j < n; j += QNT) pout[j] = (double)perm[j];
+    }
+  }
   // my column blocks into S (column-major m x n)
   for (int blk = w; blk < nbk; blk += P) {
     const int c0 = blk * BW, bw = min(BW, n - c0);
-    if (xc == 1) {
-      for (int e = t; e < m * bw; e += 256) {
+    if (xc == 1 && !pivot) {
+      for (int e = t; e < m * bw; e += QNT) {
         const int r = e / bw, qq = e % bw;
         S[r + (int64_t)m * (c0 + qq)] = X[(int64_t)r * xr + c0 + qq];
       }
     } else {
-      for (int e = t; e < m * bw; e += 256) {
+      for (int e = t; e < m * bw; e += QNT) {
         const int qq = e / m, r = e % m;
-        S[r + (int64_t)m * (c0 + qq)] = X[(int64_t)r * xr + (int64_t)(c0 + qq) * xc];
+        const int src = pivot ? perm[c0 + qq] : c0 + qq;
+        S[r + (int64_t)m * (c0 + qq)] = X[(int64_t)r * xr + (int64_t)src * xc];
       }
     }
   }
   __syncthreads();
   auto publish = [&](int j) {
-    __threadfence();
     __syncthreads();
     if (t == 0) __hip_atomic_store(flags + j, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   };
   auto apply = [&](int j, int blk) {
     const int r0 = j * BW, c0 = j * BW, bw = min(BW, n - c0);
     const int cb = blk * BW, bwc = min(BW, n - cb);
-    apply_reflector<BW>(S + r0 + (int64_t)m * c0, m, S + r0 + (int64_t)m * cb, 1, m, m - r0, bw, bwc,
+    apply_reflector<BW, QNT>(S + r0 + (int64_t)m * c0, m, S + r0 + (int64_t)m * cb, 1, m, m - r0, bw, bwc,
                         T + (int64_t)j * BW * BW, true, red);
   };
   if (w == 0) {
-    factor_panel<BW>(c, S, m, n, 0, T, lds, red);
+    factor_panel<BW, QNT>(c, S, m, n, 0, T, lds, red);
     publish(0);
   }
   for (int j = 0; j < nbk; ++j) {
     if (j % P != w) {
       if (t == 0) wait_geq(c, flags + j, 1);
       __syncthreads();
-      __threadfence();
     }
     const int j1 = j + 1;
     const bool own1 = (j1 < nbk) && (j1 % P == w);
     if (own1) {
       apply(j, j1);
-      factor_panel<BW>(c, S, m, n, j1, T, lds, red);
+      factor_panel<BW, QNT>(c, S, m, n, j1, T, lds, red);
       publish(j1);
     }
     int first = w;
@@ -371,7 +468,7 @@ __global__ __launch_bounds__(256) void k_qrf(const DevCtx* __restrict__ cp, OpAr
   // R (n x n) from my columns: row-major R (sweep) or R^T column-major (SVD)
   for (int blk = w; blk < nbk; blk += P) {
     const int c0 = blk * BW, bw = min(BW, n - c0);
-    for (int e = t; e < n * bw; e += 256) {
+    for (int e = t; e < n * bw; e += QNT) {
       const int r = e / bw, qq = e % bw, col = c0 + qq;
       const double v = (r <= col) ? S[r + (int64_t)m * col] : 0.0;
       if (sweep) Rout[(int64_t)r * n + col] = v;
@@ -389,7 +486,7 @@ __global__ __launch_bounds__(256) void k_qrf(const DevCtx* __restrict__ cp, OpAr
 // per workgroup, reflectors applied last to first.
 // ---------------------------------------------------------------------------
 template <int BW>
-__global__ __launch_bounds__(256) void k_applyq(const DevCtx* __restrict__ cp, OpArgs a) {
+__global__ __launch_bounds__(1024) void k_applyq(const DevCtx* __restrict__ cp, OpArgs a) {
   const DevCtx& c = *cp;
   const int shot = blockIdx.z, w = blockIdx.x;
   const int k = a.site;
@@ -410,7 +507,7 @@ __global__ __launch_bounds__(256) void k_applyq(const DevCtx* __restrict__ cp, O
   if (col0 >= r) return;
   const int cw = min(CW, r - col0);
   if (dm[DL::qid + k - 1]) {  // identity: rt_k = 2 rt_{k-1}, same memory shape
-    for (int e = t; e < m * cw; e += 256) {
+    for (int e = t; e < m * cw; e += QNT) {
       const int row = e / cw, qq = e % cw;
       M[(int64_t)row * r + col0 + qq] = US[(int64_t)row * r + col0 + qq];
     }
@@ -424,14 +521,14 @@ __global__ __launch_bounds__(256) void k_applyq(const DevCtx* __restrict__ cp, O
     return;
   }
   __shared__ double red[2 * 16 * 16];
-  for (int e = t; e < m * cw; e += 256) {
+  for (int e = t; e < m * cw; e += QNT) {
     const int row = e / cw, qq = e % cw;
     M[(int64_t)row * r + col0 + qq] = (row < n) ? US[(int64_t)row * r + col0 + qq] : 0.0;
   }
   __syncthreads();
   for (int j = nbk - 1; j >= 0; --j) {
     const int r0 = j * BW, c0 = j * BW, bw = min(BW, n - c0);
-    apply_reflector<BW>(S + r0 + (int64_t)m * c0, m, M + (int64_t)r0 * r + col0, r, 1, m - r0, bw, cw,
+    apply_reflector<BW, QNT>(S + r0 + (int64_t)m * c0, m, M + (int64_t)r0 * r + col0, r, 1, m - r0, bw, cw,
                         T + (int64_t)j * BW * BW, false, red);
   }
 }
@@ -442,7 +539,7 @@ __global__ __launch_bounds__(256) void k_applyq(const DevCtx* __restrict__ cp, O
 // Column chunks of BW per workgroup.
 // ---------------------------------------------------------------------------
 template <int BW>
-__global__ __launch_bounds__(256) void k_applyv(const DevCtx* __restrict__ cp, OpArgs a) {
+__global__ __launch_bounds__(1024) void k_applyv(const DevCtx* __restrict__ cp, OpArgs a) {
   const DevCtx& c = *cp;
   const int shot = blockIdx.z, w = blockIdx.x;
   const int k = a.site;
@@ -467,17 +564,17 @@ __global__ __launch_bounds__(256) void k_applyv(const DevCtx* __restrict__ cp, O
     return;
   }
   __shared__ double red[2 * 16 * 16];
-  for (int e = t; e < n * cw; e += 256) {
+  for (int e = t; e < n * cw; e += QNT) {
     const int row = e / cw, qq = e % cw;
     Y[(int64_t)row * r + col0 + qq] = (row < m) ? Vp[(int64_t)(col0 + qq) * m + row] : 0.0;
   }
   __syncthreads();
   for (int j = nbk - 1; j >= 0; --j) {
     const int r0 = j * BW, c0 = j * BW, bw = min(BW, m - c0);
-    apply_reflector<BW>(S + r0 + (int64_t)n * c0, n, Y + (int64_t)r0 * r + col0, r, 1, n - r0, bw, cw,
+    apply_reflector<BW, QNT>(S + r0 + (int64_t)n * c0, n, Y + (int64_t)r0 * r + col0, r, 1, n - r0, bw, cw,
                         T + (int64_t)j * BW * BW, false, red);
   }
-  for (int e = t; e < n * cw; e += 256) {
+  for (int e = t; e < n * cw; e += QNT) {
     const int qq = e / n, row = e % n;
     core[(int64_t)(col0 + qq) * n + row] = Y[(int64_t)row * r + col0 + qq];
   }
@@ -491,6 +588,71 @@ __global__ __launch_bounds__(256) void k_applyv(const DevCtx* __restrict__ cp, O
 // every active workgroup loads one pair of blocks into LDS and rotates all
 // column pairs of the pair once.  Sweeps repeat until one rotates nothing.
 // ---------------------------------------------------------------------------
+// Rotation of one column pair by a group of 16 lanes; each lane keeps its
+// EPL elements of both columns in registers (columns of length Lc <= 16 EPL).
+template <int EPL>
+__device__ __forceinline__ bool rotate_pair(double* ap, double* aq, int gl, int Lc, double tol, double floor2) {
+  double x[EPL], y[EPL];
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    const int i = gl + 16 * e;
+    x[e] = (i < Lc) ? ap[i] : 0.0;
+    y[e] = (i < Lc) ? aq[i] : 0.0;
+  }
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    al = fma(x[e], x[e], al);
+    be = fma(y[e], y[e], be);
+    ga = fma(x[e], y[e], ga);
+  }
+  al = row_sum16(al);
+  be = row_sum16(be);
+  ga = row_sum16(ga);
+  if (al <= floor2 || be <= floor2 || fabs(ga) <= tol * sqrt(al) * sqrt(be)) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  double tt;
+  if (fabs(zeta) > 1e100) tt = 0.5 / zeta;
+  else tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    const int i = gl + 16 * e;
+    if (i < Lc) {
+      ap[i] = cs * x[e] - sn * y[e];
+      aq[i] = sn * x[e] + cs * y[e];
+    }
+  }
+  return true;
+}
+
+template <>
+__device__ __forceinline__ bool rotate_pair<0>(double* ap, double* aq, int gl, int Lc, double tol, double floor2) {
+  double al = 0.0, be = 0.0, ga = 0.0;
+  for (int i = gl; i < Lc; i += 16) {
+    const double x = ap[i], y = aq[i];
+    al = fma(x, x, al);
+    be = fma(y, y, be);
+    ga = fma(x, y, ga);
+  }
+  al = row_sum16(al);
+  be = row_sum16(be);
+  ga = row_sum16(ga);
+  if (al <= floor2 || be <= floor2 || fabs(ga) <= tol * sqrt(al) * sqrt(be)) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  double tt;
+  if (fabs(zeta) > 1e100) tt = 0.5 / zeta;
+  else tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+  for (int i = gl; i < Lc; i += 16) {
+    const double x = ap[i], y = aq[i];
+    ap[i] = cs * x - sn * y;
+    aq[i] = sn * x + cs * y;
+  }
+  return true;
+}
+
+template <int EPL>
 __global__ __launch_bounds__(512) void k_jac(const DevCtx* __restrict__ cp, OpArgs a, int b) {
   const DevCtx& c = *cp;
   const int shot = blockIdx.z, w = blockIdx.x, P = gridDim.x;
@@ -512,7 +674,20 @@ __global__ __launch_bounds__(512) void k_jac(const DevCtx* __restrict__ cp, OpAr
   extern __shared__ double blk[];   // 2b columns, stride ldl
   const int ldl = Lc + 1;
   __shared__ int nrot;
+  __shared__ double fro_red[16];
   const double tol = 1e-15 * sqrt((double)Lc);
+  // Columns below 1e-14 ||A||_F are numerically zero (rounding noise of the
+  // factorisations): they are not rotated, since their direction cannot be
+  // resolved and chasing it would never converge.
+  double fro = 0.0;
+  if (ok)
+    for (int64_t e = t; e < (int64_t)Lc * cc; e += blockDim.x) fro = fma(A[e], A[e], fro);
+  fro = wave_sum(fro);
+  if (lane == 0) fro_red[wv] = fro;
+  __syncthreads();
+  fro = 0.0;
+  for (int i = 0; i < nwv; ++i) fro += fro_red[i];
+  const double floor2 = 1e-28 * fro;
   for (int sweep = 0; sweep < MPSW_MAX_SWEEPS; ++sweep) {
     for (int rnd = 0; rnd < nbe - 1; ++rnd) {
       if (ok && w < pact && cc > 1) {
@@ -531,38 +706,17 @@ __global__ __launch_bounds__(512) void k_jac(const DevCtx* __restrict__ cp, OpAr
           blk[jj * ldl + i] = A[(int64_t)gcol * Lc + i];
         }
         __syncthreads();
-        // one cyclic pass over all column pairs of the loaded block pair
+        // one cyclic pass over all column pairs of the loaded block pair; a
+        // pair is handled by a group of 16 lanes (4 pairs per wave in flight)
         const int npl = ncol + (ncol & 1);
+        const int g = t >> 4, gl = t & 15, ng = blockDim.x >> 4;
         for (int ir = 0; ir < npl - 1; ++ir) {
-          for (int pi = wv; pi < npl / 2; pi += nwv) {
+          for (int pi = g; pi < npl / 2; pi += ng) {
             int p, q;
             if (pi == 0) { p = ir; q = npl - 1; }
             else { p = (ir + pi) % (npl - 1); q = (ir - pi + (npl - 1)) % (npl - 1); }
             if (p >= ncol || q >= ncol) continue;
-            double* ap = blk + p * ldl;
-            double* aq = blk + q * ldl;
-            double al = 0.0, be = 0.0, ga = 0.0;
-            for (int i = lane; i < Lc; i += 64) {
-              const double x = ap[i], y = aq[i];
-              al = fma(x, x, al);
-              be = fma(y, y, be);
-              ga = fma(x, y, ga);
-            }
-            al = wave_sum(al);
-            be = wave_sum(be);
-            ga = wave_sum(ga);
-            if (al == 0.0 || be == 0.0 || fabs(ga) <= tol * sqrt(al) * sqrt(be)) continue;
-            const double zeta = (be - al) / (2.0 * ga);
-            double tt;
-            if (fabs(zeta) > 1e100) tt = 0.5 / zeta;
-            else tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-            for (int i = lane; i < Lc; i += 64) {
-              const double x = ap[i], y = aq[i];
-              ap[i] = cs * x - sn * y;
-              aq[i] = sn * x + cs * y;
-            }
-            if (lane == 0) atomicAdd(&nrot, 1);
+            if (rotate_pair<EPL>(blk + p * ldl, blk + q * ldl, gl, Lc, tol, floor2) && gl == 0) atomicAdd(&nrot, 1);
           }
           __syncthreads();
         }
@@ -578,7 +732,10 @@ __global__ __launch_bounds__(512) void k_jac(const DevCtx* __restrict__ cp, OpAr
     }
     // every workgroup reads the same final count after the barrier
     const int rot = ld_acquire(sy + MPSW_SYNC_ROT + (sweep & 63));
-    if (rot == 0 || !ok || cc <= 1) break;
+    if (rot == 0 || !ok || cc <= 1) {
+      if (w == 0 && t == 0) atomicMax((int*)dm + DL::jac_sweeps, sweep + 1);
+      break;
+    }
   }
 }
 
@@ -661,11 +818,15 @@ __global__ __launch_bounds__(256) void k_jacfin(const DevCtx* __restrict__ cp, O
     if (t == 0) raise_err(c, MPSW_DEV_ERR_CAP);
     return;
   }
+  // A's row l belongs to column perm[l] of the matrix the last QR factored
+  const double* pv = E + c.L.off_perm;
+  const bool pivoted = cc <= MPSW_PERM_MAX;
   for (int64_t e = t; e < (int64_t)r * cc; e += blockDim.x) {
     const int i = (int)(e / cc), l = (int)(e % cc);
     const int j = order[i];
     const double s = sig[j];
-    out[e] = (s > 0.0) ? A[(int64_t)j * Lc + l] / s : ((l == i) ? 1.0 : 0.0);
+    const int dst = pivoted ? (int)pv[l] : l;
+    out[(int64_t)i * cc + dst] = (s > 0.0) ? A[(int64_t)j * Lc + l] / s : ((l == i) ? 1.0 : 0.0);
   }
   if (t == 0) dm[DL::rho + k] = r;
 }
@@ -679,33 +840,39 @@ void launch_sync_reset(const DevCtx* d, int nshots, hipStream_t s) {
 
 void launch_qrf(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, size_t lds, hipStream_t s) {
   if (bw == 16)
-    hipLaunchKernelGGL(k_qrf<16>, dim3(nwg, 1, nshots), dim3(256), lds, s, d, a);
+    hipLaunchKernelGGL(k_qrf<16>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
   else if (bw == 8)
-    hipLaunchKernelGGL(k_qrf<8>, dim3(nwg, 1, nshots), dim3(256), lds, s, d, a);
+    hipLaunchKernelGGL(k_qrf<8>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
   else
-    hipLaunchKernelGGL(k_qrf<4>, dim3(nwg, 1, nshots), dim3(256), lds, s, d, a);
+    hipLaunchKernelGGL(k_qrf<4>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
 }
 
 void launch_applyq(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, hipStream_t s) {
   if (bw == 16)
-    hipLaunchKernelGGL(k_applyq<16>, dim3(nwg, 1, nshots), dim3(256), 0, s, d, a);
+    hipLaunchKernelGGL(k_applyq<16>, dim3(nwg, 1, nshots), dim3(QNT), 0, s, d, a);
   else if (bw == 8)
-    hipLaunchKernelGGL(k_applyq<8>, dim3(nwg, 1, nshots), dim3(256), 0, s, d, a);
+    hipLaunchKernelGGL(k_applyq<8>, dim3(nwg, 1, nshots), dim3(QNT), 0, s, d, a);
   else
-    hipLaunchKernelGGL(k_applyq<4>, dim3(nwg, 1, nshots), dim3(256), 0, s, d, a);
+    hipLaunchKernelGGL(k_applyq<4>, dim3(nwg, 1, nshots), dim3(QNT), 0, s, d, a);
 }
 
 void launch_applyv(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, hipStream_t s) {
   if (bw == 16)
-    hipLaunchKernelGGL(k_applyv<16>, dim3(nwg, 1, nshots), dim3(256), 0, s, d, a);
+    hipLaunchKernelGGL(k_applyv<16>, dim3(nwg, 1, nshots), dim3(QNT), 0, s, d, a);
   else if (bw == 8)
-    hipLaunchKernelGGL(k_applyv<8>, dim3(nwg, 1, nshots), dim3(256), 0, s, d, a);
+    hipLaunchKernelGGL(k_applyv<8>, dim3(nwg, 1, nshots), dim3(QNT), 0, s, d, a);
   else
-    hipLaunchKernelGGL(k_applyv<4>, dim3(nwg, 1, nshots), dim3(256), 0, s, d, a);
+    hipLaunchKernelGGL(k_applyv<4>, dim3(nwg, 1, nshots), dim3(QNT), 0, s, d, a);
 }
 
-void launch_jac(const DevCtx* d, const OpArgs& a, int b, int nwg, int nshots, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(k_jac, dim3(nwg, 1, nshots), dim3(512), lds, s, d, a, b);
+void launch_jac(const DevCtx* d, const OpArgs& a, int b, int nwg, int nshots, size_t lds, int64_t lcap, hipStream_t s) {
+  const dim3 g(nwg, 1, nshots), blk(512);
+  if (lcap <= 32) hipLaunchKernelGGL(k_jac<2>, g, blk, lds, s, d, a, b);
+  else if (lcap <= 64) hipLaunchKernelGGL(k_jac<4>, g, blk, lds, s, d, a, b);
+  else if (lcap <= 128) hipLaunchKernelGGL(k_jac<8>, g, blk, lds, s, d, a, b);
+  else if (lcap <= 256) hipLaunchKernelGGL(k_jac<16>, g, blk, lds, s, d, a, b);
+  else if (lcap <= 512) hipLaunchKernelGGL(k_jac<32>, g, blk, lds, s, d, a, b);
+  else hipLaunchKernelGGL(k_jac<0>, g, blk, lds, s, d, a, b);
 }
 
 void launch_jacfin(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s) {
@@ -716,7 +883,12 @@ void set_lds_limits(size_t bytes) {
   (void)hipFuncSetAttribute((const void*)k_qrf<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   (void)hipFuncSetAttribute((const void*)k_qrf<8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   (void)hipFuncSetAttribute((const void*)k_qrf<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  (void)hipFuncSetAttribute((const void*)k_jac, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  (void)hipFuncSetAttribute((const void*)k_jac<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  (void)hipFuncSetAttribute((const void*)k_jac<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  (void)hipFuncSetAttribute((const void*)k_jac<8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  (void)hipFuncSetAttribute((const void*)k_jac<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  (void)hipFuncSetAttribute((const void*)k_jac<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  (void)hipFuncSetAttribute((const void*)k_jac<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 }  // namespace mpsw

@@ -36,6 +36,29 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 
+// Sum over each row of 16 lanes with DPP row rotations and quad permutes
+// (every lane of the row receives the sum).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row_sum16(double v) {
+  v += dpp_f64<0x128>(v);  // row_ror:8
+  v += dpp_f64<0x124>(v);  // row_ror:4
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  return v;
+}
+// Sum over the 64 lanes of a wave (row sums, then across the four rows).
+__device__ __forceinline__ double wave_sum64(double v) {
+  v = row_sum16(v);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
 __device__ __forceinline__ int* shot_sync(const DevCtx& c, int shot) { return c.sync + (int64_t)shot * MPSW_SYNC_STRIDE; }
 
 }  // namespace mpsw

@@ -41,7 +41,8 @@ struct ShotDimsLayout {
   static constexpr int src_iz = src_ix + 1;
   static constexpr int src_nt = src_iz + 1;
   static constexpr int maxbond = src_nt + 1;                       // [3] per rounding of the last step
-  static constexpr int size = maxbond + 4;
+  static constexpr int jac_sweeps = maxbond + 3;                   // most Jacobi sweeps since the last reset
+  static constexpr int size = jac_sweeps + 1;
 };
 
 // Per-shot double block layout (offsets in doubles, separate small array).
@@ -69,6 +70,7 @@ struct EngineLayout {
   int64_t off_qrS2, cap_qrS2, off_qrT2, cap_qrT2;  // second QR of a wide bond matrix
   int64_t off_Vp, cap_Vp;   // V'^T of a wide bond matrix
   int64_t off_Yv, cap_Yv;   // V = Q1 [V'; 0] work
+  int64_t off_perm, cap_perm; // column order of the last SVD QR (stored as doubles)
   int64_t off_sJ, cap_sJ;   // Jacobi accumulated rotations
   int64_t off_qrS, cap_qrS; // Householder working matrix
   int64_t off_qrT, cap_qrT; // Householder tau

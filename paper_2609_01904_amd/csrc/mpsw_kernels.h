@@ -40,7 +40,7 @@ void launch_sync_reset(const DevCtx* d, int nshots, hipStream_t s);
 void launch_qrf(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, size_t lds, hipStream_t s);
 void launch_applyq(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, hipStream_t s);
 void launch_applyv(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, hipStream_t s);
-void launch_jac(const DevCtx* d, const OpArgs& a, int b, int nwg, int nshots, size_t lds, hipStream_t s);
+void launch_jac(const DevCtx* d, const OpArgs& a, int b, int nwg, int nshots, size_t lds, int64_t lcap, hipStream_t s);
 void launch_jacfin(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
 void set_lds_limits(size_t bytes);
 void launch_finish(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);

@@ -252,6 +252,7 @@ void layout_engine(const Plan& p, EngineLayout& L) {
   L.cap_qrT2 = capQRT2; add64(off, L.off_qrT2, capQRT2);
   L.cap_Vp = capVp; add64(off, L.off_Vp, capVp);
   L.cap_Yv = capYv; add64(off, L.off_Yv, capYv);
+  L.cap_perm = 4096; add64(off, L.off_perm, 4096);
   L.cap_qrS = capQRS; add64(off, L.off_qrS, capQRS);
   L.cap_qrT = capQRT; add64(off, L.off_qrT, capQRT);
   L.stride = off;
@@ -385,7 +386,7 @@ size_t lds_limit() {
 // Householder panel width for a QR whose row count is at most mcap: the panel
 // (mcap x bw doubles) lives in LDS.
 int qr_panel(int64_t mcap) {
-  const size_t lim = lds_limit() - 8192;   // static LDS of the kernel
+  const size_t lim = lds_limit() - 24576;   // static LDS of the kernel
   for (int bw = 16; bw >= 4; bw >>= 1)
     if ((size_t)mcap * bw * 8 <= lim) return bw;
   return 0;
@@ -395,7 +396,7 @@ int qr_panel(int64_t mcap) {
 // (2 bw columns of lcap+1 doubles) lives in LDS.
 int jac_block(int64_t lcap) {
   const size_t lim = lds_limit() - 1024;   // static LDS of the kernel
-  for (int b = 16; b >= 1; b >>= 1)
+  for (int b = 32; b >= 1; b >>= 1)
     if ((size_t)2 * b * (lcap + 1) * 8 <= lim) return b;
   return 0;
 }
@@ -517,7 +518,7 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
                (size_t)ccap * bw2 * 8, strm);
     const int b = jac_block(ccap);
     const int64_t nb = cdiv(ccap, b);
-    launch_jac(d, v, b, (int)std::max<int64_t>(1, (nb + (nb & 1)) / 2), nshots, (size_t)2 * b * (ccap + 1) * 8, strm);
+    launch_jac(d, v, b, (int)std::max<int64_t>(1, (nb + (nb & 1)) / 2), nshots, (size_t)2 * b * (ccap + 1) * 8, ccap, strm);
     launch_jacfin(d, v, nshots, strm);
     launch_applyv(d, v, bw1, std::max(1, cdiv(s.rho[k], bw1)), nshots, strm);
     OpArgs g{};
@@ -1042,6 +1043,7 @@ int mpsw_get_stats(mpsw_state st, int shot, mpsw_stats* out) {
     out->tail2[i] = r[RL::tail2 + i];
   }
   out->fallbacks = 0;
+  out->max_jacobi_sweeps = d[DL::jac_sweeps];
   return MPSW_OK;
 }
 
@@ -1095,6 +1097,7 @@ int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, doubl
   place(L.off_sA, L.cap_sA); place(L.off_sJ, L.cap_sJ); place(L.off_qrS, L.cap_qrS); place(L.off_qrT, L.cap_qrT);
   place(L.off_sA2, L.cap_sA2); place(L.off_qrS2, L.cap_qrS2); place(L.off_qrT2, L.cap_qrT2);
   place(L.off_Vp, L.cap_Vp); place(L.off_Yv, L.cap_Yv);
+  L.cap_perm = 4096; place(L.off_perm, L.cap_perm);
   L.stride = off;
   const int64_t core_cap = (int64_t)q * n + 2;
   double *eng = nullptr, *mps = nullptr, *reals = nullptr;
@@ -1166,7 +1169,7 @@ int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, doubl
     const int b = jac_block(q);
     if (b == 0) { cleanup(); hipFree(e.d); return fail(MPSW_ENOMEM, "columns too long for LDS"); }
     const int64_t nb = cdiv(q, b);
-    launch_jac(e.d, v, b, (int)std::max<int64_t>(1, (nb + (nb & 1)) / 2), 1, (size_t)2 * b * (q + 1) * 8, s0);
+    launch_jac(e.d, v, b, (int)std::max<int64_t>(1, (nb + (nb & 1)) / 2), 1, (size_t)2 * b * (q + 1) * 8, q, s0);
     launch_jacfin(e.d, v, 1, s0);
     launch_applyv(e.d, v, bw, std::max<int>(1, cdiv(q, bw)), 1, s0);
     OpArgs g{};

@@ -41,7 +41,7 @@ class Config(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("nsites", ctypes.c_int), ("bonds", ctypes.c_int * 64),
                 ("max_exact_bond", ctypes.c_int * 3), ("tail2", ctypes.c_double * 3),
-                ("fallbacks", ctypes.c_int64)]
+                ("fallbacks", ctypes.c_int64), ("max_jacobi_sweeps", ctypes.c_int)]
 
 
 _lib = None
@@ -182,7 +182,7 @@ class State:
         _check(load().mpsw_get_stats(self._h, shot, ctypes.byref(s)))
         return {"step": s.step, "bonds": list(s.bonds[: self.K + 1]),
                 "max_exact_bond": list(s.max_exact_bond), "tail2": list(s.tail2),
-                "fallbacks": s.fallbacks}
+                "fallbacks": s.fallbacks, "max_jacobi_sweeps": s.max_jacobi_sweeps}
 
 
 def debug_laplacian_mpo(n, boundary=MPSW_PERIODIC):
