@@ -1,0 +1,235 @@
+"""Throughput of the quantics-MPS wave step (eq. 17) on one GPU.
+
+One step = the three roundings of the time step (Laplacian MPO, c^2 Hadamard,
+MPS sum + source), each an L->R QR sweep plus an R->L truncated SVD sweep
+(Sec. 4.3), for every shot of the batch.  The workload is the n = 10 grid
+(1024 x 1024, dh = 10 m, dt = 1 ms) over the seeded layered-fault velocity model
+(c^2 MPO cutoff 1e-6), chi_max = 128, eps = 1e-6, Ricker 15 Hz sources at depth
+index 1.  Timing starts from a developed wavefield (a seeded superposition of
+circular wavefronts, every middle bond at the chi cap), so the timed steps are
+steady-state steps at the cap.
+
+Prints ONE JSON line (rank 0).  `value` is shot-steps per second over the
+timed steps with all inputs resident on the device.  `roofline` is the dominant
+kernel class: its algorithmic flops (counted on the device from the live bond
+sizes) over its event-timed launch durations in the same timed region.
+`cpu_baseline` times the FP64 CPU oracle (dense-detour stepper) on a bounded
+sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# Peaks of one MI355X (published).  FP64 vector: 256 CUs x 4 SIMDs x 16 lanes
+# x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s, the same as the FP64 matrix-core peak.
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+KERNEL_SOURCES = {
+    0: ["paper_2609_01904_amd/csrc/fact.hip"],
+    1: ["paper_2609_01904_amd/csrc/fact.hip"],
+    2: ["paper_2609_01904_amd/csrc/kernels.hip"],
+    3: ["paper_2609_01904_amd/csrc/fact.hip"],
+    4: ["paper_2609_01904_amd/csrc/fact.hip"],
+}
+KERNEL_NAMES = {0: "k_qrf", 1: "k_jac", 2: "k_gemm", 3: "k_applyq", 4: "k_applyv"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash(kclass):
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES[kclass] + ["paper_2609_01904_amd/csrc/mpsw_device.h",
+                                         "paper_2609_01904_amd/csrc/mpsw_internal.h"]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kclass, workload, batch):
+    """HBM bytes per launch from a committed counter summary, or None when the
+    summary is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{KERNEL_NAMES[kclass]}_{workload}_b{batch}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.strip().split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("SOURCE_HASH") != source_hash(kclass):
+        return None
+    try:
+        return float(vals["HBM_BYTES_PER_LAUNCH"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_state(mpsw, synth, workload, batch, precision):
+    cfg = synth.get_config(workload)
+    n = cfg["n"]
+    N = 1 << n
+    prec = {"fp64": mpsw.MPSW_FP64, "fp32": mpsw.MPSW_FP32, "bf16": mpsw.MPSW_BF16}[precision]
+    cfgs = [mpsw.make_config(n, cfg["chi"], cfg["eps"], cfg["lam"], precision=prec) for _ in range(batch)]
+    st = mpsw.State(cfgs if batch > 1 else cfgs[0])
+    st.set_velocity_dense(cfg["c2"], cfg["eps_c"])
+    fields = []
+    up0, u0 = synth.wavefront_fields(n, seed=0)
+    for b in range(batch):
+        # shot b starts from one of the 8 symmetries of the square of the same wavefield
+        sym = lambda f: np.rot90(f[::-1] if (b // 4) % 2 else f, b % 4).copy()  # noqa: E731
+        up, u = sym(up0), sym(u0)
+        st.set_fields(b, up, u)
+        # distinct source positions along the surface row
+        ix = (cfg["ix"] + b * (N // max(batch, 1))) % N
+        st.set_source(b, ix, cfg["iz"], cfg["wavelet_samples"])
+        fields.append((up, u, ix))
+    return st, cfg, fields
+
+
+def cpu_baseline(synth, workload, fields, seconds):
+    """Steps/s of the FP64 CPU oracle (dense-detour stepper) from shot 0's state."""
+    from oracle import mps as OM
+    from oracle.stepper import DenseStepper
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    cfg = synth.get_config(workload)
+    n = cfg["n"]
+    N = 1 << n
+    c2 = OM.to_dense(OM.tt_svd(cfg["c2"].reshape(-1), 2 * n, cfg["eps_c"], chi_max=1 << 30)).reshape(N, N)
+    up, u, ix = fields[0]
+    ds = DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], c2, src=(ix, cfg["iz"]),
+                      wavelet=cfg["wavelet_samples"])
+    ds.set_fields(up, u)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        ds.step()
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 50:
+            break
+    return {"value": steps / el, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{steps} steps of the same workload (shot 0, same starting wavefield) with the "
+                      f"FP64 dense-detour oracle stepper on the host, {el:.1f} s"}
+
+
+def copy_calibration(torch):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=1, help="shots advanced together")
+    ap.add_argument("--workload", default="C3")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--kernel-class", type=int, default=-1,
+                    help="kernel class for the roofline (-1: the one with most time)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (byte-counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(shots are independent and would be partitioned across GPUs by the caller)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
+
+    from paper_2609_01904_amd import mpsw
+    import synth
+
+    t_setup = time.perf_counter()
+    st, cfg, fields = make_state(mpsw, synth, args.workload, args.batch, args.precision)
+    torch.cuda.synchronize()
+    log(f"setup {time.perf_counter() - t_setup:.1f} s; bonds {st.bonds(0, 0)}")
+
+    st.step(args.warmup)
+    torch.cuda.synchronize()
+    kclass = args.kernel_class
+    if kclass < 0:   # the class with the most event time over one probe step (untimed)
+        best = None
+        for c in range(5):
+            st.profile(c)
+            st.step(1)
+            p = st.profile_read(c)
+            log(f"probe class {mpsw.KC_NAMES[c]}: {p['total_ms']:.2f} ms in {p['launches']} launches")
+            if best is None or p["total_ms"] > best[1]:
+                best = (c, p["total_ms"])
+        kclass = best[0]
+    st.profile(kclass)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.step(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = st.profile_read(kclass)
+    stats = [st.stats(b) for b in range(args.batch)]
+    log(f"timed {args.steps} steps x {args.batch} shots in {el:.3f} s; bonds {stats[0]['bonds']}; "
+        f"max Jacobi sweeps {stats[0]['max_jacobi_sweeps']}")
+
+    value = args.batch * args.steps / el
+    avg_ms = prof["total_ms"] / max(prof["launches"], 1)
+    flops_per_launch = prof["alg_flops"] / max(prof["launches"], 1)
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    traffic = read_traffic(kclass, args.workload, args.batch)
+    # every kernel of the FP64 path computes on the FP64 vector ALUs
+    roofline = {"bound": "alu", "achieved": achieved,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": traffic, "kernel": KERNEL_NAMES[kclass], "launches": prof["launches"],
+                "avg_launch_ms": avg_ms, "alg_flops_per_launch": flops_per_launch,
+                "share_of_step_time": prof["total_ms"] / (el * 1e3)}
+    out = {
+        "metric": "MPS FDTD steps/sec at n=10, chi=128 (chosen vs plain FP64) at stated rel-L2 err",
+        "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: n={cfg['n']} (1024x1024), chi_max={cfg['chi']}, "
+                               f"eps={cfg['eps']}, layered-fault c^2 (cutoff {cfg['eps_c']}), "
+                               f"start from a developed wavefield at the chi cap",
+                   "shots": args.batch, "precision": args.precision, "rank": "exact SVD"},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(synth, args.workload, fields, args.cpu_seconds)
+    st.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

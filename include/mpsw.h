@@ -124,8 +124,38 @@ int mpsw_to_dense(mpsw_state st, int shot, int which, double* out, int out_is_de
  * the c^2 operator (2).  Synchronises.  Errors: EINVAL, EHIP. */
 int mpsw_get_bonds(mpsw_state st, int shot, int which, int* bonds);
 
-/* Statistics of shot `shot` after the last step.  Synchronises. */
+/* Statistics of shot `shot` after the last step.  Synchronises and reports
+ * device-side failures of the steps enqueued so far: ENOMEM (a live size
+ * exceeded a workspace), ENONFINITE, EHIP (a bounded inter-workgroup wait gave
+ * up). */
 int mpsw_get_stats(mpsw_state st, int shot, mpsw_stats* out);
+
+/* Kernel classes of mpsw_profile / mpsw_profile_read. */
+enum {
+  MPSW_KC_QR = 0,      /* Householder QR factorisations (L->R sweep and SVD) */
+  MPSW_KC_JACOBI = 1,  /* one-sided Jacobi sweeps of the SVD */
+  MPSW_KC_GEMM = 2,    /* contractions */
+  MPSW_KC_APPLYQ = 3,  /* Q_{k-1} applied to U Sigma */
+  MPSW_KC_APPLYV = 4,  /* reflectors applied to the right singular vectors */
+  MPSW_KC_COUNT = 5
+};
+
+/* Launch statistics of one kernel class since the last mpsw_profile call. */
+typedef struct {
+  int64_t launches;  /* launches timed with events (0 unless this class is the timed one) */
+  double total_ms;   /* summed event time of those launches */
+  double alg_flops;  /* algorithmic flops of every launch of the class, all shots:
+                        QR 2mn^2 - 2n^3/3 (m x n, m >= n); Jacobi 9c^3 (c x c factor);
+                        GEMM 2MNK; reflector application 4mnr - 2n^2 r */
+} mpsw_kprof;
+
+/* Reset the counters of every class and time each launch of class `kclass`
+ * (-1: none) with a pair of events on the state's stream until the next call.
+ * Synchronises.  Errors: EINVAL, EHIP. */
+int mpsw_profile(mpsw_state st, int kclass);
+
+/* Read the counters of class `kclass`.  Synchronises.  Errors: EINVAL, EHIP. */
+int mpsw_profile_read(mpsw_state st, int kclass, mpsw_kprof* out);
 
 /* Number of shots and sites of the state. */
 int mpsw_get_shape(mpsw_state st, int* nshots, int* nsites);

@@ -358,6 +358,8 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
     if (w == 0 && t == 0) raise_err(c, MPSW_DEV_ERR_CAP);
     return;
   }
+  if (w == 0 && t == 0)   // Householder QR of an m x n matrix, m >= n
+    count_flops(c, shot, MPSW_KC_QR, 2.0 * m * (double)n * n - 2.0 * (double)n * n * n / 3.0);
   // the two QRs of one SVD use disjoint flag ranges
   int* flags = shot_sync(c, shot) + MPSW_SYNC_FLAGS + (a.op == 2 ? (MPSW_SYNC_STRIDE - MPSW_SYNC_FLAGS) / 2 : 0);
   extern __shared__ double lds[];
@@ -521,6 +523,8 @@ __global__ __launch_bounds__(1024) void k_applyq(const DevCtx* __restrict__ cp, 
     return;
   }
   __shared__ double red[2 * 16 * 16];
+  if (w == 0 && t == 0)   // n reflectors of length <= m applied to r columns
+    count_flops(c, shot, MPSW_KC_APPLYQ, 4.0 * m * (double)n * r - 2.0 * (double)n * n * r);
   for (int e = t; e < m * cw; e += QNT) {
     const int row = e / cw, qq = e % cw;
     M[(int64_t)row * r + col0 + qq] = (row < n) ? US[(int64_t)row * r + col0 + qq] : 0.0;
@@ -564,6 +568,8 @@ __global__ __launch_bounds__(1024) void k_applyv(const DevCtx* __restrict__ cp, 
     return;
   }
   __shared__ double red[2 * 16 * 16];
+  if (w == 0 && t == 0)   // m reflectors of length <= n applied to r columns
+    count_flops(c, shot, MPSW_KC_APPLYV, 4.0 * n * (double)m * r - 2.0 * (double)m * m * r);
   for (int e = t; e < n * cw; e += QNT) {
     const int row = e / cw, qq = e % cw;
     Y[(int64_t)row * r + col0 + qq] = (row < m) ? Vp[(int64_t)(col0 + qq) * m + row] : 0.0;
@@ -688,6 +694,8 @@ __global__ __launch_bounds__(512) void k_jac(const DevCtx* __restrict__ cp, OpAr
   fro = 0.0;
   for (int i = 0; i < nwv; ++i) fro += fro_red[i];
   const double floor2 = 1e-28 * fro;
+  // the eigen stage of an SVD of a c x c factor, 9 c^3 by the standard count
+  if (ok && w == 0 && t == 0) count_flops(c, shot, MPSW_KC_JACOBI, 9.0 * (double)cc * cc * cc);
   for (int sweep = 0; sweep < MPSW_MAX_SWEEPS; ++sweep) {
     for (int rnd = 0; rnd < nbe - 1; ++rnd) {
       if (ok && w < pact && cc > 1) {

@@ -176,6 +176,7 @@ __global__ __launch_bounds__(256) void k_gemm(const DevCtx* __restrict__ cp, OpA
   if (z == 0 && blockIdx.x == 0 && threadIdx.x == 0 && d.nbatch > (int)gridDim.y) raise_err(c, MPSW_DEV_ERR_GRID);
   const int tn = (d.N + 63) >> 6, tm = (d.M + 63) >> 6;
   if (blockIdx.x == 0 && threadIdx.x == 0 && (int64_t)tm * tn > (int64_t)gridDim.x) raise_err(c, MPSW_DEV_ERR_GRID);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !d.copy) count_flops(c, shot, MPSW_KC_GEMM, 2.0 * d.M * d.N * d.K);
   if ((int)blockIdx.x >= tm * tn) return;
   const int m0 = (blockIdx.x / tn) * 64, n0 = (blockIdx.x % tn) * 64;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;

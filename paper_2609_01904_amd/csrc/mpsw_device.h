@@ -12,6 +12,10 @@ __device__ __forceinline__ double* shot_reals(const DevCtx& c, int shot) { retur
 __device__ __forceinline__ double* shot_eng(const DevCtx& c, int shot) { return c.eng + (int64_t)shot * c.L.stride; }
 __device__ __forceinline__ double* shot_mps(const DevCtx& c, int shot) { return c.mps + (int64_t)shot * c.mps_stride; }
 __device__ __forceinline__ void raise_err(const DevCtx& c, int bit) { atomicOr(c.err, bit); }
+// Algorithmic flops of one launch (counted once per shot by one thread).
+__device__ __forceinline__ void count_flops(const DevCtx& c, int shot, int cls, double f) {
+  atomicAdd(shot_reals(c, shot) + ShotRealLayout::alg_flops + cls, f);
+}
 
 // ---------------------------------------------------------------------------
 // Reductions

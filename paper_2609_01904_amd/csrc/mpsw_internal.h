@@ -22,6 +22,14 @@
 #define MPSW_DEV_ERR_GRID 4       // a launch grid was smaller than the live work
 #define MPSW_DEV_ERR_TIMEOUT 8    // a bounded inter-workgroup wait gave up
 
+// Kernel classes for the algorithmic-flop counters and event timing.
+#define MPSW_KC_QR 0       // Householder QR factorisations (sweep and SVD)
+#define MPSW_KC_JACOBI 1   // one-sided Jacobi sweeps
+#define MPSW_KC_GEMM 2     // contractions (GEMM-shaped)
+#define MPSW_KC_APPLYQ 3   // Q_{k-1} applied to U Sigma
+#define MPSW_KC_APPLYV 4   // Q1 applied to V' (wide bond matrices)
+#define MPSW_KC_COUNT 5
+
 // Per-shot synchronisation area (ints) used by the multi-workgroup kernels.
 #define MPSW_SYNC_STRIDE 1024
 #define MPSW_SYNC_BARRIER 0       // barrier arrival counter
@@ -50,7 +58,8 @@ struct ShotRealLayout {
   static constexpr int eps = 0;
   static constexpr int tail2 = 1;     // [3]
   static constexpr int sigma_log = 4; // [3][MAXK][32]: leading singular values of the last step
-  static constexpr int size = sigma_log + 3 * MPSW_MAXK * 32;
+  static constexpr int alg_flops = sigma_log + 3 * MPSW_MAXK * 32;  // [MPSW_KC_COUNT] per kernel class
+  static constexpr int size = alg_flops + 8;
 };
 
 // Capacities (doubles) and offsets of one engine's buffers inside a shot arena.

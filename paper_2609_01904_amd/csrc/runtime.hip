@@ -308,6 +308,10 @@ struct mpsw_state_s {
   int64_t off_mps[MPSW_NSLOT][MPSW_MAXK];
   int64_t cap_mps[MPSW_NSLOT][MPSW_MAXK];
   Grids g;
+  // event timing of one kernel class (mpsw_profile)
+  int prof_cls = -1;
+  std::vector<hipEvent_t> prof_ev;
+  size_t prof_used = 0;
 };
 
 namespace {
@@ -319,7 +323,31 @@ int check_dev_err(mpsw_state st) {
   if (e & MPSW_DEV_ERR_NONFINITE) return fail(MPSW_ENONFINITE, "non-finite singular value encountered");
   if (e & (MPSW_DEV_ERR_CAP | MPSW_DEV_ERR_GRID))
     return fail(MPSW_ENOMEM, "a live size exceeded the workspace (device error bits " + std::to_string(e) + ")");
+  if (e & MPSW_DEV_ERR_TIMEOUT)
+    return fail(MPSW_EHIP, "a bounded inter-workgroup wait gave up (device error bits " + std::to_string(e) + ")");
   return MPSW_OK;
+}
+
+// Brackets the launches of kernel class `cls` with events when it is the
+// timed class.
+template <class F>
+void prof(mpsw_state st, int cls, hipStream_t s, F&& launch) {
+  if (st->prof_cls != cls) {
+    launch();
+    return;
+  }
+  while (st->prof_ev.size() < st->prof_used + 2) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) {
+      launch();
+      return;
+    }
+    st->prof_ev.push_back(ev);
+  }
+  hipEventRecord(st->prof_ev[st->prof_used], s);
+  launch();
+  hipEventRecord(st->prof_ev[st->prof_used + 1], s);
+  st->prof_used += 2;
 }
 
 // device context for the main (step) engine
@@ -454,10 +482,10 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
       g.site = k;
       g.op = G_KRON_R1;
       g.aux = rd;
-      launch_gemm(d, g, tiles(2 * R[k], (int64_t)D[k + 1] * p2(K - k - 1)), 1, nshots, strm);
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(2 * R[k], (int64_t)D[k + 1] * p2(K - k - 1)), 1, nshots, strm); });
       g.op = G_KRON_R2;
       g.aux = wr;
-      launch_gemm(d, g, tiles(D[k], p2(K - k - 1)), (int)(2 * R[k]), nshots, strm);
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(D[k], p2(K - k - 1)), (int)(2 * R[k]), nshots, strm); });
     }
   }
   for (int k = 0; k < K; ++k) {
@@ -469,22 +497,22 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
     if (kind == K_LAPLACE || kind == K_SUM) {
       g.op = G_L2R_EXPLICIT;
       g.aux = last ? 1 : 0;
-      launch_gemm(d, g, tiles(s.rt[k], 2 * s.rin[k + 1]), 1, nshots, strm);
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(s.rt[k], 2 * s.rin[k + 1]), 1, nshots, strm); });
     } else if (kind == K_C2 && k < n) {
       g.op = G_KRON_L1;
-      launch_gemm(d, g, tiles(D[k], 2 * R[k + 1]), (int)s.rt[k], nshots, strm);
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(D[k], 2 * R[k + 1]), (int)s.rt[k], nshots, strm); });
       g.op = G_KRON_L2;
-      launch_gemm(d, g, tiles(R[k + 1], D[k + 1]), (int)(2 * s.rt[k]), nshots, strm);
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(R[k + 1], D[k + 1]), (int)(2 * s.rt[k]), nshots, strm); });
       if (k == n - 1) {
         g.op = G_MEET;
         g.aux = (K - n) & 1;
-        launch_gemm(d, g, tiles(2 * s.rt[k], p2(K - n)), 1, nshots, strm);
+        prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(2 * s.rt[k], p2(K - n)), 1, nshots, strm); });
         meet = true;
       }
     } else {
       g.op = G_COPY_RX;
       g.aux = last ? 1 : 0;
-      launch_gemm(d, g, tiles(s.rt[k], s.rin[k]), 1, nshots, strm);
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(s.rt[k], s.rin[k]), 1, nshots, strm); });
     }
     if (!last) {
       const int64_t mcap = 2 * s.rt[k], ncap = s.rin[k + 1];
@@ -496,7 +524,7 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
       q.op = 0;
       q.aux = meet ? 1 : 0;
       launch_sync_reset(d, nshots, strm);
-      launch_qrf(d, q, bw, nwg, nshots, (size_t)mcap * bw * 8, strm);
+      prof(st, MPSW_KC_QR, strm, [&] { launch_qrf(d, q, bw, nwg, nshots, (size_t)mcap * bw * 8, strm); });
     }
   }
   for (int k = K - 1; k >= 1; --k) {
@@ -511,27 +539,27 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
     const int bw1 = qr_panel(rows), bw2 = qr_panel(ccap);
     OpArgs q = v;
     q.op = 1;
-    launch_qrf(d, q, bw1, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(ccap, bw1))), nshots,
-               (size_t)rows * bw1 * 8, strm);
+    prof(st, MPSW_KC_QR, strm, [&] { launch_qrf(d, q, bw1, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(ccap, bw1))), nshots,
+               (size_t)rows * bw1 * 8, strm); });
     q.op = 2;
-    launch_qrf(d, q, bw2, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(ccap, bw2))), nshots,
-               (size_t)ccap * bw2 * 8, strm);
+    prof(st, MPSW_KC_QR, strm, [&] { launch_qrf(d, q, bw2, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(ccap, bw2))), nshots,
+               (size_t)ccap * bw2 * 8, strm); });
     const int b = jac_block(ccap);
     const int64_t nb = cdiv(ccap, b);
-    launch_jac(d, v, b, (int)std::max<int64_t>(1, (nb + (nb & 1)) / 2), nshots, (size_t)2 * b * (ccap + 1) * 8, ccap, strm);
+    prof(st, MPSW_KC_JACOBI, strm, [&] { launch_jac(d, v, b, (int)std::max<int64_t>(1, (nb + (nb & 1)) / 2), nshots, (size_t)2 * b * (ccap + 1) * 8, ccap, strm); });
     launch_jacfin(d, v, nshots, strm);
-    launch_applyv(d, v, bw1, std::max(1, cdiv(s.rho[k], bw1)), nshots, strm);
+    prof(st, MPSW_KC_APPLYV, strm, [&] { launch_applyv(d, v, bw1, std::max(1, cdiv(s.rho[k], bw1)), nshots, strm); });
     OpArgs g{};
     g.shot = -1;
     g.site = k;
     g.slot = out_slot;
     g.op = G_US;
-    launch_gemm(d, g, tiles(s.rt[k], s.rho[k]), 1, nshots, strm);
+    prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(s.rt[k], s.rho[k]), 1, nshots, strm); });
     OpArgs ap{};
     ap.shot = -1;
     ap.site = k;
     const int bwq = qr_panel(2 * s.rt[k - 1]);
-    launch_applyq(d, ap, bwq, std::max(1, cdiv(s.rho[k], bwq)), nshots, strm);
+    prof(st, MPSW_KC_APPLYQ, strm, [&] { launch_applyq(d, ap, bwq, std::max(1, cdiv(s.rho[k], bwq)), nshots, strm); });
   }
   OpArgs f{};
   f.shot = -1;
@@ -859,6 +887,7 @@ int mpsw_destroy(mpsw_state st) {
   hipFree(st->sync);
   hipFree(st->eng.eng);
   hipFree(st->eng.d);
+  for (hipEvent_t ev : st->prof_ev) hipEventDestroy(ev);
   delete st;
   return MPSW_OK;
 }
@@ -1052,6 +1081,39 @@ int mpsw_get_stats(mpsw_state st, int shot, mpsw_stats* out) {
 //         (the identity merge when m <= n: Q = I, R = A);
 //   op 1: SVD of A (m x n, n even): out1 = V^T (r x n), out2 = U Sigma (m x r),
 //         r = min(m, n) (no truncation); returns r.
+int mpsw_profile(mpsw_state st, int kclass) {
+  if (!st || kclass < -1 || kclass >= MPSW_KC_COUNT) return fail(MPSW_EINVAL, "invalid state or kernel class");
+  HIP_TRY(hipStreamSynchronize(st->stream));
+  std::vector<double> r((size_t)RL::size * st->B);
+  HIP_TRY(hipMemcpy(r.data(), st->reals, r.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int i = 0; i < st->B; ++i)
+    for (int c = 0; c < MPSW_KC_COUNT; ++c) r[(size_t)i * RL::size + RL::alg_flops + c] = 0.0;
+  HIP_TRY(hipMemcpy(st->reals, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice));
+  st->prof_cls = kclass;
+  st->prof_used = 0;
+  return MPSW_OK;
+}
+
+int mpsw_profile_read(mpsw_state st, int kclass, mpsw_kprof* out) {
+  if (!st || !out || kclass < 0 || kclass >= MPSW_KC_COUNT) return fail(MPSW_EINVAL, "invalid arguments");
+  HIP_TRY(hipStreamSynchronize(st->stream));
+  std::vector<double> r((size_t)RL::size * st->B);
+  HIP_TRY(hipMemcpy(r.data(), st->reals, r.size() * sizeof(double), hipMemcpyDeviceToHost));
+  out->alg_flops = 0.0;
+  for (int i = 0; i < st->B; ++i) out->alg_flops += r[(size_t)i * RL::size + RL::alg_flops + kclass];
+  out->launches = 0;
+  out->total_ms = 0.0;
+  if (kclass == st->prof_cls) {
+    for (size_t i = 0; i + 1 < st->prof_used; i += 2) {
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, st->prof_ev[i], st->prof_ev[i + 1]));
+      out->total_ms += ms;
+      ++out->launches;
+    }
+  }
+  return MPSW_OK;
+}
+
 int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, double* out2) {
   if (!A || !out1 || !out2 || m < 1 || n < 1 || m > 4096 || n > 4096) return fail(MPSW_EINVAL, "bad argument");
   if (op == 0 && (m & 1)) return fail(MPSW_EINVAL, "QR test needs an even row count");

@@ -21,8 +21,11 @@ EXPORTS = [
     "mpsw_create_state", "mpsw_create_batch", "mpsw_set_velocity_dense", "mpsw_set_velocity_mpo",
     "mpsw_set_source", "mpsw_set_fields", "mpsw_step", "mpsw_to_dense", "mpsw_get_bonds",
     "mpsw_get_stats", "mpsw_get_shape", "mpsw_destroy", "mpsw_last_error", "mpsw_debug_laplacian_mpo",
-    "mpsw_debug_factor",
+    "mpsw_debug_factor", "mpsw_profile", "mpsw_profile_read",
 ]
+
+KC_QR, KC_JACOBI, KC_GEMM, KC_APPLYQ, KC_APPLYV = 0, 1, 2, 3, 4
+KC_NAMES = {KC_QR: "qr", KC_JACOBI: "jacobi", KC_GEMM: "gemm", KC_APPLYQ: "applyq", KC_APPLYV: "applyv"}
 
 
 class MpswError(RuntimeError):
@@ -42,6 +45,10 @@ class Stats(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("nsites", ctypes.c_int), ("bonds", ctypes.c_int * 64),
                 ("max_exact_bond", ctypes.c_int * 3), ("tail2", ctypes.c_double * 3),
                 ("fallbacks", ctypes.c_int64), ("max_jacobi_sweeps", ctypes.c_int)]
+
+
+class KProf(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("alg_flops", ctypes.c_double)]
 
 
 _lib = None
@@ -72,6 +79,8 @@ def load():
         "mpsw_destroy": [P],
         "mpsw_debug_laplacian_mpo": [I, I, P, P, ctypes.c_int64],
         "mpsw_debug_factor": [I, I, I, P, P, P],
+        "mpsw_profile": [P, I],
+        "mpsw_profile_read": [P, I, ctypes.POINTER(KProf)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -183,6 +192,16 @@ class State:
         return {"step": s.step, "bonds": list(s.bonds[: self.K + 1]),
                 "max_exact_bond": list(s.max_exact_bond), "tail2": list(s.tail2),
                 "fallbacks": s.fallbacks, "max_jacobi_sweeps": s.max_jacobi_sweeps}
+
+
+    def profile(self, kclass=-1):
+        """Reset the per-class flop counters; time launches of `kclass` with events."""
+        _check(load().mpsw_profile(self._h, int(kclass)))
+
+    def profile_read(self, kclass):
+        p = KProf()
+        _check(load().mpsw_profile_read(self._h, int(kclass), ctypes.byref(p)))
+        return {"launches": int(p.launches), "total_ms": float(p.total_ms), "alg_flops": float(p.alg_flops)}
 
 
 def debug_laplacian_mpo(n, boundary=MPSW_PERIODIC):

@@ -12,10 +12,11 @@ depth / position as described there).
 """
 from .velocity import layered_fault_velocity, constant_velocity
 from .wavelet import ricker, impulse
-from .fields import plane_wave_fields, random_fields, random_mps_cores
+from .fields import plane_wave_fields, random_fields, random_mps_cores, wavefront_fields
 from .configs import CONFIGS, get_config
 
 __all__ = [
     "layered_fault_velocity", "constant_velocity", "ricker", "impulse",
-    "plane_wave_fields", "random_fields", "random_mps_cores", "CONFIGS", "get_config",
+    "plane_wave_fields", "random_fields", "random_mps_cores", "wavefront_fields", "CONFIGS",
+    "get_config",
 ]

@@ -59,3 +59,35 @@ def random_mps_cores(K, bonds, seed=0):
     rng = np.random.default_rng(seed)
     return [rng.standard_normal((bonds[k], 2, bonds[k + 1])) / np.sqrt(2 * bonds[k])
             for k in range(K)]
+
+
+def wavefront_fields(n, seed=0, nfronts=48, dh=10.0, dt=1e-3, f0=15.0, vmin=1500.0, vmax=4500.0):
+    """(u^{-1}, u^0) of a developed wavefield: a seeded superposition of
+    expanding circular Ricker wavefronts.
+
+    Front j has centre p_j (uniform over the grid), radius R_j, speed c_j and
+    amplitude a_j / sqrt(R_j / dh) (cylindrical spreading); its profile is the
+    Ricker shape of the travel-time offset tau = (|p - p_j| - R_j - c_j t) / c_j.
+    u^0 is the field at t = 0 and u^{-1} at t = -dt.  Used as a saturated
+    starting state (all bonds at the chi cap) for timing steady-state steps.
+    """
+    rng = np.random.default_rng(seed)
+    N = 1 << n
+    X = N * dh
+    cx = rng.uniform(0.0, X, nfronts)
+    cz = rng.uniform(0.0, X, nfronts)
+    R = rng.uniform(0.05 * X, 0.8 * X, nfronts)
+    c = rng.uniform(vmin, vmax, nfronts)
+    amp = rng.uniform(0.5, 1.0, nfronts) * rng.choice([-1.0, 1.0], nfronts)
+    x = (np.arange(N) * dh)[:, None]
+    z = (np.arange(N) * dh)[None, :]
+    out = []
+    for t in (-dt, 0.0):
+        u = np.zeros((N, N))
+        for j in range(nfronts):
+            dist = np.sqrt((x - cx[j]) ** 2 + (z - cz[j]) ** 2)
+            tau = (dist - R[j] - c[j] * t) / c[j]
+            a = (np.pi * f0 * tau) ** 2
+            u += amp[j] / np.sqrt(R[j] / dh) * (1.0 - 2.0 * a) * np.exp(-a)
+        out.append(u)
+    return out[0], out[1]
