@@ -14,20 +14,26 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace mpsw {
 
 #define MPSW_SPIN_LIMIT (1 << 22)
 #define MPSW_PERM_MAX 1024
 #define QNT 1024   // threads of the QR-family kernels
+#define MPSW_APPLY_LDS (16 * 256 + 256)   // doubles of LDS for apply_reflector
 
 __device__ __forceinline__ int ld_acquire(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One thread waits until *p >= v (bounded).
+// One thread waits until *p >= v (bounded).  The spin uses relaxed loads and
+// a single acquire fence follows: an acquire load per spin would invalidate
+// the L2 of the waiting workgroup's XCD on every iteration, evicting the data
+// every other workgroup on that XCD is working on.
 __device__ void wait_geq(const DevCtx& c, const int* p, int v) {
   int it = 0;
-  while (ld_acquire(p) < v) {
+  while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) {
     if ((++it & 127) == 0) {
       const int e = __hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (it > MPSW_SPIN_LIMIT || (e & MPSW_DEV_ERR_TIMEOUT)) {
@@ -37,6 +43,7 @@ __device__ void wait_geq(const DevCtx& c, const int* p, int v) {
     }
     __builtin_amdgcn_s_sleep(1);
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 // Barrier of the nwg workgroups of one shot (arrival counter, monotone).
@@ -47,7 +54,7 @@ __device__ void shot_barrier(const DevCtx& c, int* ctr, int nwg, int& epoch) {
   __syncthreads();
   ++epoch;
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(ctr, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     wait_geq(c, ctr, epoch * nwg);
   }
   __syncthreads();
@@ -60,78 +67,99 @@ __global__ void k_sync_reset(const DevCtx* __restrict__ cp) {
 }
 
 // ---------------------------------------------------------------------------
-// Block reflector application on column-major storage.
+// Block reflector application on the FP64 matrix cores, 1024 threads.
 // V: unit lower trapezoidal (mj x bw), element (r, p) at V[r + ldv * p] for r > p.
-// C: mj x bwc, element (r, q) at C[r * crs + q * ccs].
-// C <- C - V op(T) V^T C with op(T) = T^T (trans) or T; T is bw x bw upper, row-major ld BW.
-// Thread layout: t = q * RS + rs (RS = NT / BW row slices per column; a slice
-// group never straddles a wave).
+// C: mj x bwc (bwc <= 16), element (r, q) at C[r * crs + q * ccs].
+// C <- C - V op(T) V^T C with op(T) = T^T (trans) or T; T is bw x bw upper,
+// row-major with leading dimension BW.
+//
+// Both products are 16 x 16 tiles of v_mfma_f64_16x16x4f64 (operand lanes:
+// a = A[l % 16][l / 16], b = B[l / 16][l % 16]; result D[l / 16 + 4 v][l % 16]),
+// padded with zeros beyond bw and bwc.  Phase 1 (W = V^T C) splits the rows
+// over the 16 waves, four rows per product and UN products in flight per wave,
+// then sums the 16 partial tiles in a fixed order; phase 2 (C -= V W2) gives
+// each wave 16-row tiles of C.  wsp: LDS of >= 16 * 256 + 256 doubles.
 // ---------------------------------------------------------------------------
-template <int BW, int NT>
+typedef double mpsw_d4 __attribute__((ext_vector_type(4)));
+
+template <int BW>
 __device__ void apply_reflector(const double* __restrict__ V, int64_t ldv, double* C, int64_t crs, int64_t ccs,
-                                int mj, int bw, int bwc, const double* __restrict__ T, bool trans,
-                                double* red /* LDS >= BW*(NT/64) + BW*BW */) {
-  constexpr int RS = NT / BW;
-  const int t = threadIdx.x;
-  const int q = t / RS, rs = t % RS;
-  double acc[BW];
+                                int mj, int bw, int bwc, const double* __restrict__ T, bool trans, double* wsp) {
+  static_assert(BW <= 16, "panel wider than one matrix-core tile");
+  const int t = threadIdx.x, l = t & 63, wv = t >> 6;
+  const int li = l & 15, lk = l >> 4;
+  // unit lower trapezoid of V, zero beyond the panel width
+  auto vfull = [&](int r, int p) -> double {
+    if (r >= mj || p >= bw) return 0.0;
+    const double v = V[r + ldv * p];   // inside the factored matrix for every r < mj
+    return (r > p) ? v : ((r == p) ? 1.0 : 0.0);
+  };
+  constexpr int UN = 4;
+  const int nsteps = (mj + 3) >> 2;
+  mpsw_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int s0 = wv; s0 < nsteps; s0 += 16 * UN) {
+    double av[UN], bv[UN];
 #pragma unroll
-  for (int p = 0; p < BW; ++p) acc[p] = 0.0;
-  if (q < bwc) {
-    for (int r = rs; r < mj; r += RS) {
-      const double cv = C[(int64_t)r * crs + (int64_t)q * ccs];
-#pragma unroll
-      for (int p = 0; p < BW; ++p) {
-        double v = 0.0;
-        if (p < bw) v = (r > p) ? V[r + ldv * p] : ((r == p) ? 1.0 : 0.0);
-        acc[p] = fma(v, cv, acc[p]);
-      }
+    for (int u = 0; u < UN; ++u) {
+      const int r = 4 * (s0 + 16 * u) + lk;
+      av[u] = vfull(r, li);
+      bv[u] = (r < mj && li < bwc) ? C[(int64_t)r * crs + (int64_t)li * ccs] : 0.0;
     }
-  }
-  // reduce over the RS row slices: whole waves per column, then the WPC
-  // wave partials of a column in a fixed order (bitwise reproducible)
-  static_assert(RS % 64 == 0, "row slices of a column must fill whole waves");
-  constexpr int WPC = RS / 64;
-  double* Wp = red;            // [BW][BW][WPC] wave partials
-  double* W2 = red + BW * BW * WPC;
-  const int wq = rs >> 6;
 #pragma unroll
-  for (int p = 0; p < BW; ++p) {
-    const double v = wave_sum64(acc[p]);
-    if ((t & 63) == 0) Wp[(p * BW + q) * WPC + wq] = v;
+    for (int u = 0; u < UN; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
   }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) wsp[wv * 256 + (lk + 4 * v) * 16 + li] = acc[v];
   __syncthreads();
-  if (t < BW * BW) {
-    const int p = t / BW, qq = t % BW;
-    auto Wv = [&](int s2) {
-      double x = 0.0;
-#pragma unroll
-      for (int u = 0; u < WPC; ++u) x += Wp[(s2 * BW + qq) * WPC + u];
-      return x;
-    };
+  double* W2 = wsp + 16 * 256;
+  if (t < 256) {
     double s = 0.0;
-    if (trans) {   // (T^T W)[p][q] = sum_{s<=p} T[s][p] W[s][q]
-      for (int s2 = 0; s2 <= p && s2 < bw; ++s2) s = fma(T[s2 * BW + p], Wv(s2), s);
-    } else {       // (T W)[p][q] = sum_{s>=p} T[p][s] W[s][q]
-      for (int s2 = p; s2 < bw; ++s2) s = fma(T[p * BW + s2], Wv(s2), s);
-    }
-    W2[p * BW + qq] = s;
+    for (int w = 0; w < 16; ++w) s += wsp[w * 256 + t];
+    wsp[t] = s;   // W[p][q], p = t / 16, q = t % 16
   }
   __syncthreads();
-  if (q < bwc) {
-    double w2[BW];
-#pragma unroll
-    for (int p = 0; p < BW; ++p) w2[p] = W2[p * BW + q];
-    for (int r = rs; r < mj; r += RS) {
-      double s = 0.0;
-#pragma unroll
-      for (int p = 0; p < BW; ++p) {
-        if (p < bw) {
-          const double v = (r > p) ? V[r + ldv * p] : ((r == p) ? 1.0 : 0.0);
-          s = fma(v, w2[p], s);
-        }
+  if (t < 256) {
+    const int p = t >> 4, q = t & 15;
+    double s = 0.0;
+    if (p < bw) {
+      if (trans) {   // (T^T W)[p][q] = sum_{s<=p} T[s][p] W[s][q]
+        for (int s2 = 0; s2 <= p; ++s2) s = fma(T[s2 * BW + p], wsp[s2 * 16 + q], s);
+      } else {       // (T W)[p][q] = sum_{s>=p} T[p][s] W[s][q]
+        for (int s2 = p; s2 < bw; ++s2) s = fma(T[p * BW + s2], wsp[s2 * 16 + q], s);
       }
-      C[(int64_t)r * crs + (int64_t)q * ccs] -= s;
+    }
+    W2[t] = s;
+  }
+  __syncthreads();
+  // phase 2: C[r][q] -= sum_p V[r][p] W2[p][q], 16-row tiles
+  double bk[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) bk[kk] = W2[(4 * kk + lk) * 16 + li];
+  const int ntile = (mj + 15) >> 4;
+  for (int tb = wv; tb < ntile; tb += 32) {
+    double av[2][4], cv[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r0 = 16 * (tb + 16 * h);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) av[h][kk] = (4 * kk < bw) ? vfull(r0 + li, 4 * kk + lk) : 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + lk + 4 * v;
+        cv[h][v] = (r < mj && li < bwc) ? C[(int64_t)r * crs + (int64_t)li * ccs] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      mpsw_d4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) d = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h][kk], bk[kk], d, 0, 0, 0);
+      const int r0 = 16 * (tb + 16 * h);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + lk + 4 * v;
+        if (r < mj && li < bwc) C[(int64_t)r * crs + (int64_t)li * ccs] = cv[h][v] - d[v];
+      }
     }
   }
   __syncthreads();
@@ -153,10 +181,9 @@ __device__ void factor_panel(const DevCtx& c, double* S, int m, int n, int j, do
   const int bw = min(BW, n - c0);
   const int t = threadIdx.x;
   double* Pn = lds;  // mj x bw, ld mj
-  for (int e = t; e < mj * bw; e += NT) {
-    const int qq = e / mj, r = e % mj;
-    Pn[r + (int64_t)mj * qq] = S[r0 + r + (int64_t)m * (c0 + qq)];
-  }
+  bulk_copy<8>(mj * bw, t, NT,
+               [&](int e) { return S[r0 + (int)(e % mj) + (int64_t)m * (c0 + (int)(e / mj))]; },
+               [&](int e, double v) { Pn[e] = v; });
   __shared__ double taus[16], betas[16], scales[16];
   __shared__ double part[NT / 64];
   __syncthreads();
@@ -270,10 +297,8 @@ __device__ void factor_panel(const DevCtx& c, double* S, int m, int n, int j, do
   }
   for (int e = bw + t; e < BW; e += NT)   // unused columns of a ragged panel
     for (int p = 0; p < BW; ++p) T[(int64_t)j * BW * BW + p * BW + e] = 0.0;
-  for (int e = t; e < mj * bw; e += NT) {
-    const int qq = e / mj, r = e % mj;
-    S[r0 + r + (int64_t)m * (c0 + qq)] = Pn[r + (int64_t)mj * qq];
-  }
+  bulk_copy<8>(mj * bw, t, NT, [&](int e) { return Pn[e]; },
+               [&](int e, double v) { S[r0 + (int)(e % mj) + (int64_t)m * (c0 + (int)(e / mj))] = v; });
   __syncthreads();
 }
 
@@ -421,16 +446,17 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
   for (int blk = w; blk < nbk; blk += P) {
     const int c0 = blk * BW, bw = min(BW, n - c0);
     if (xc == 1 && !pivot) {
-      for (int e = t; e < m * bw; e += QNT) {
-        const int r = e / bw, qq = e % bw;
-        S[r + (int64_t)m * (c0 + qq)] = X[(int64_t)r * xr + c0 + qq];
-      }
+      bulk_copy<8>(m * bw, t, QNT,
+                   [&](int e) { return X[(e / bw) * xr + c0 + (int)(e % bw)]; },
+                   [&](int e, double v) { S[(e / bw) + (int64_t)m * (c0 + (int)(e % bw))] = v; });
     } else {
-      for (int e = t; e < m * bw; e += QNT) {
-        const int qq = e / m, r = e % m;
-        const int src = pivot ? perm[c0 + qq] : c0 + qq;
-        S[r + (int64_t)m * (c0 + qq)] = X[(int64_t)r * xr + (int64_t)src * xc];
-      }
+      bulk_copy<8>(m * bw, t, QNT,
+                   [&](int e) {
+                     const int qq = (int)(e / m), r = (int)(e % m);
+                     const int src = pivot ? perm[c0 + qq] : c0 + qq;
+                     return X[(int64_t)r * xr + (int64_t)src * xc];
+                   },
+                   [&](int e, double v) { S[(e % m) + (int64_t)m * (c0 + (int)(e / m))] = v; });
     }
   }
   __syncthreads();
@@ -441,8 +467,8 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
   auto apply = [&](int j, int blk) {
     const int r0 = j * BW, c0 = j * BW, bw = min(BW, n - c0);
     const int cb = blk * BW, bwc = min(BW, n - cb);
-    apply_reflector<BW, QNT>(S + r0 + (int64_t)m * c0, m, S + r0 + (int64_t)m * cb, 1, m, m - r0, bw, bwc,
-                        T + (int64_t)j * BW * BW, true, red);
+    apply_reflector<BW>(S + r0 + (int64_t)m * c0, m, S + r0 + (int64_t)m * cb, 1, m, m - r0, bw, bwc,
+                        T + (int64_t)j * BW * BW, true, lds);
   };
   if (w == 0) {
     factor_panel<BW, QNT>(c, S, m, n, 0, T, lds, red);
@@ -470,12 +496,16 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
   // R (n x n) from my columns: row-major R (sweep) or R^T column-major (SVD)
   for (int blk = w; blk < nbk; blk += P) {
     const int c0 = blk * BW, bw = min(BW, n - c0);
-    for (int e = t; e < n * bw; e += QNT) {
-      const int r = e / bw, qq = e % bw, col = c0 + qq;
-      const double v = (r <= col) ? S[r + (int64_t)m * col] : 0.0;
-      if (sweep) Rout[(int64_t)r * n + col] = v;
-      else Rout[col + (int64_t)n * r] = v;
-    }
+    bulk_copy<8>(n * bw, t, QNT,
+                 [&](int e) {
+                   const int r = (int)(e / bw), col = c0 + (int)(e % bw);
+                   return (r <= col) ? S[r + (int64_t)m * col] : 0.0;
+                 },
+                 [&](int e, double v) {
+                   const int r = (int)(e / bw), col = c0 + (int)(e % bw);
+                   if (sweep) Rout[(int64_t)r * n + col] = v;
+                   else Rout[col + (int64_t)n * r] = v;
+                 });
   }
   if (sweep && w == 0 && t == 0) {
     dm[DL::rt + k + 1] = n;
@@ -504,15 +534,13 @@ __global__ __launch_bounds__(1024) void k_applyq(const DevCtx* __restrict__ cp, 
     if (w == 0 && t == 0) raise_err(c, MPSW_DEV_ERR_CAP);
     return;
   }
-  constexpr int CW = BW;
+  constexpr int CW = 16;   // columns per workgroup: one matrix-core tile
   const int col0 = w * CW;
   if (col0 >= r) return;
   const int cw = min(CW, r - col0);
   if (dm[DL::qid + k - 1]) {  // identity: rt_k = 2 rt_{k-1}, same memory shape
-    for (int e = t; e < m * cw; e += QNT) {
-      const int row = e / cw, qq = e % cw;
-      M[(int64_t)row * r + col0 + qq] = US[(int64_t)row * r + col0 + qq];
-    }
+    bulk_copy<8>(m * cw, t, QNT, [&](int e) { return US[(e / cw) * r + col0 + (int)(e % cw)]; },
+                 [&](int e, double v) { M[(e / cw) * r + col0 + (int)(e % cw)] = v; });
     return;
   }
   const double* S = E + L.off_q[k - 1];
@@ -522,18 +550,17 @@ __global__ __launch_bounds__(1024) void k_applyq(const DevCtx* __restrict__ cp, 
     if (t == 0) raise_err(c, MPSW_DEV_ERR_CAP);
     return;
   }
-  __shared__ double red[2 * 16 * 16];
+  extern __shared__ double wsp[];
   if (w == 0 && t == 0)   // n reflectors of length <= m applied to r columns
     count_flops(c, shot, MPSW_KC_APPLYQ, 4.0 * m * (double)n * r - 2.0 * (double)n * n * r);
-  for (int e = t; e < m * cw; e += QNT) {
-    const int row = e / cw, qq = e % cw;
-    M[(int64_t)row * r + col0 + qq] = (row < n) ? US[(int64_t)row * r + col0 + qq] : 0.0;
-  }
+  bulk_copy<8>(m * cw, t, QNT,
+               [&](int e) { return (e / cw < n) ? US[(e / cw) * r + col0 + (int)(e % cw)] : 0.0; },
+               [&](int e, double v) { M[(e / cw) * r + col0 + (int)(e % cw)] = v; });
   __syncthreads();
   for (int j = nbk - 1; j >= 0; --j) {
     const int r0 = j * BW, c0 = j * BW, bw = min(BW, n - c0);
-    apply_reflector<BW, QNT>(S + r0 + (int64_t)m * c0, m, M + (int64_t)r0 * r + col0, r, 1, m - r0, bw, cw,
-                        T + (int64_t)j * BW * BW, false, red);
+    apply_reflector<BW>(S + r0 + (int64_t)m * c0, m, M + (int64_t)r0 * r + col0, r, 1, m - r0, bw, cw,
+                        T + (int64_t)j * BW * BW, false, wsp);
   }
 }
 
@@ -553,9 +580,9 @@ __global__ __launch_bounds__(1024) void k_applyv(const DevCtx* __restrict__ cp, 
   const int m = dm[DL::rt + k], n = 2 * dm[DL::rho + k + 1], r = dm[DL::rho + k];
   if (m >= n) return;
   const int t = threadIdx.x;
-  const int col0 = w * BW;
+  const int col0 = w * 16;   // columns per workgroup: one matrix-core tile
   if (col0 >= r) return;
-  const int cw = min(BW, r - col0);
+  const int cw = min(16, r - col0);
   const int nbk = (m + BW - 1) / BW;
   double* Y = E + L.off_Yv;           // n x r row-major work
   const double* Vp = E + L.off_Vp;    // r x m
@@ -567,23 +594,23 @@ __global__ __launch_bounds__(1024) void k_applyv(const DevCtx* __restrict__ cp, 
     if (t == 0) raise_err(c, MPSW_DEV_ERR_CAP);
     return;
   }
-  __shared__ double red[2 * 16 * 16];
+  extern __shared__ double wsp[];
   if (w == 0 && t == 0)   // m reflectors of length <= n applied to r columns
     count_flops(c, shot, MPSW_KC_APPLYV, 4.0 * n * (double)m * r - 2.0 * (double)m * m * r);
-  for (int e = t; e < n * cw; e += QNT) {
-    const int row = e / cw, qq = e % cw;
-    Y[(int64_t)row * r + col0 + qq] = (row < m) ? Vp[(int64_t)(col0 + qq) * m + row] : 0.0;
-  }
+  bulk_copy<8>(n * cw, t, QNT,
+               [&](int e) {
+                 const int row = (int)(e / cw), qq = (int)(e % cw);
+                 return (row < m) ? Vp[(int64_t)(col0 + qq) * m + row] : 0.0;
+               },
+               [&](int e, double v) { Y[(e / cw) * r + col0 + (int)(e % cw)] = v; });
   __syncthreads();
   for (int j = nbk - 1; j >= 0; --j) {
     const int r0 = j * BW, c0 = j * BW, bw = min(BW, m - c0);
-    apply_reflector<BW, QNT>(S + r0 + (int64_t)n * c0, n, Y + (int64_t)r0 * r + col0, r, 1, n - r0, bw, cw,
-                        T + (int64_t)j * BW * BW, false, red);
+    apply_reflector<BW>(S + r0 + (int64_t)n * c0, n, Y + (int64_t)r0 * r + col0, r, 1, n - r0, bw, cw,
+                        T + (int64_t)j * BW * BW, false, wsp);
   }
-  for (int e = t; e < n * cw; e += QNT) {
-    const int qq = e / n, row = e % n;
-    core[(int64_t)(col0 + qq) * n + row] = Y[(int64_t)row * r + col0 + qq];
-  }
+  bulk_copy<8>(n * cw, t, QNT, [&](int e) { return Y[(e % n) * r + col0 + (int)(e / n)]; },
+               [&](int e, double v) { core[(int64_t)(col0 + (int)(e / n)) * n + (e % n)] = v; });
 }
 
 // ---------------------------------------------------------------------------
@@ -708,11 +735,10 @@ __global__ __launch_bounds__(512) void k_jac(const DevCtx* __restrict__ cp, OpAr
         const int ncol = np_ + nq_;
         if (t == 0) nrot = 0;
         // load
-        for (int e = t; e < ncol * Lc; e += blockDim.x) {
-          const int jj = e / Lc, i = e % Lc;
-          const int gcol = (jj < np_) ? bp * b + jj : bq * b + (jj - np_);
-          blk[jj * ldl + i] = A[(int64_t)gcol * Lc + i];
-        }
+        auto gcol = [&](int jj) { return (jj < np_) ? bp * b + jj : bq * b + (jj - np_); };
+        bulk_copy<8>(ncol * Lc, t, blockDim.x,
+                     [&](int e) { return A[(int64_t)gcol((int)(e / Lc)) * Lc + (e % Lc)]; },
+                     [&](int e, double v) { blk[(e / Lc) * ldl + (e % Lc)] = v; });
         __syncthreads();
         // one cyclic pass over all column pairs of the loaded block pair; a
         // pair is handled by a group of 16 lanes (4 pairs per wave in flight)
@@ -729,11 +755,8 @@ __global__ __launch_bounds__(512) void k_jac(const DevCtx* __restrict__ cp, OpAr
           __syncthreads();
         }
         // store
-        for (int e = t; e < ncol * Lc; e += blockDim.x) {
-          const int jj = e / Lc, i = e % Lc;
-          const int gcol = (jj < np_) ? bp * b + jj : bq * b + (jj - np_);
-          A[(int64_t)gcol * Lc + i] = blk[jj * ldl + i];
-        }
+        bulk_copy<8>(ncol * Lc, t, blockDim.x, [&](int e) { return blk[(e / Lc) * ldl + (e % Lc)]; },
+                     [&](int e, double v) { A[(int64_t)gcol((int)(e / Lc)) * Lc + (e % Lc)] = v; });
         if (t == 0 && nrot > 0) atomicAdd(sy + MPSW_SYNC_ROT + (sweep & 63), nrot);
       }
       shot_barrier(c, sy + MPSW_SYNC_BARRIER, P, epoch);
@@ -847,6 +870,7 @@ void launch_sync_reset(const DevCtx* d, int nshots, hipStream_t s) {
 }
 
 void launch_qrf(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, size_t lds, hipStream_t s) {
+  lds = std::max(lds, (size_t)MPSW_APPLY_LDS * sizeof(double));   // the panel, or the reflector workspace
   if (bw == 16)
     hipLaunchKernelGGL(k_qrf<16>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
   else if (bw == 8)
@@ -856,21 +880,23 @@ void launch_qrf(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, s
 }
 
 void launch_applyq(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, hipStream_t s) {
+  const size_t lds = (size_t)MPSW_APPLY_LDS * sizeof(double);
   if (bw == 16)
-    hipLaunchKernelGGL(k_applyq<16>, dim3(nwg, 1, nshots), dim3(QNT), 0, s, d, a);
+    hipLaunchKernelGGL(k_applyq<16>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
   else if (bw == 8)
-    hipLaunchKernelGGL(k_applyq<8>, dim3(nwg, 1, nshots), dim3(QNT), 0, s, d, a);
+    hipLaunchKernelGGL(k_applyq<8>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
   else
-    hipLaunchKernelGGL(k_applyq<4>, dim3(nwg, 1, nshots), dim3(QNT), 0, s, d, a);
+    hipLaunchKernelGGL(k_applyq<4>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
 }
 
 void launch_applyv(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, hipStream_t s) {
+  const size_t lds = (size_t)MPSW_APPLY_LDS * sizeof(double);
   if (bw == 16)
-    hipLaunchKernelGGL(k_applyv<16>, dim3(nwg, 1, nshots), dim3(QNT), 0, s, d, a);
+    hipLaunchKernelGGL(k_applyv<16>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
   else if (bw == 8)
-    hipLaunchKernelGGL(k_applyv<8>, dim3(nwg, 1, nshots), dim3(QNT), 0, s, d, a);
+    hipLaunchKernelGGL(k_applyv<8>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
   else
-    hipLaunchKernelGGL(k_applyv<4>, dim3(nwg, 1, nshots), dim3(QNT), 0, s, d, a);
+    hipLaunchKernelGGL(k_applyv<4>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
 }
 
 void launch_jac(const DevCtx* d, const OpArgs& a, int b, int nwg, int nshots, size_t lds, int64_t lcap, hipStream_t s) {

@@ -63,6 +63,27 @@ __device__ __forceinline__ double wave_sum64(double v) {
   return v;
 }
 
+// Element-wise transfer of n items, dst(e, src(e)), with U independent loads in
+// flight per thread before any of them is used: a loop with one load per
+// iteration pays a full memory latency per iteration.
+// Indices are 32-bit (every buffer here holds < 2^31 elements).
+template <int U, class Src, class Dst>
+__device__ __forceinline__ void bulk_copy(int n, int t, int nt, Src src, Dst dst) {
+  for (int b = t; b < n; b += nt * U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = b + u * nt;
+      v[u] = (e < n) ? src(e) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = b + u * nt;
+      if (e < n) dst(e, v[u]);
+    }
+  }
+}
+
 __device__ __forceinline__ int* shot_sync(const DevCtx& c, int shot) { return c.sync + (int64_t)shot * MPSW_SYNC_STRIDE; }
 
 }  // namespace mpsw

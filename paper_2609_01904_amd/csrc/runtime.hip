@@ -548,7 +548,7 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
     const int64_t nb = cdiv(ccap, b);
     prof(st, MPSW_KC_JACOBI, strm, [&] { launch_jac(d, v, b, (int)std::max<int64_t>(1, (nb + (nb & 1)) / 2), nshots, (size_t)2 * b * (ccap + 1) * 8, ccap, strm); });
     launch_jacfin(d, v, nshots, strm);
-    prof(st, MPSW_KC_APPLYV, strm, [&] { launch_applyv(d, v, bw1, std::max(1, cdiv(s.rho[k], bw1)), nshots, strm); });
+    prof(st, MPSW_KC_APPLYV, strm, [&] { launch_applyv(d, v, bw1, std::max(1, cdiv(s.rho[k], 16)), nshots, strm); });
     OpArgs g{};
     g.shot = -1;
     g.site = k;
@@ -559,7 +559,7 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
     ap.shot = -1;
     ap.site = k;
     const int bwq = qr_panel(2 * s.rt[k - 1]);
-    prof(st, MPSW_KC_APPLYQ, strm, [&] { launch_applyq(d, ap, bwq, std::max(1, cdiv(s.rho[k], bwq)), nshots, strm); });
+    prof(st, MPSW_KC_APPLYQ, strm, [&] { launch_applyq(d, ap, bwq, std::max(1, cdiv(s.rho[k], 16)), nshots, strm); });
   }
   OpArgs f{};
   f.shot = -1;
@@ -1210,7 +1210,7 @@ int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, doubl
     hipMemcpy(dims, d1.data(), DL::size * 4, hipMemcpyHostToDevice);
     OpArgs ap{};
     ap.shot = -1; ap.site = 1;
-    launch_applyq(e.d, ap, bw, std::max(1, cdiv(rt1, bw)), 1, s0);
+    launch_applyq(e.d, ap, bw, std::max(1, cdiv(rt1, 16)), 1, s0);
     hipDeviceSynchronize();
     hipMemcpy(out1, eng + L.off_M, (size_t)m * rt1 * 8, hipMemcpyDeviceToHost);
     hipMemcpy(out2, eng + L.off_R, (size_t)rt1 * n * 8, hipMemcpyDeviceToHost);
@@ -1233,7 +1233,7 @@ int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, doubl
     const int64_t nb = cdiv(q, b);
     launch_jac(e.d, v, b, (int)std::max<int64_t>(1, (nb + (nb & 1)) / 2), 1, (size_t)2 * b * (q + 1) * 8, q, s0);
     launch_jacfin(e.d, v, 1, s0);
-    launch_applyv(e.d, v, bw, std::max<int>(1, cdiv(q, bw)), 1, s0);
+    launch_applyv(e.d, v, bw, std::max<int>(1, cdiv(q, 16)), 1, s0);
     OpArgs g{};
     g.shot = -1; g.site = 1; g.slot = 0; g.op = G_US;
     launch_gemm(e.d, g, tiles(m, q), 1, 1, s0);
