@@ -621,33 +621,73 @@ __global__ __launch_bounds__(1024) void k_applyv(const DevCtx* __restrict__ cp, 
 // every active workgroup loads one pair of blocks into LDS and rotates all
 // column pairs of the pair once.  Sweeps repeat until one rotates nothing.
 // ---------------------------------------------------------------------------
-// Rotation of one column pair by a group of 16 lanes; each lane keeps its
-// EPL elements of both columns in registers (columns of length Lc <= 16 EPL).
+// Rotation of one column pair by a group of 16 lanes (a DPP row); each lane
+// keeps its EPL elements of both columns in registers (columns of length
+// Lc <= 16 EPL; EPL = 0: any length, streamed from LDS).  Returns the squared
+// cosine of the pair's angle, ga^2 / (al be), or -1 when either column is
+// numerically zero; rotates when it exceeds tol2.
+//
+// The angle (Rutishauser's formulas) uses the hardware reciprocal and
+// reciprocal square root, each refined by one Newton step: the tangent then
+// carries a relative error of a few ulps, which only changes how far the pair
+// is rotated, while cs = 1/sqrt(1+t^2), sn = cs t keep the rotation orthogonal
+// to rounding.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  return r * fma(-x, r, 2.0);
+}
+__device__ __forceinline__ double rsq_nr(double x) {   // x >= 1 here
+  const double y = __builtin_amdgcn_rsq(x);
+  return y * fma(-0.5 * x * y, y, 1.5);
+}
+
+__device__ __forceinline__ bool jacobi_angle(double al, double be, double ga, double tol2, double floor2,
+                                             double& rel2, double& cs, double& sn) {
+  if (al <= floor2 || be <= floor2) {
+    rel2 = -1.0;
+    return false;
+  }
+  const double ab = al * be, g2 = ga * ga;
+  rel2 = g2 * rcp_nr(ab);
+  if (!(g2 > tol2 * ab)) return false;
+  const double zeta = (be - al) * rcp_nr(2.0 * ga);
+  double tt;
+  if (fabs(zeta) > 1e100) {
+    tt = 0.5 * rcp_nr(zeta);
+  } else {
+    const double q = fma(zeta, zeta, 1.0);
+    tt = copysign(rcp_nr(fabs(zeta) + q * rsq_nr(q)), zeta);
+  }
+  cs = rsq_nr(fma(tt, tt, 1.0));
+  sn = cs * tt;
+  return true;
+}
+
 template <int EPL>
-__device__ __forceinline__ bool rotate_pair(double* ap, double* aq, int gl, int Lc, double tol, double floor2) {
+__device__ __forceinline__ double rotate_pair(double* ap, double* aq, int gl, int Lc, double tol2, double floor2) {
   double x[EPL], y[EPL];
-  double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
     const int i = gl + 16 * e;
     x[e] = (i < Lc) ? ap[i] : 0.0;
     y[e] = (i < Lc) ? aq[i] : 0.0;
   }
+  // two accumulators per sum halve the dependent chains
+  double al0 = 0.0, be0 = 0.0, ga0 = 0.0, al1 = 0.0, be1 = 0.0, ga1 = 0.0;
 #pragma unroll
-  for (int e = 0; e < EPL; ++e) {
-    al = fma(x[e], x[e], al);
-    be = fma(y[e], y[e], be);
-    ga = fma(x[e], y[e], ga);
+  for (int e = 0; e < EPL; e += 2) {
+    al0 = fma(x[e], x[e], al0);
+    be0 = fma(y[e], y[e], be0);
+    ga0 = fma(x[e], y[e], ga0);
+    if (e + 1 < EPL) {
+      al1 = fma(x[e + 1], x[e + 1], al1);
+      be1 = fma(y[e + 1], y[e + 1], be1);
+      ga1 = fma(x[e + 1], y[e + 1], ga1);
+    }
   }
-  al = row_sum16(al);
-  be = row_sum16(be);
-  ga = row_sum16(ga);
-  if (al <= floor2 || be <= floor2 || fabs(ga) <= tol * sqrt(al) * sqrt(be)) return false;
-  const double zeta = (be - al) / (2.0 * ga);
-  double tt;
-  if (fabs(zeta) > 1e100) tt = 0.5 / zeta;
-  else tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+  const double al = row_sum16(al0 + al1), be = row_sum16(be0 + be1), ga = row_sum16(ga0 + ga1);
+  double rel2, cs, sn;
+  if (!jacobi_angle(al, be, ga, tol2, floor2, rel2, cs, sn)) return rel2;
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
     const int i = gl + 16 * e;
@@ -656,11 +696,11 @@ __device__ __forceinline__ bool rotate_pair(double* ap, double* aq, int gl, int 
       aq[i] = sn * x[e] + cs * y[e];
     }
   }
-  return true;
+  return rel2;
 }
 
 template <>
-__device__ __forceinline__ bool rotate_pair<0>(double* ap, double* aq, int gl, int Lc, double tol, double floor2) {
+__device__ __forceinline__ double rotate_pair<0>(double* ap, double* aq, int gl, int Lc, double tol2, double floor2) {
   double al = 0.0, be = 0.0, ga = 0.0;
   for (int i = gl; i < Lc; i += 16) {
     const double x = ap[i], y = aq[i];
@@ -671,26 +711,30 @@ __device__ __forceinline__ bool rotate_pair<0>(double* ap, double* aq, int gl, i
   al = row_sum16(al);
   be = row_sum16(be);
   ga = row_sum16(ga);
-  if (al <= floor2 || be <= floor2 || fabs(ga) <= tol * sqrt(al) * sqrt(be)) return false;
-  const double zeta = (be - al) / (2.0 * ga);
-  double tt;
-  if (fabs(zeta) > 1e100) tt = 0.5 / zeta;
-  else tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+  double rel2, cs, sn;
+  if (!jacobi_angle(al, be, ga, tol2, floor2, rel2, cs, sn)) return rel2;
   for (int i = gl; i < Lc; i += 16) {
     const double x = ap[i], y = aq[i];
     ap[i] = cs * x - sn * y;
     aq[i] = sn * x + cs * y;
   }
-  return true;
+  return rel2;
 }
 
+// A sweep visits every column pair once: round 0 pairs the blocks and
+// rotates all pairs among the 2b columns of a block pair (so every block's
+// internal pairs are done), later rounds only the b x b cross pairs, b
+// parallel rotations per step (block B_g meets A_{(g+s) mod na} at step s).
+// A sweep whose largest pair cosine was below 1e-9 leaves cosines of order
+// 1e-18 behind (quadratic convergence), so it is the last one.
+#define JNT 512   // threads of k_jac: 32 groups of 16 lanes, one column pair each per step
+
 template <int EPL>
-__global__ __launch_bounds__(512) void k_jac(const DevCtx* __restrict__ cp, OpArgs a, int b) {
+__global__ __launch_bounds__(JNT) void k_jac(const DevCtx* __restrict__ cp, OpArgs a, int b) {
   const DevCtx& c = *cp;
   const int shot = blockIdx.z, w = blockIdx.x, P = gridDim.x;
   const int k = a.site;
-  const int* dm = shot_dims(c, shot);
+  int* dm = shot_dims(c, shot);
   double* E = shot_eng(c, shot);
   const int m = dm[DL::rt + k], n = 2 * dm[DL::rho + k + 1];
   const int cc = (m >= n) ? n : m;
@@ -701,20 +745,20 @@ __global__ __launch_bounds__(512) void k_jac(const DevCtx* __restrict__ cp, OpAr
   const int pact = nbe / 2;
   int* sy = shot_sync(c, shot);
   int epoch = 0;
-  const bool ok = ((int64_t)Lc * cc <= c.L.cap_sA) && pact <= P;
-  if (!ok && w == 0 && t == 0) raise_err(c, (pact > P) ? MPSW_DEV_ERR_GRID : MPSW_DEV_ERR_CAP);
+  const bool ok = ((int64_t)Lc * cc <= c.L.cap_sA) && pact <= P && b <= JNT / 16;
+  if (!ok && w == 0 && t == 0) raise_err(c, (pact > P || b > JNT / 16) ? MPSW_DEV_ERR_GRID : MPSW_DEV_ERR_CAP);
   double* A = E + c.L.off_sA;
   extern __shared__ double blk[];   // 2b columns, stride ldl
   const int ldl = Lc + 1;
   __shared__ int nrot;
+  __shared__ unsigned int maxrel;   // float bits of the largest squared cosine
   __shared__ double fro_red[16];
-  const double tol = 1e-15 * sqrt((double)Lc);
+  const double tol = 1e-15 * sqrt((double)Lc), tol2 = tol * tol;
   // Columns below 1e-14 ||A||_F are numerically zero (rounding noise of the
   // factorisations): they are not rotated, since their direction cannot be
   // resolved and chasing it would never converge.
   double fro = 0.0;
-  if (ok)
-    for (int64_t e = t; e < (int64_t)Lc * cc; e += blockDim.x) fro = fma(A[e], A[e], fro);
+  if (ok) bulk_copy<8>(Lc * cc, t, JNT, [&](int e) { return A[e]; }, [&](int, double v) { fro = fma(v, v, fro); });
   fro = wave_sum(fro);
   if (lane == 0) fro_red[wv] = fro;
   __syncthreads();
@@ -723,6 +767,13 @@ __global__ __launch_bounds__(512) void k_jac(const DevCtx* __restrict__ cp, OpAr
   const double floor2 = 1e-28 * fro;
   // the eigen stage of an SVD of a c x c factor, 9 c^3 by the standard count
   if (ok && w == 0 && t == 0) count_flops(c, shot, MPSW_KC_JACOBI, 9.0 * (double)cc * cc * cc);
+  const int g = t >> 4, gl = t & 15, ng = JNT / 16;
+  auto note = [&](double rel2) {   // one lane per group
+    if (gl == 0 && rel2 >= 0.0) {
+      if (rel2 > tol2) atomicAdd(&nrot, 1);
+      atomicMax(&maxrel, __float_as_uint((float)fmin(rel2, 1.0)));
+    }
+  };
   for (int sweep = 0; sweep < MPSW_MAX_SWEEPS; ++sweep) {
     for (int rnd = 0; rnd < nbe - 1; ++rnd) {
       if (ok && w < pact && cc > 1) {
@@ -733,37 +784,48 @@ __global__ __launch_bounds__(512) void k_jac(const DevCtx* __restrict__ cp, OpAr
         const int np_ = (bp < nb) ? min(b, cc - bp * b) : 0;
         const int nq_ = (bq < nb) ? min(b, cc - bq * b) : 0;
         const int ncol = np_ + nq_;
-        if (t == 0) nrot = 0;
-        // load
+        if (t == 0) { nrot = 0; maxrel = 0u; }
         auto gcol = [&](int jj) { return (jj < np_) ? bp * b + jj : bq * b + (jj - np_); };
         bulk_copy<8>(ncol * Lc, t, blockDim.x,
-                     [&](int e) { return A[(int64_t)gcol((int)(e / Lc)) * Lc + (e % Lc)]; },
+                     [&](int e) { return A[(int64_t)gcol(e / Lc) * Lc + (e % Lc)]; },
                      [&](int e, double v) { blk[(e / Lc) * ldl + (e % Lc)] = v; });
         __syncthreads();
-        // one cyclic pass over all column pairs of the loaded block pair; a
-        // pair is handled by a group of 16 lanes (4 pairs per wave in flight)
-        const int npl = ncol + (ncol & 1);
-        const int g = t >> 4, gl = t & 15, ng = blockDim.x >> 4;
-        for (int ir = 0; ir < npl - 1; ++ir) {
-          for (int pi = g; pi < npl / 2; pi += ng) {
-            int p, q;
-            if (pi == 0) { p = ir; q = npl - 1; }
-            else { p = (ir + pi) % (npl - 1); q = (ir - pi + (npl - 1)) % (npl - 1); }
-            if (p >= ncol || q >= ncol) continue;
-            if (rotate_pair<EPL>(blk + p * ldl, blk + q * ldl, gl, Lc, tol, floor2) && gl == 0) atomicAdd(&nrot, 1);
+        if (rnd == 0) {   // all pairs among the loaded columns, round-robin
+          const int npl = ncol + (ncol & 1);
+          for (int ir = 0; ir < npl - 1; ++ir) {
+            for (int pi = g; pi < npl / 2; pi += ng) {
+              int p, q;
+              if (pi == 0) { p = ir; q = npl - 1; }
+              else { p = (ir + pi) % (npl - 1); q = (ir - pi + (npl - 1)) % (npl - 1); }
+              if (p >= ncol || q >= ncol) continue;
+              note(rotate_pair<EPL>(blk + p * ldl, blk + q * ldl, gl, Lc, tol2, floor2));
+            }
+            __syncthreads();
           }
-          __syncthreads();
+        } else if (np_ > 0 && nq_ > 0) {   // cross pairs only
+          const int na = max(np_, nq_), ns = min(np_, nq_);
+          const int a0 = (np_ >= nq_) ? 0 : np_, s0 = (np_ >= nq_) ? np_ : 0;
+          for (int s = 0; s < na; ++s) {
+            if (g < ns) {
+              const int p = s0 + g, q = a0 + (g + s) % na;
+              note(rotate_pair<EPL>(blk + p * ldl, blk + q * ldl, gl, Lc, tol2, floor2));
+            }
+            __syncthreads();
+          }
         }
-        // store
         bulk_copy<8>(ncol * Lc, t, blockDim.x, [&](int e) { return blk[(e / Lc) * ldl + (e % Lc)]; },
-                     [&](int e, double v) { A[(int64_t)gcol((int)(e / Lc)) * Lc + (e % Lc)] = v; });
-        if (t == 0 && nrot > 0) atomicAdd(sy + MPSW_SYNC_ROT + (sweep & 63), nrot);
+                     [&](int e, double v) { A[(int64_t)gcol(e / Lc) * Lc + (e % Lc)] = v; });
+        if (t == 0) {
+          if (nrot > 0) atomicAdd(sy + MPSW_SYNC_ROT + (sweep & 63), nrot);
+          atomicMax((unsigned int*)sy + MPSW_SYNC_MAXREL + (sweep & 63), maxrel);
+        }
       }
       shot_barrier(c, sy + MPSW_SYNC_BARRIER, P, epoch);
     }
-    // every workgroup reads the same final count after the barrier
+    // every workgroup reads the same final values after the barrier
     const int rot = ld_acquire(sy + MPSW_SYNC_ROT + (sweep & 63));
-    if (rot == 0 || !ok || cc <= 1) {
+    const float mx = __uint_as_float((unsigned int)ld_acquire(sy + MPSW_SYNC_MAXREL + (sweep & 63)));
+    if (rot == 0 || mx < 1e-18f || !ok || cc <= 1) {
       if (w == 0 && t == 0) atomicMax((int*)dm + DL::jac_sweeps, sweep + 1);
       break;
     }
@@ -900,7 +962,7 @@ void launch_applyv(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots
 }
 
 void launch_jac(const DevCtx* d, const OpArgs& a, int b, int nwg, int nshots, size_t lds, int64_t lcap, hipStream_t s) {
-  const dim3 g(nwg, 1, nshots), blk(512);
+  const dim3 g(nwg, 1, nshots), blk(JNT);
   if (lcap <= 32) hipLaunchKernelGGL(k_jac<2>, g, blk, lds, s, d, a, b);
   else if (lcap <= 64) hipLaunchKernelGGL(k_jac<4>, g, blk, lds, s, d, a, b);
   else if (lcap <= 128) hipLaunchKernelGGL(k_jac<8>, g, blk, lds, s, d, a, b);

@@ -34,7 +34,8 @@
 #define MPSW_SYNC_STRIDE 1024
 #define MPSW_SYNC_BARRIER 0       // barrier arrival counter
 #define MPSW_SYNC_ROT 8           // [64] rotations seen per Jacobi sweep
-#define MPSW_SYNC_FLAGS 128       // [<= 896] panel-ready flags of the QR factorisation
+#define MPSW_SYNC_MAXREL 128      // [64] largest squared pair cosine per Jacobi sweep (float bits)
+#define MPSW_SYNC_FLAGS 192       // [<= 832] panel-ready flags of the QR factorisation
 #define MPSW_MAX_SWEEPS 60
 
 // Per-shot integer block layout (offsets in ints).

@@ -422,9 +422,14 @@ int qr_panel(int64_t mcap) {
 
 // Jacobi block width for columns of length at most lcap: a block pair
 // (2 bw columns of lcap+1 doubles) lives in LDS.
+// About 16 blocks per sweep spread a sweep over 8 workgroups; every block
+// pair's rotations are a sequence of b-wide steps, so smaller blocks only add
+// rounds (and barriers) without shortening the sequence.
 int jac_block(int64_t lcap) {
   const size_t lim = lds_limit() - 1024;   // static LDS of the kernel
-  for (int b = 32; b >= 1; b >>= 1)
+  int want = 4;   // at most 16: one wave per column pair of a step
+  while (want < 16 && want * 16 < lcap) want <<= 1;
+  for (int b = want; b >= 1; b >>= 1)
     if ((size_t)2 * b * (lcap + 1) * 8 <= lim) return b;
   return 0;
 }
