@@ -66,7 +66,7 @@ typedef struct mpsw_config {
 typedef struct mpsw_state_s* mpsw_state;
 
 typedef struct mpsw_stats {
-  int64_t step;            /* steps taken since creation */
+  int64_t step;            /* steps taken by this shot since its fields were set (or creation) */
   int nsites;              /* K */
   int bonds[64];           /* bonds of psi^k, K+1 entries */
   int max_exact_bond[3];   /* largest bond before truncation in the last step, per rounding */
@@ -106,13 +106,32 @@ int mpsw_set_velocity_mpo(mpsw_state st, const int* bonds, const double* cores);
 int mpsw_set_source(mpsw_state st, int shot, int ix, int iz, int nt, const double* wavelet);
 
 /* Initial fields of shot `shot` from dense host arrays (NULL = zero); each is
- * stored as its right-to-left TT-SVD with the state's (eps, chi_max).
- * Resets the step counter to 0.  Errors: EINVAL, ENOMEM, EHIP. */
+ * stored as its right-to-left TT-SVD with the shot's (eps, chi_max).
+ * Restarts the shot's step counter (its source clock) at 0.  Errors: EINVAL,
+ * ENOMEM, EHIP. */
 int mpsw_set_fields(mpsw_state st, int shot, const double* u_prev, const double* u_cur);
 
 /* Enqueue k >= 0 steps of eq. 17 on the state's stream (asynchronous).
  * Errors: ESTATE (no velocity set), EINVAL, EHIP. */
 int mpsw_step(mpsw_state st, int k);
+
+/* Graph mode (on != 0): mpsw_step replays captured HIP graphs, three steps
+ * (one turn of the psi slot rotation) per launch, capturing on first use
+ * and again after a velocity change; remaining steps run eagerly.  Results
+ * are identical to eager stepping.  Errors: EINVAL, EHIP. */
+int mpsw_set_graph_mode(mpsw_state st, int on);
+
+/* A group steps several states together (states may differ in n; shots of a
+ * state may differ in chi_max and eps) as one HIP graph with one branch per
+ * state, launched on `hip_stream`.  The states stay owned by the caller and
+ * must outlive the group. */
+typedef struct mpsw_group_s* mpsw_group;
+int mpsw_group_create(const mpsw_state* states, int nstates, void* hip_stream, mpsw_group* out);
+/* Enqueue k steps of every state (asynchronous; ordered after, and before,
+ * the work already enqueued on each state's own stream).  Errors: EINVAL,
+ * ESTATE, EHIP. */
+int mpsw_group_step(mpsw_group g, int k);
+int mpsw_group_destroy(mpsw_group g);
 
 /* Write the dense field of shot `shot` (which = 0: u^k, 1: u^{k-1}) into the
  * caller's buffer of 4^n float64 (host memory, or device memory if

@@ -342,7 +342,9 @@ __global__ void k_pack_sum(const DevCtx* __restrict__ cp, OpArgs a) {
   // source coefficient and bit
   double ssrc = 0.0;
   const int nt = dm[DL::src_nt];
-  if (a.step >= 0 && a.step < nt && a.step < c.nt_max) ssrc = c.wavelet[(int64_t)shot * c.nt_max + a.step];
+  // the step index lives on the device, so a captured step replays correctly
+  const int stp = dm[DL::step];
+  if (stp >= 0 && stp < nt && stp < c.nt_max) ssrc = c.wavelet[(int64_t)shot * c.nt_max + stp];
   const int ix = dm[DL::src_ix], iz = dm[DL::src_iz];
   const int bit = (k < n) ? ((ix >> (n - 1 - k)) & 1) : ((iz >> (K - 1 - k)) & 1);
   const double coef[3] = {2.0, -1.0, c.lam2};
@@ -395,6 +397,7 @@ __global__ void k_finish(const DevCtx* __restrict__ cp, OpArgs a) {
     b[0] = 1;
     for (int k = 1; k < c.K; ++k) b[k] = dm[DL::rho + k];
     b[c.K] = 1;
+    if (a.aux == 1) dm[DL::step] += 1;   // last rounding of a time step
   }
 }
 

@@ -51,7 +51,8 @@ struct ShotDimsLayout {
   static constexpr int src_nt = src_iz + 1;
   static constexpr int maxbond = src_nt + 1;                       // [3] per rounding of the last step
   static constexpr int jac_sweeps = maxbond + 3;                   // most Jacobi sweeps since the last reset
-  static constexpr int size = jac_sweeps + 1;
+  static constexpr int step = jac_sweeps + 1;                      // steps taken since the fields were set
+  static constexpr int size = step + 1;
 };
 
 // Per-shot double block layout (offsets in doubles, separate small array).

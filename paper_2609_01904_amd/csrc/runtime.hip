@@ -308,11 +308,25 @@ struct mpsw_state_s {
   int64_t off_mps[MPSW_NSLOT][MPSW_MAXK];
   int64_t cap_mps[MPSW_NSLOT][MPSW_MAXK];
   Grids g;
+  // captured steps: one graph of three steps (a full turn of the psi slot
+  // rotation) per rotation phase, replayed by mpsw_step in graph mode
+  bool graph_mode = false;
+  int engine_gen = 0;                  // bumped whenever the step engine is rebuilt
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
   // event timing of one kernel class (mpsw_profile)
   int prof_cls = -1;
   std::vector<hipEvent_t> prof_ev;
   size_t prof_used = 0;
 };
+
+static void drop_graphs(mpsw_state st) {
+  for (int i = 0; i < 3; ++i)
+    if (st->gexec[i]) {
+      hipGraphExecDestroy(st->gexec[i]);
+      st->gexec[i] = nullptr;
+    }
+}
 
 namespace {
 
@@ -569,6 +583,7 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
   OpArgs f{};
   f.shot = -1;
   f.slot = out_slot;
+  f.aux = (kind == K_SUM) ? 1 : 0;   // the sum rounding ends a time step
   launch_finish(d, f, nshots, strm);
 }
 
@@ -700,6 +715,8 @@ int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t ch
 
 // Build the step engine once c^2 is known.
 int build_step_engine(mpsw_state st) {
+  drop_graphs(st);
+  ++st->engine_gen;
   const int K = st->K, n = st->n;
   Engine& e = st->eng;
   if (e.eng) { hipFree(e.eng); e.eng = nullptr; }
@@ -893,6 +910,8 @@ int mpsw_destroy(mpsw_state st) {
   hipFree(st->eng.eng);
   hipFree(st->eng.d);
   for (hipEvent_t ev : st->prof_ev) hipEventDestroy(ev);
+  drop_graphs(st);
+  if (st->cap_stream) hipStreamDestroy(st->cap_stream);
   delete st;
   return MPSW_OK;
 }
@@ -987,27 +1006,198 @@ int mpsw_set_fields(mpsw_state st, int shot, const double* u_prev, const double*
     int rc = dense_to_mps(st, fields[t], st->cfg[shot].eps, st->cfg[shot].chi_max, shot, slots[t], false);
     if (rc != MPSW_OK) return rc;
   }
+  const int zero = 0;   // this shot's source clock restarts
+  HIP_TRY(hipMemcpy(st->dims + (int64_t)shot * DL::size + DL::step, &zero, sizeof(int), hipMemcpyHostToDevice));
   st->step = 0;
   return MPSW_OK;
 }
+
+namespace {
+
+// Enqueue one time step (eq. 17: three roundings) on strm and turn the slot
+// rotation on the host.
+void enqueue_step(mpsw_state st, hipStream_t strm) {
+  Engine& e = st->eng;
+  const int step = (int)std::min<int64_t>(st->step, 1 << 30);
+  run_rounding(st, e, K_LAPLACE, e.sw[0], MPSW_SLOT_Y, 0, st->cur, 0, step, st->B, strm);
+  run_rounding(st, e, K_C2, e.sw[2], MPSW_SLOT_W, 1, 0, 0, step, st->B, strm);
+  run_rounding(st, e, K_SUM, e.sw[1], st->nxt, 2, st->cur, st->prev, step, st->B, strm);
+  const int old_prev = st->prev;
+  st->prev = st->cur;
+  st->cur = st->nxt;
+  st->nxt = old_prev;
+  ++st->step;
+}
+
+int ensure_cap_stream(mpsw_state st) {
+  if (!st->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&st->cap_stream, hipStreamNonBlocking));
+  return MPSW_OK;
+}
+
+// Capture three steps of st on the capture stream into *exec (the host-side
+// slot rotation returns to the same phase; nothing executes until launch).
+int capture_three_steps(mpsw_state st, hipStream_t cap, hipGraphExec_t* exec) {
+  const int saved_prof = st->prof_cls;
+  st->prof_cls = -1;   // no event nodes inside a graph
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < 3; ++i) enqueue_step(st, cap);
+  st->step -= 3;   // counted when the graph is launched
+  const hipError_t ce = hipStreamEndCapture(cap, &graph);
+  st->prof_cls = saved_prof;
+  if (ce != hipSuccess) return fail(MPSW_EHIP, std::string("step capture failed: ") + hipGetErrorString(ce));
+  const hipError_t ie = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (ie != hipSuccess) return fail(MPSW_EHIP, std::string("graph instantiation failed: ") + hipGetErrorString(ie));
+  return MPSW_OK;
+}
+
+}  // namespace
 
 int mpsw_step(mpsw_state st, int k) {
   if (!st) return fail(MPSW_EINVAL, "null state");
   if (k < 0) return fail(MPSW_EINVAL, "k must be >= 0");
   if (!st->have_velocity) return fail(MPSW_ESTATE, "set the velocity before stepping");
-  Engine& e = st->eng;
-  for (int it = 0; it < k; ++it) {
-    const int step = (int)std::min<int64_t>(st->step, 1 << 30);
-    run_rounding(st, e, K_LAPLACE, e.sw[0], MPSW_SLOT_Y, 0, st->cur, 0, step, st->B, st->stream);
-    run_rounding(st, e, K_C2, e.sw[2], MPSW_SLOT_W, 1, 0, 0, step, st->B, st->stream);
-    run_rounding(st, e, K_SUM, e.sw[1], st->nxt, 2, st->cur, st->prev, step, st->B, st->stream);
-    const int old_prev = st->prev;
-    st->prev = st->cur;
-    st->cur = st->nxt;
-    st->nxt = old_prev;
-    ++st->step;
+  if (st->graph_mode) {
+    int rc = ensure_cap_stream(st);
+    if (rc != MPSW_OK) return rc;
+    for (; k >= 3; k -= 3) {
+      const int phase = st->cur;
+      if (!st->gexec[phase] && (rc = capture_three_steps(st, st->cap_stream, &st->gexec[phase])) != MPSW_OK)
+        return rc;
+      HIP_TRY(hipGraphLaunch(st->gexec[phase], st->stream));
+      st->step += 3;
+    }
   }
+  for (int it = 0; it < k; ++it) enqueue_step(st, st->stream);
   HIP_TRY(hipGetLastError());
+  return MPSW_OK;
+}
+
+int mpsw_set_graph_mode(mpsw_state st, int on) {
+  if (!st) return fail(MPSW_EINVAL, "null state");
+  st->graph_mode = (on != 0);
+  if (!st->graph_mode) drop_graphs(st);
+  return MPSW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Groups: several states (different grids n, different chi per shot) stepped
+// by one graph with one branch per state.
+// ---------------------------------------------------------------------------
+struct mpsw_group_s {
+  std::vector<mpsw_state> states;
+  hipStream_t stream = nullptr;        // the caller's stream (launches)
+  hipStream_t cap = nullptr;           // capture origin
+  std::vector<hipStream_t> branch;     // one capture stream per state
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;        // capture joins; reused to order the states' streams
+  hipGraphExec_t exec = nullptr;
+  std::vector<int> phases;             // slot phases the graph was captured at
+  std::vector<int> gens;               // engine generations the graph was captured with
+};
+
+int mpsw_group_create(const mpsw_state* states, int nstates, void* stream, mpsw_group* out) {
+  if (!states || nstates < 1 || !out) return fail(MPSW_EINVAL, "null argument or nstates < 1");
+  for (int i = 0; i < nstates; ++i) {
+    if (!states[i]) return fail(MPSW_EINVAL, "null state in group");
+    for (int j = 0; j < i; ++j)
+      if (states[j] == states[i]) return fail(MPSW_EINVAL, "a state appears twice in the group");
+  }
+  mpsw_group g = new mpsw_group_s();
+  g->states.assign(states, states + nstates);
+  g->stream = (hipStream_t)stream;
+  g->branch.assign(nstates, nullptr);
+  g->join.assign(nstates, nullptr);
+  bool ok = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&g->fork, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; ok && i < nstates; ++i)
+    ok = hipStreamCreateWithFlags(&g->branch[i], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&g->join[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    mpsw_group_destroy(g);
+    return fail(MPSW_EHIP, "group stream or event creation failed");
+  }
+  *out = g;
+  return MPSW_OK;
+}
+
+int mpsw_group_step(mpsw_group g, int k) {
+  if (!g) return fail(MPSW_EINVAL, "null group");
+  if (k < 0) return fail(MPSW_EINVAL, "k must be >= 0");
+  const int ns = (int)g->states.size();
+  for (mpsw_state st : g->states)
+    if (!st->have_velocity) return fail(MPSW_ESTATE, "set the velocity of every state before stepping");
+  // order after the states' own pending work
+  for (int i = 0; i < ns; ++i) {
+    HIP_TRY(hipEventRecord(g->join[i], g->states[i]->stream));
+    HIP_TRY(hipStreamWaitEvent(g->stream, g->join[i], 0));
+  }
+  for (; k >= 3; k -= 3) {
+    std::vector<int> ph(ns), gen(ns);
+    for (int i = 0; i < ns; ++i) {
+      ph[i] = g->states[i]->cur;
+      gen[i] = g->states[i]->engine_gen;
+    }
+    if (!g->exec || ph != g->phases || gen != g->gens) {
+      if (g->exec) hipGraphExecDestroy(g->exec);
+      g->exec = nullptr;
+      hipGraph_t graph = nullptr;
+      HIP_TRY(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+      hipError_t ce = hipEventRecord(g->fork, g->cap);
+      std::vector<int> saved(ns);
+      for (int i = 0; i < ns && ce == hipSuccess; ++i) {
+        mpsw_state st = g->states[i];
+        ce = hipStreamWaitEvent(g->branch[i], g->fork, 0);
+        if (ce != hipSuccess) break;
+        saved[i] = st->prof_cls;
+        st->prof_cls = -1;
+        for (int s = 0; s < 3; ++s) enqueue_step(st, g->branch[i]);
+        st->step -= 3;
+        st->prof_cls = saved[i];
+        ce = hipEventRecord(g->join[i], g->branch[i]);
+        if (ce == hipSuccess) ce = hipStreamWaitEvent(g->cap, g->join[i], 0);
+      }
+      const hipError_t ee = hipStreamEndCapture(g->cap, &graph);
+      if (ce != hipSuccess || ee != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        return fail(MPSW_EHIP, std::string("group capture failed: ") + hipGetErrorString(ce != hipSuccess ? ce : ee));
+      }
+      const hipError_t ie = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+      hipGraphDestroy(graph);
+      if (ie != hipSuccess) return fail(MPSW_EHIP, std::string("graph instantiation failed: ") + hipGetErrorString(ie));
+      g->phases = ph;
+      g->gens = gen;
+    }
+    HIP_TRY(hipGraphLaunch(g->exec, g->stream));
+    for (mpsw_state st : g->states) st->step += 3;
+  }
+  // remaining steps eagerly, then hand the states back to their own streams
+  for (int i = 0; i < ns && k > 0; ++i) {
+    HIP_TRY(hipEventRecord(g->join[i], g->stream));
+    HIP_TRY(hipStreamWaitEvent(g->branch[i], g->join[i], 0));
+    for (int s = 0; s < k; ++s) enqueue_step(g->states[i], g->branch[i]);
+    HIP_TRY(hipEventRecord(g->join[i], g->branch[i]));
+    HIP_TRY(hipStreamWaitEvent(g->stream, g->join[i], 0));
+  }
+  HIP_TRY(hipEventRecord(g->fork, g->stream));
+  for (mpsw_state st : g->states) HIP_TRY(hipStreamWaitEvent(st->stream, g->fork, 0));
+  HIP_TRY(hipGetLastError());
+  return MPSW_OK;
+}
+
+int mpsw_group_destroy(mpsw_group g) {
+  if (!g) return MPSW_OK;
+  if (g->stream) hipStreamSynchronize(g->stream);
+  else hipDeviceSynchronize();
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  for (hipStream_t s : g->branch)
+    if (s) hipStreamDestroy(s);
+  for (hipEvent_t e : g->join)
+    if (e) hipEventDestroy(e);
+  if (g->fork) hipEventDestroy(g->fork);
+  if (g->cap) hipStreamDestroy(g->cap);
+  delete g;
   return MPSW_OK;
 }
 
@@ -1069,7 +1259,7 @@ int mpsw_get_stats(mpsw_state st, int shot, mpsw_stats* out) {
   HIP_TRY(hipMemcpy(d.data(), st->dims + (int64_t)shot * DL::size, DL::size * sizeof(int), hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(r.data(), st->reals + (int64_t)shot * RL::size, RL::size * sizeof(double), hipMemcpyDeviceToHost));
   std::memset(out, 0, sizeof(*out));
-  out->step = st->step;
+  out->step = d[DL::step];
   out->nsites = st->K;
   for (int k = 0; k <= st->K; ++k) out->bonds[k] = d[DL::bonds + st->cur * (MPSW_MAXK + 1) + k];
   for (int i = 0; i < 3; ++i) {

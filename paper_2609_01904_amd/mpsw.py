@@ -21,7 +21,8 @@ EXPORTS = [
     "mpsw_create_state", "mpsw_create_batch", "mpsw_set_velocity_dense", "mpsw_set_velocity_mpo",
     "mpsw_set_source", "mpsw_set_fields", "mpsw_step", "mpsw_to_dense", "mpsw_get_bonds",
     "mpsw_get_stats", "mpsw_get_shape", "mpsw_destroy", "mpsw_last_error", "mpsw_debug_laplacian_mpo",
-    "mpsw_debug_factor", "mpsw_profile", "mpsw_profile_read",
+    "mpsw_debug_factor", "mpsw_profile", "mpsw_profile_read", "mpsw_set_graph_mode",
+    "mpsw_group_create", "mpsw_group_step", "mpsw_group_destroy",
 ]
 
 KC_QR, KC_JACOBI, KC_GEMM, KC_APPLYQ, KC_APPLYV = 0, 1, 2, 3, 4
@@ -80,6 +81,10 @@ def load():
         "mpsw_debug_laplacian_mpo": [I, I, P, P, ctypes.c_int64],
         "mpsw_debug_factor": [I, I, I, P, P, P],
         "mpsw_profile": [P, I],
+        "mpsw_set_graph_mode": [P, I],
+        "mpsw_group_create": [ctypes.POINTER(P), I, P, ctypes.POINTER(P)],
+        "mpsw_group_step": [P, I],
+        "mpsw_group_destroy": [P],
         "mpsw_profile_read": [P, I, ctypes.POINTER(KProf)],
     }
     for name, args in sig.items():
@@ -194,6 +199,10 @@ class State:
                 "fallbacks": s.fallbacks, "max_jacobi_sweeps": s.max_jacobi_sweeps}
 
 
+    def set_graph_mode(self, on=True):
+        """Replay captured HIP graphs (three steps per launch) in step()."""
+        _check(load().mpsw_set_graph_mode(self._h, 1 if on else 0))
+
     def profile(self, kclass=-1):
         """Reset the per-class flop counters; time launches of `kclass` with events."""
         _check(load().mpsw_profile(self._h, int(kclass)))
@@ -202,6 +211,31 @@ class State:
         p = KProf()
         _check(load().mpsw_profile_read(self._h, int(kclass), ctypes.byref(p)))
         return {"launches": int(p.launches), "total_ms": float(p.total_ms), "alg_flops": float(p.alg_flops)}
+
+
+class Group:
+    """Several states (any mix of grids) stepped together by one HIP graph."""
+
+    def __init__(self, states, stream=None):
+        lib = load()
+        self.states = list(states)   # keep the states alive as long as the group
+        arr = (ctypes.c_void_p * len(self.states))(*[s._h.value for s in self.states])
+        self._h = ctypes.c_void_p()
+        _check(lib.mpsw_group_create(arr, len(self.states), _stream_handle(stream), ctypes.byref(self._h)))
+
+    def step(self, k=1):
+        _check(load().mpsw_group_step(self._h, int(k)))
+
+    def close(self):
+        if self._h:
+            load().mpsw_group_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def debug_laplacian_mpo(n, boundary=MPSW_PERIODIC):
