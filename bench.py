@@ -147,6 +147,9 @@ def main():
     ap.add_argument("--batch", type=int, default=1, help="shots advanced together")
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--graph", action="store_true",
+                    help="replay captured HIP graphs (three steps per launch) in the timed region; "
+                         "the roofline kernel is then timed over an equal eager region after it")
     ap.add_argument("--kernel-class", type=int, default=-1,
                     help="kernel class for the roofline (-1: the one with most time)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -178,7 +181,9 @@ def main():
     torch.cuda.synchronize()
     log(f"setup {time.perf_counter() - t_setup:.1f} s; bonds {st.bonds(0, 0)}")
 
-    st.step(args.warmup)
+    if args.graph:
+        st.set_graph_mode(True)
+    st.step(max(args.warmup, 3 if args.graph else 0))
     torch.cuda.synchronize()
     kclass = args.kernel_class
     if kclass < 0:   # the class with the most event time over one probe step (untimed)
@@ -197,6 +202,10 @@ def main():
     st.step(args.steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    if args.graph:   # events cannot sit inside the graphs: time the kernel over eager steps
+        st.set_graph_mode(False)
+        st.profile(kclass)
+        st.step(args.steps)
     prof = st.profile_read(kclass)
     stats = [st.stats(b) for b in range(args.batch)]
     log(f"timed {args.steps} steps x {args.batch} shots in {el:.3f} s; bonds {stats[0]['bonds']}; "
@@ -222,7 +231,8 @@ def main():
         "config": {"workload": f"{args.workload}: n={cfg['n']} (1024x1024), chi_max={cfg['chi']}, "
                                f"eps={cfg['eps']}, layered-fault c^2 (cutoff {cfg['eps_c']}), "
                                f"start from a developed wavefield at the chi cap",
-                   "shots": args.batch, "precision": args.precision, "rank": "exact SVD"},
+                   "shots": args.batch, "precision": args.precision, "rank": "exact SVD",
+                   "graph": bool(args.graph)},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

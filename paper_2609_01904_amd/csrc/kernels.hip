@@ -167,7 +167,26 @@ __device__ bool plan_gemm(const DevCtx& c, const OpArgs& a, int shot, int z, int
   return true;
 }
 
-// C = A * B (FP64), 64x64 output tiles, 256 threads, 4x4 outputs per thread.
+// C = A * B on the matrix cores: 64 x 64 output tiles per 256-thread
+// workgroup, each wave a 32 x 32 quarter (2 x 2 tiles of 16 x 16); K in
+// slices of 16 staged through LDS as FP64, the next slice's global loads in
+// flight while the current one is multiplied.  Lane layouts (checked on the
+// device): f64 16x16x4 and f32 16x16x4 take a = A[l%16][l/16], b = B[l/16][l%16];
+// bf16 16x16x16 takes a[q] = A[l%16][4(l/16)+q], b[q] = B[4(l/16)+q][l%16];
+// results are D[l/16 + 4v][l%16] (f64) and D[4(l/16) + v][l%16] (f32 accumulators).
+// In the FP32 and BF16 modes each slice's FP32 sums are added into FP64
+// accumulators, so the FP32 rounding of long sums is confined to 16 terms.
+typedef double gd4 __attribute__((ext_vector_type(4)));
+typedef float gf4 __attribute__((ext_vector_type(4)));
+typedef short gs4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_rne(float x) {   // round to nearest even (finite x)
+  const unsigned u = __float_as_uint(x);
+  return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_val(short h) { return __uint_as_float(((unsigned)(unsigned short)h) << 16); }
+
+template <int MODE>
 __global__ __launch_bounds__(256) void k_gemm(const DevCtx* __restrict__ cp, OpArgs a) {
   const DevCtx& c = *cp;
   const int shot = (a.shot >= 0) ? a.shot : (int)blockIdx.z, z = blockIdx.y;
@@ -179,64 +198,125 @@ __global__ __launch_bounds__(256) void k_gemm(const DevCtx* __restrict__ cp, OpA
   if (blockIdx.x == 0 && threadIdx.x == 0 && !d.copy) count_flops(c, shot, MPSW_KC_GEMM, 2.0 * d.M * d.N * d.K);
   if ((int)blockIdx.x >= tm * tn) return;
   const int m0 = (blockIdx.x / tn) * 64, n0 = (blockIdx.x % tn) * 64;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int t = threadIdx.x;
 
   if (d.copy) {
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    for (int e = t; e < 64 * 64; e += 256) {
       const int i = m0 + (e >> 6), j = n0 + (e & 63);
       if (i < d.M && j < d.N) d.C[(int64_t)i * d.crs + j] = d.B[(int64_t)i * d.brs + (int64_t)j * d.bcs];
     }
     return;
   }
 
-  __shared__ double As[16][64 + 1];
-  __shared__ double Bs[16][64 + 1];
-  double acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-
+  __shared__ double As[16][64 + 2];
+  __shared__ double Bs[16][64 + 2];
   const bool a_k_fast = (d.acs == 1);
   const bool b_n_fast = (d.bcs == 1);
+  // element u (0..3) of this thread's share of the A and B slices
+  auto a_idx = [&](int u, int& mm, int& kk) {
+    const int e = t + 256 * u;
+    if (a_k_fast) { kk = e & 15; mm = e >> 4; } else { mm = e & 63; kk = e >> 6; }
+  };
+  auto b_idx = [&](int u, int& nn, int& kk) {
+    const int e = t + 256 * u;
+    if (b_n_fast) { nn = e & 63; kk = e >> 6; } else { kk = e & 15; nn = e >> 4; }
+  };
+  double ra[4], rb[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int mm, kk, nn, kb;
+      a_idx(u, mm, kk);
+      b_idx(u, nn, kb);
+      const int gi = m0 + mm, gk = k0 + kk, gj = n0 + nn, gkb = k0 + kb;
+      ra[u] = (gi < d.M && gk < d.K) ? d.A[(int64_t)gi * d.ars + (int64_t)gk * d.acs] : 0.0;
+      rb[u] = (gj < d.N && gkb < d.K) ? d.B[(int64_t)gkb * d.brs + (int64_t)gj * d.bcs] : 0.0;
+    }
+  };
+  const int l = t & 63, w = t >> 6, li = l & 15, lq = l >> 4;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  gd4 acc64[2][2];
+  gf4 acc32[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc64[i][j] = gd4{0.0, 0.0, 0.0, 0.0};
+      acc32[i][j] = gf4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+  fetch(0);
   for (int k0 = 0; k0 < d.K; k0 += 16) {
-    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-      int mm, kk;
-      if (a_k_fast) { kk = e & 15; mm = e >> 4; } else { mm = e & 63; kk = e >> 6; }
-      const int gi = m0 + mm, gk = k0 + kk;
-      As[kk][mm] = (gi < d.M && gk < d.K) ? d.A[(int64_t)gi * d.ars + (int64_t)gk * d.acs] : 0.0;
-    }
-    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-      int nn, kk;
-      if (b_n_fast) { nn = e & 63; kk = e >> 6; } else { kk = e & 15; nn = e >> 4; }
-      const int gj = n0 + nn, gk = k0 + kk;
-      Bs[kk][nn] = (gj < d.N && gk < d.K) ? d.B[(int64_t)gk * d.brs + (int64_t)gj * d.bcs] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int mm, kk, nn, kb;
+      a_idx(u, mm, kk);
+      b_idx(u, nn, kb);
+      As[kk][mm] = ra[u];
+      Bs[kb][nn] = rb[u];
     }
     __syncthreads();
+    if (k0 + 16 < d.K) fetch(k0 + 16);   // next slice in flight during the products
+    if (MODE == GEMM_FP64 || MODE == GEMM_FP32) {
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double av[4], bv[4];
+      for (int ks = 0; ks < 4; ++ks) {
+        const int kr = 4 * ks + lq;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[kk][ty + 16 * i];
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx + 16 * j];
+          for (int j = 0; j < 2; ++j) {
+            const double av = As[kr][wm + 16 * i + li], bv = Bs[kr][wn + 16 * j + li];
+            if (MODE == GEMM_FP64)
+              acc64[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc64[i][j], 0, 0, 0);
+            else
+              acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)av, (float)bv, acc32[i][j], 0, 0, 0);
+          }
+      }
+    } else {   // BF16 x 3
+      gs4 ahi[2], alo[2], bhi[2], blo[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        for (int q = 0; q < 4; ++q) {
+          const float x = (float)As[4 * lq + q][wm + 16 * i + li];
+          const short h = bf16_rne(x);
+          ahi[i][q] = h;
+          alo[i][q] = bf16_rne(x - bf16_val(h));
+          const float y = (float)Bs[4 * lq + q][wn + 16 * i + li];
+          const short hy = bf16_rne(y);
+          bhi[i][q] = hy;
+          blo[i][q] = bf16_rne(y - bf16_val(hy));
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo[i], bhi[j], acc32[i][j], 0, 0, 0);
+          acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[i], blo[j], acc32[i][j], 0, 0, 0);
+          acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[i], bhi[j], acc32[i][j], 0, 0, 0);
+        }
+    }
+    if (MODE != GEMM_FP64) {   // FP32 sums of one 16-deep slice, accumulated across slices in FP64
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc32[i][j][v];
+          acc32[i][j] = gf4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int gi = m0 + ty + 16 * i;
-    if (gi >= d.M) continue;
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gj = n0 + tx + 16 * j;
-      if (gj < d.N) d.C[(int64_t)gi * d.crs + gj] = acc[i][j];
-    }
-  }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = m0 + wm + 16 * i + ((MODE == GEMM_FP64) ? (lq + 4 * v) : (4 * lq + v));
+        const int gj = n0 + wn + 16 * j + li;
+        if (gi < d.M && gj < d.N) d.C[(int64_t)gi * d.crs + gj] = acc64[i][j][v];
+      }
 }
 
 // ---------------------------------------------------------------------------
@@ -427,7 +507,10 @@ __global__ void k_zero_state(const DevCtx* __restrict__ cp, OpArgs a) {
 // ---------------------------------------------------------------------------
 void launch_gemm(const DevCtx* d, const OpArgs& a, int grid_tiles, int grid_batch, int nshots, hipStream_t s) {
   if (grid_tiles <= 0 || grid_batch <= 0) return;
-  hipLaunchKernelGGL(k_gemm, dim3(grid_tiles, grid_batch, nshots), dim3(256), 0, s, d, a);
+  const dim3 g(grid_tiles, grid_batch, nshots);
+  if (a.mode == GEMM_FP32) hipLaunchKernelGGL(k_gemm<GEMM_FP32>, g, dim3(256), 0, s, d, a);
+  else if (a.mode == GEMM_BF16X3) hipLaunchKernelGGL(k_gemm<GEMM_BF16X3>, g, dim3(256), 0, s, d, a);
+  else hipLaunchKernelGGL(k_gemm<GEMM_FP64>, g, dim3(256), 0, s, d, a);
 }
 void launch_prepare(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s) {
   hipLaunchKernelGGL(k_prepare, dim3((nshots + 63) / 64), dim3(64), 0, s, d, a);

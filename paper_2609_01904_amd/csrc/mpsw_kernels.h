@@ -17,6 +17,13 @@ enum GemmOp {
   G_US                 // U_r Sigma_r = M_k V_r
 };
 
+// Arithmetic of the contractions (k_gemm); storage is FP64 in every mode.
+enum GemmMode {
+  GEMM_FP64 = 0,   // FP64 matrix cores
+  GEMM_FP32 = 1,   // operands rounded to FP32, FP32 matrix cores, FP32 accumulation
+  GEMM_BF16X3 = 2  // operands split x = hi + lo in BF16, hi*hi + hi*lo + lo*hi, FP32 accumulation
+};
+
 // Rounding input kinds (k_prepare / k_init_R).
 enum PrepOp { P_LAPLACE = 1, P_C2, P_SUM, P_DENSE };
 
@@ -28,7 +35,7 @@ struct OpArgs {
   int aux;     // op-specific flag (buffer select, rounding index)
   int step;    // step index (source sample)
   int shot;    // restrict to one shot (-1 = all)
-  int pad;
+  int mode;    // contraction arithmetic of k_gemm: GEMM_FP64, GEMM_FP32 or GEMM_BF16X3
 };
 
 void launch_gemm(const DevCtx* d, const OpArgs& a, int grid_tiles, int grid_batch, int nshots, hipStream_t s);

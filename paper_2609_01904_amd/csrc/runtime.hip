@@ -310,6 +310,7 @@ struct mpsw_state_s {
   Grids g;
   // captured steps: one graph of three steps (a full turn of the psi slot
   // rotation) per rotation phase, replayed by mpsw_step in graph mode
+  int gemm_mode = 0;                   // GemmMode of the step's contractions
   bool graph_mode = false;
   int engine_gen = 0;                  // bumped whenever the step engine is rebuilt
   hipStream_t cap_stream = nullptr;
@@ -472,6 +473,9 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
                   int slot_a, int slot_b, int step, int nshots, hipStream_t strm) {
   const int K = st->K, n = st->n;
   const DevCtx* d = e.d;
+  // contractions of a time step run in the state's precision; set-up (dense
+  // fields to MPS) always in FP64
+  const int gmode = (kind == K_DENSE) ? GEMM_FP64 : st->gemm_mode;
   OpArgs a{};
   a.shot = -1;
   a.aux = log_idx;
@@ -497,6 +501,7 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
     for (int k = K - 1; k >= n; --k) {
       const int rd = (K - k - 1) & 1, wr = (K - k) & 1;
       OpArgs g{};
+      g.mode = gmode;
       g.shot = -1;
       g.site = k;
       g.op = G_KRON_R1;
@@ -509,6 +514,7 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
   }
   for (int k = 0; k < K; ++k) {
     OpArgs g{};
+    g.mode = gmode;
     g.shot = -1;
     g.site = k;
     const bool last = (k == K - 1);
@@ -569,6 +575,7 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
     launch_jacfin(d, v, nshots, strm);
     prof(st, MPSW_KC_APPLYV, strm, [&] { launch_applyv(d, v, bw1, std::max(1, cdiv(s.rho[k], 16)), nshots, strm); });
     OpArgs g{};
+    g.mode = gmode;
     g.shot = -1;
     g.site = k;
     g.slot = out_slot;
@@ -772,10 +779,10 @@ int create_group(const mpsw_config* cfgs, int nshots, void* stream, mpsw_state* 
     if (c.n != c0.n || c.lambda != c0.lambda || c.precision != c0.precision || c.boundary != c0.boundary)
       return fail(MPSW_EINVAL, "shots of one batch must share n, lambda, precision and boundary");
   }
-  if (c0.precision != MPSW_FP64) return fail(MPSW_EINVAL, "this build implements the FP64 path only");
   if (c0.rank_mode != MPSW_RANK_EXACT) return fail(MPSW_EINVAL, "this build implements the exact rank mode only");
   mpsw_state st = new mpsw_state_s();
   st->B = nshots;
+  st->gemm_mode = (c0.precision == MPSW_FP32) ? GEMM_FP32 : (c0.precision == MPSW_BF16) ? GEMM_BF16X3 : GEMM_FP64;
   st->n = c0.n;
   st->K = 2 * c0.n;
   st->cfg.assign(cfgs, cfgs + nshots);
