@@ -185,6 +185,20 @@ int mpsw_destroy(mpsw_state st);
 /* Message of the last failure on the calling thread ("" if none). */
 const char* mpsw_last_error(void);
 
+/* Truncation-rank network (34 -> 128 -> 128 -> 1, ReLU, FP32), trained and
+ * evaluated on the GPU.  X: m x 34 features (row-major), y: m targets (rank /
+ * chi_max), w: the MPSW_MLP_NPARAM parameters W1 (34 x 128, input by output),
+ * b1, W2 (128 x 128), b2, W3 (128), b3.  Loss: mean of wt (out - y)^2 with
+ * wt = alpha where out < y, else 1.  All pointers are host memory borrowed for
+ * the call.  Errors: EINVAL, ENOMEM, EHIP. */
+#define MPSW_MLP_NPARAM 21121
+/* Loss and gradient at w (gradient in the parameter order). */
+int mpsw_mlp_grad(const float* X, const float* y, int m, float alpha, const float* w, float* grad, float* loss);
+/* `epochs` full-batch Adam steps from w (updated in place) at learning rate lr. */
+int mpsw_mlp_train(const float* X, const float* y, int m, int epochs, float lr, float alpha, float* w);
+/* Network outputs for m feature rows. */
+int mpsw_mlp_forward(const float* X, int m, const float* w, float* out);
+
 /* Host-only helper (no device work), used by the CPU tests: the fused
  * Laplacian MPO S_x+ + S_x- + S_z+ + S_z- - 4I (eqs. 6 and 16) the library
  * applies, for an n-bit register pair and a boundary.  Writes K+1 bonds into

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/mpsw.h"
+
 #define MPSW_MAXK 24          // n <= 12
 #define MPSW_NSLOT 5          // MPS buffers: 0..2 psi rotation, 3 = y, 4 = w
 #define MPSW_SLOT_Y 3
@@ -22,13 +24,13 @@
 #define MPSW_DEV_ERR_GRID 4       // a launch grid was smaller than the live work
 #define MPSW_DEV_ERR_TIMEOUT 8    // a bounded inter-workgroup wait gave up
 
-// Kernel classes for the algorithmic-flop counters and event timing.
-#define MPSW_KC_QR 0       // Householder QR factorisations (sweep and SVD)
-#define MPSW_KC_JACOBI 1   // one-sided Jacobi sweeps
-#define MPSW_KC_GEMM 2     // contractions (GEMM-shaped)
-#define MPSW_KC_APPLYQ 3   // Q_{k-1} applied to U Sigma
-#define MPSW_KC_APPLYV 4   // Q1 applied to V' (wide bond matrices)
-#define MPSW_KC_COUNT 5
+// Truncation-rank network: 34 inputs, two hidden layers of 128, one output.
+#define MLP_NIN 34
+#define MLP_NH 128
+#define MLP_NPARAM (MLP_NIN * MLP_NH + MLP_NH + MLP_NH * MLP_NH + MLP_NH + MLP_NH + 1)
+
+// Kernel classes for the algorithmic-flop counters and event timing are the
+// MPSW_KC_* values of the public header.
 
 // Per-shot synchronisation area (ints) used by the multi-workgroup kernels.
 #define MPSW_SYNC_STRIDE 1024

@@ -39,6 +39,15 @@ int fail(int code, const std::string& msg) {
   } while (0)
 
 inline int64_t p2(int e) { return (int64_t)1 << e; }
+
+}  // namespace
+
+namespace mpsw {
+// Records the message returned by mpsw_last_error (for the other source files).
+int set_last_error(int code, const char* msg) { return fail(code, msg); }
+}  // namespace mpsw
+
+namespace {
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // ---------------------------------------------------------------------------

@@ -22,8 +22,10 @@ EXPORTS = [
     "mpsw_set_source", "mpsw_set_fields", "mpsw_step", "mpsw_to_dense", "mpsw_get_bonds",
     "mpsw_get_stats", "mpsw_get_shape", "mpsw_destroy", "mpsw_last_error", "mpsw_debug_laplacian_mpo",
     "mpsw_debug_factor", "mpsw_profile", "mpsw_profile_read", "mpsw_set_graph_mode",
-    "mpsw_group_create", "mpsw_group_step", "mpsw_group_destroy",
+    "mpsw_group_create", "mpsw_group_step", "mpsw_group_destroy", "mpsw_mlp_grad", "mpsw_mlp_train",
+    "mpsw_mlp_forward",
 ]
+MLP_NPARAM = 21121
 
 KC_QR, KC_JACOBI, KC_GEMM, KC_APPLYQ, KC_APPLYV = 0, 1, 2, 3, 4
 KC_NAMES = {KC_QR: "qr", KC_JACOBI: "jacobi", KC_GEMM: "gemm", KC_APPLYQ: "applyq", KC_APPLYV: "applyv"}
@@ -85,6 +87,9 @@ def load():
         "mpsw_group_create": [ctypes.POINTER(P), I, P, ctypes.POINTER(P)],
         "mpsw_group_step": [P, I],
         "mpsw_group_destroy": [P],
+        "mpsw_mlp_grad": [P, P, I, ctypes.c_float, P, P, P],
+        "mpsw_mlp_train": [P, P, I, I, ctypes.c_float, ctypes.c_float, P],
+        "mpsw_mlp_forward": [P, I, P, P],
         "mpsw_profile_read": [P, I, ctypes.POINTER(KProf)],
     }
     for name, args in sig.items():
@@ -236,6 +241,41 @@ class Group:
             self.close()
         except Exception:
             pass
+
+
+def _f32(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def mlp_grad(X, y, w, alpha):
+    """(loss, gradient) of the rank network on the GPU."""
+    X, px = _f32(X)
+    y, py = _f32(y)
+    w, pw = _f32(w)
+    g = np.zeros(MLP_NPARAM, dtype=np.float32)
+    loss = np.zeros(1, dtype=np.float32)
+    _check(load().mpsw_mlp_grad(px, py, X.shape[0], float(alpha), pw, g.ctypes.data_as(ctypes.c_void_p),
+                                loss.ctypes.data_as(ctypes.c_void_p)))
+    return float(loss[0]), g
+
+
+def mlp_train(X, y, w, epochs, lr, alpha):
+    """Weights after `epochs` full-batch Adam steps on the GPU."""
+    X, px = _f32(X)
+    y, py = _f32(y)
+    w = np.array(w, dtype=np.float32)
+    _check(load().mpsw_mlp_train(px, py, X.shape[0], int(epochs), float(lr), float(alpha),
+                                 w.ctypes.data_as(ctypes.c_void_p)))
+    return w
+
+
+def mlp_forward(X, w):
+    X, px = _f32(X)
+    w, pw = _f32(w)
+    out = np.zeros(X.shape[0], dtype=np.float32)
+    _check(load().mpsw_mlp_forward(px, X.shape[0], pw, out.ctypes.data_as(ctypes.c_void_p)))
+    return out
 
 
 def debug_laplacian_mpo(n, boundary=MPSW_PERIODIC):
