@@ -72,8 +72,9 @@ typedef struct mpsw_stats {
   int max_exact_bond[3];   /* largest bond before truncation in the last step, per rounding */
   double tail2[3];         /* discarded sum of squared singular values in the last step,
                               summed over bonds, per rounding */
-  int64_t fallbacks;       /* learned-rank mode: bonds that fell back to the exact SVD */
+  int64_t fallbacks;       /* learned-rank mode: sketches rejected (the exact SVD ran) */
   int max_jacobi_sweeps;   /* most one-sided Jacobi sweeps any bond needed since creation */
+  int64_t sketches;        /* learned-rank mode: bonds sketched by the randomized range finder */
 } mpsw_stats;
 
 /* Create a state for one shot with psi^0 = psi^{-1} = 0 (bond 1).
@@ -175,6 +176,22 @@ int mpsw_profile(mpsw_state st, int kclass);
 
 /* Read the counters of class `kclass`.  Synchronises.  Errors: EINVAL, EHIP. */
 int mpsw_profile_read(mpsw_state st, int kclass, mpsw_kprof* out);
+
+/* Learned-rank rounding (rank_mode MPSW_RANK_LEARNED): for every bond of the
+ * SVD sweep the rank network (parameters w, MPSW_MLP_NPARAM floats, host
+ * memory copied) proposes r from the bond's leading singular values at the
+ * previous step; a randomized range finder of width r + 8 with one power
+ * iteration sketches the bond matrix (Gaussian test matrix from the state's
+ * seed), the SVD stage runs on the sketch, and a FP64 residual test keeps it
+ * or runs the exact SVD (counted in mpsw_stats.fallbacks).  Required before
+ * stepping a learned-rank state.  Errors: EINVAL, EHIP. */
+int mpsw_rank_model_set(mpsw_state st, const float* w, int nw);
+
+/* The leading 32 singular values (descending, 0 where absent) of every bond
+ * of rounding `rounding` (0: L psi, 1: c^2 y, 2: the sum) in the last step of
+ * shot `shot`: out[k * 32 + i] for k = 0..K-1 (row k is bond k, the SVD of
+ * site k; row 0 is unused).  Synchronises.  Errors: EINVAL, EHIP. */
+int mpsw_get_sigma_log(mpsw_state st, int shot, int rounding, double* out);
 
 /* Number of shots and sites of the state. */
 int mpsw_get_shape(mpsw_state st, int* nshots, int* nsites);

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpsw.so")
-SOURCES = ["kernels.hip", "fact.hip", "mlp.hip", "runtime.hip"]
+SOURCES = ["kernels.hip", "fact.hip", "mlp.hip", "rrf.hip", "runtime.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

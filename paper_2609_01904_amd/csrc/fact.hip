@@ -311,6 +311,7 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
   const EngineLayout& L = c.L;
   const int k = a.site;
   const bool sweep = (a.op == 0);
+  const bool sketch = (a.op == 3);   // basis of a randomized range finder sketch
   int m, n;
   int64_t xr, xc;   // element (r, col) of the matrix to factor is X[r * xr + col * xc]
   const double* X;
@@ -329,9 +330,24 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
     capT = L.cap_qt[k];
     Rout = E + L.off_R;
     capRout = L.cap_R;
+  } else if (sketch) {   // Y (2 rho_{k+1} x l, aux 0) or Z (rt_k x l, aux 1), row-major
+    if (!gate_open(dm, a.gate)) return;
+    m = a.aux ? dm[DL::rt + k] : 2 * dm[DL::rho + k + 1];
+    n = dm[DL::rrf_l];
+    X = E + (a.aux ? L.off_Zs : L.off_Ys);
+    capX = a.aux ? L.cap_Zs : L.cap_Ys;
+    xr = n; xc = 1;
+    S = E + L.off_qrS;
+    capS = L.cap_qrS;
+    T = E + L.off_qrT;
+    capT = L.cap_qrT;
+    Rout = nullptr;
+    capRout = 0;
+    if (m < n) return;   // the planner never asks for a sketch wider than tall
   } else {
     // bond matrix M (mm x nn) = (rt_k x 2 rho_{k+1})
-    const int mm = dm[DL::rt + k], nn = 2 * dm[DL::rho + k + 1];
+    if (!gate_open(dm, a.gate)) return;
+    const int mm = dm[DL::rt + k], nn = svd_cols(dm, k);
     const bool tall = mm >= nn;
     if (a.op == 1) {   // M = Q R (tall) or M^T = Q1 R1 (wide)
       m = tall ? mm : nn;
@@ -379,7 +395,7 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
   }
   const int nbk = (n + BW - 1) / BW;
   if ((int64_t)m * n > capS || (int64_t)nbk * BW * BW > capT || nbk > (MPSW_SYNC_STRIDE - MPSW_SYNC_FLAGS) / 2 ||
-      (int64_t)n * n > capRout) {
+      (Rout && (int64_t)n * n > capRout)) {
     if (w == 0 && t == 0) raise_err(c, MPSW_DEV_ERR_CAP);
     return;
   }
@@ -395,7 +411,7 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
   // workgroup 0 records it for k_jacfin.
   __shared__ double cnorm[MPSW_PERM_MAX];
   __shared__ int perm[MPSW_PERM_MAX];
-  const bool pivot = !sweep && n <= MPSW_PERM_MAX;
+  const bool pivot = !sweep && !sketch && n <= MPSW_PERM_MAX;
   if (pivot) {
     if (xr == 1) {          // columns contiguous: one wave per column
       const int lane = t & 63, wv = t >> 6;
@@ -494,7 +510,7 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
     }
   }
   // R (n x n) from my columns: row-major R (sweep) or R^T column-major (SVD)
-  for (int blk = w; blk < nbk; blk += P) {
+  for (int blk = w; blk < nbk && Rout; blk += P) {
     const int c0 = blk * BW, bw = min(BW, n - c0);
     bulk_copy<8>(n * bw, t, QNT,
                  [&](int e) {
@@ -577,7 +593,8 @@ __global__ __launch_bounds__(1024) void k_applyv(const DevCtx* __restrict__ cp, 
   const int* dm = shot_dims(c, shot);
   double* E = shot_eng(c, shot);
   const EngineLayout& L = c.L;
-  const int m = dm[DL::rt + k], n = 2 * dm[DL::rho + k + 1], r = dm[DL::rho + k];
+  if (!gate_open(dm, a.gate)) return;
+  const int m = dm[DL::rt + k], n = svd_cols(dm, k), r = dm[DL::rho + k];
   if (m >= n) return;
   const int t = threadIdx.x;
   const int col0 = w * 16;   // columns per workgroup: one matrix-core tile
@@ -611,6 +628,46 @@ __global__ __launch_bounds__(1024) void k_applyv(const DevCtx* __restrict__ cp, 
   }
   bulk_copy<8>(n * cw, t, QNT, [&](int e) { return Y[(e % n) * r + col0 + (int)(e / n)]; },
                [&](int e, double v) { core[(int64_t)(col0 + (int)(e / n)) * n + (e % n)] = v; });
+}
+
+// ---------------------------------------------------------------------------
+// Explicit orthonormal basis of a sketch: Q = H_0 ... H_{nb-1} [I_l; 0] from
+// the reflectors k_qrf (op 3) left in qrS/qrT, written over the sketch
+// (Y for aux 0, Z for aux 1; m x l row-major).  Column chunks of 16 per
+// workgroup.
+// ---------------------------------------------------------------------------
+template <int BW>
+__global__ __launch_bounds__(1024) void k_formq(const DevCtx* __restrict__ cp, OpArgs a) {
+  const DevCtx& c = *cp;
+  const int shot = blockIdx.z, w = blockIdx.x;
+  const int k = a.site;
+  const int* dm = shot_dims(c, shot);
+  if (!gate_open(dm, a.gate)) return;
+  double* E = shot_eng(c, shot);
+  const EngineLayout& L = c.L;
+  const int m = a.aux ? dm[DL::rt + k] : 2 * dm[DL::rho + k + 1], l = dm[DL::rrf_l];
+  const int t = threadIdx.x;
+  const int col0 = w * 16;
+  if (col0 >= l || m < l) return;
+  const int cw = min(16, l - col0);
+  const int nbk = (l + BW - 1) / BW;
+  double* Q = E + (a.aux ? L.off_Zs : L.off_Ys);
+  const double* S = E + L.off_qrS;
+  const double* T = E + L.off_qrT;
+  if ((int64_t)m * l > (a.aux ? L.cap_Zs : L.cap_Ys) || (int64_t)m * l > L.cap_qrS ||
+      (int64_t)nbk * BW * BW > L.cap_qrT) {
+    if (t == 0) raise_err(c, MPSW_DEV_ERR_CAP);
+    return;
+  }
+  extern __shared__ double wsp[];
+  bulk_copy<8>(m * cw, t, QNT, [&](int e) { return ((e / cw) == col0 + (e % cw)) ? 1.0 : 0.0; },
+               [&](int e, double v) { Q[(int64_t)(e / cw) * l + col0 + (e % cw)] = v; });
+  __syncthreads();
+  for (int j = nbk - 1; j >= 0; --j) {
+    const int r0 = j * BW, c0 = j * BW, bw = min(BW, l - c0);
+    apply_reflector<BW>(S + r0 + (int64_t)m * c0, m, Q + (int64_t)r0 * l + col0, l, 1, m - r0, bw, cw,
+                        T + (int64_t)j * BW * BW, false, wsp);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -736,7 +793,8 @@ __global__ __launch_bounds__(JNT) void k_jac(const DevCtx* __restrict__ cp, OpAr
   const int k = a.site;
   int* dm = shot_dims(c, shot);
   double* E = shot_eng(c, shot);
-  const int m = dm[DL::rt + k], n = 2 * dm[DL::rho + k + 1];
+  if (!gate_open(dm, a.gate)) return;
+  const int m = dm[DL::rt + k], n = svd_cols(dm, k);
   const int cc = (m >= n) ? n : m;
   const int Lc = cc;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nwv = blockDim.x >> 6;
@@ -844,7 +902,8 @@ __global__ __launch_bounds__(256) void k_jacfin(const DevCtx* __restrict__ cp, O
   int* dm = shot_dims(c, shot);
   double* re = shot_reals(c, shot);
   double* E = shot_eng(c, shot);
-  const int m = dm[DL::rt + k], n = 2 * dm[DL::rho + k + 1];
+  if (!gate_open(dm, a.gate)) return;
+  const int m = dm[DL::rt + k], n = svd_cols(dm, k);
   const bool tall = m >= n;
   const int cc = tall ? n : m, Lc = cc;
   __shared__ double sig[JF_MAXC];
@@ -893,11 +952,19 @@ __global__ __launch_bounds__(256) void k_jacfin(const DevCtx* __restrict__ cp, O
       const double s = sig[order[i]];
       tail = fma(s, s, tail);
     }
-    if (a.aux >= 0 && a.aux < 3) {
+    if (a.gate == GATE_SKETCH) {   // judged by k_rrf_accept before anything is kept
+      double all = tail;
+      for (int i = 0; i < r; ++i) all = fma(sig[order[i]], sig[order[i]], all);
+      re[RL::rrf_tail] = tail;
+      re[RL::rrf_sig1] = s0;
+      re[RL::rrf_sum2] = all;
+    } else if (a.aux >= 0 && a.aux < 3) {
       re[RL::tail2 + a.aux] += tail;
+      if (cc > dm[DL::maxbond + a.aux]) dm[DL::maxbond + a.aux] = cc;
+    }
+    if (a.aux >= 0 && a.aux < 3) {
       double* lg = re + RL::sigma_log + (a.aux * MPSW_MAXK + k) * 32;
       for (int i = 0; i < 32; ++i) lg[i] = (i < cc) ? sig[order[i]] : 0.0;
-      if (cc > dm[DL::maxbond + a.aux]) dm[DL::maxbond + a.aux] = cc;
     }
     rank_s = r;
   }
@@ -959,6 +1026,16 @@ void launch_applyv(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots
     hipLaunchKernelGGL(k_applyv<8>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
   else
     hipLaunchKernelGGL(k_applyv<4>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
+}
+
+void launch_formq(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, hipStream_t s) {
+  const size_t lds = (size_t)MPSW_APPLY_LDS * sizeof(double);
+  if (bw == 16)
+    hipLaunchKernelGGL(k_formq<16>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
+  else if (bw == 8)
+    hipLaunchKernelGGL(k_formq<8>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
+  else
+    hipLaunchKernelGGL(k_formq<4>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
 }
 
 void launch_jac(const DevCtx* d, const OpArgs& a, int b, int nwg, int nshots, size_t lds, int64_t lcap, hipStream_t s) {

@@ -132,12 +132,41 @@ __device__ bool plan_gemm(const DevCtx& c, const OpArgs& a, int shot, int z, int
       break;
     }
     case G_US: {  // U_r Sigma_r (rt_k x rho_k) = M_k (rt_k x 2rho_{k+1}) * core_k^T
-      const int m = dm[DL::rt + k], nn = 2 * dm[DL::rho + k + 1], r = dm[DL::rho + k];
+      const int m = dm[DL::rt + k], nn = svd_cols(dm, k), r = dm[DL::rho + k];
       d.M = m; d.K = nn; d.N = r;
       d.A = E + L.off_M; d.ars = nn; d.acs = 1;
       d.B = mps_core(c, shot, a.slot, k); d.brs = 1; d.bcs = nn;
       d.C = E + L.off_US; d.crs = r; d.capC = L.cap_US;
       if ((int64_t)m * nn > L.cap_M || (int64_t)r * nn > c.cap_mps[a.slot][k]) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+      break;
+    }
+    // randomized range finder of the bond matrix M (rt_k x 2 rho_{k+1}, row-major
+    // in M), sketch width l: Omega (rt x l), Y (2 rho x l), Z (rt x l), G (l x l)
+    case G_RRF_Y: {  // Y = M^T Omega (aux 0) or M^T Z (aux 1)
+      const int m = dm[DL::rt + k], nn = 2 * dm[DL::rho + k + 1], l = dm[DL::rrf_l];
+      d.M = nn; d.K = m; d.N = l;
+      d.A = E + L.off_M; d.ars = 1; d.acs = nn;
+      d.B = E + (a.aux ? L.off_Zs : L.off_Om); d.brs = l; d.bcs = 1;
+      d.C = E + L.off_Ys; d.crs = l; d.capC = L.cap_Ys;
+      if ((int64_t)m * nn > L.cap_M || (int64_t)m * l > (a.aux ? L.cap_Zs : L.cap_Om)) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+      break;
+    }
+    case G_RRF_Z: {  // Z = M Q (Q = orthonormal Y)
+      const int m = dm[DL::rt + k], nn = 2 * dm[DL::rho + k + 1], l = dm[DL::rrf_l];
+      d.M = m; d.K = nn; d.N = l;
+      d.A = E + L.off_M; d.ars = nn; d.acs = 1;
+      d.B = E + L.off_Ys; d.brs = l; d.bcs = 1;
+      d.C = E + L.off_Zs; d.crs = l; d.capC = L.cap_Zs;
+      if ((int64_t)m * nn > L.cap_M || (int64_t)nn * l > L.cap_Ys) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+      break;
+    }
+    case G_RRF_CORE: {  // core (r x 2 rho) = core_small (r x l) Q^T; Q is 2 rho x l row-major
+      const int nn = 2 * dm[DL::rho + k + 1], l = dm[DL::rrf_l], r = dm[DL::rho + k];
+      d.M = r; d.K = l; d.N = nn;
+      d.A = mps_core(c, shot, a.slot, k); d.ars = l; d.acs = 1;
+      d.B = E + L.off_Ys; d.brs = 1; d.bcs = l;
+      d.C = E + L.off_Tc; d.crs = nn; d.capC = L.cap_Tc;
+      if ((int64_t)r * l > c.cap_mps[a.slot][k] || (int64_t)nn * l > L.cap_Ys) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
       break;
     }
     case G_DENSE: {  // V_{k+1} (2^k x 2 r_{k+1}) = V_k (2^k x r_k) * G_k (r_k x 2 r_{k+1})
@@ -190,6 +219,7 @@ template <int MODE>
 __global__ __launch_bounds__(256) void k_gemm(const DevCtx* __restrict__ cp, OpArgs a) {
   const DevCtx& c = *cp;
   const int shot = (a.shot >= 0) ? a.shot : (int)blockIdx.z, z = blockIdx.y;
+  if (!gate_open(shot_dims(c, shot), a.gate)) return;
   GemmDesc d;
   if (!plan_gemm(c, a, shot, z, blockIdx.z, d)) return;
   if (z == 0 && blockIdx.x == 0 && threadIdx.x == 0 && d.nbatch > (int)gridDim.y) raise_err(c, MPSW_DEV_ERR_GRID);

@@ -84,6 +84,23 @@ __device__ __forceinline__ void bulk_copy(int n, int t, int nt, Src src, Dst dst
   }
 }
 
+// Columns of the bond matrix of site k the SVD stage factors: 2 rho_{k+1},
+// or the sketch width while a randomized range finder result is judged.
+__device__ __forceinline__ int svd_cols(const int* dm, int k) {
+  const int o = dm[ShotDimsLayout::svd_n];
+  return (o > 0) ? o : 2 * dm[ShotDimsLayout::rho + k + 1];
+}
+// Whether a launch with this gate runs for the shot's current bond.
+__device__ __forceinline__ bool gate_open(const int* dm, int gate) {
+  const int s = dm[ShotDimsLayout::rrf];
+  switch (gate) {
+    case GATE_SKETCH: return s == 1;
+    case GATE_EXACT: return s != 2;
+    case GATE_ACCEPTED: return s == 2;
+    default: return true;
+  }
+}
+
 __device__ __forceinline__ int* shot_sync(const DevCtx& c, int shot) { return c.sync + (int64_t)shot * MPSW_SYNC_STRIDE; }
 
 }  // namespace mpsw

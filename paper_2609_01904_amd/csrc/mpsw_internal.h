@@ -28,6 +28,8 @@
 #define MLP_NIN 34
 #define MLP_NH 128
 #define MLP_NPARAM (MLP_NIN * MLP_NH + MLP_NH + MLP_NH * MLP_NH + MLP_NH + MLP_NH + 1)
+#define MPSW_RRF_MAXL 512         // widest randomized range finder sketch
+#define MPSW_RRF_OVER 8           // oversampling of the sketch width
 
 // Kernel classes for the algorithmic-flop counters and event timing are the
 // MPSW_KC_* values of the public header.
@@ -54,7 +56,13 @@ struct ShotDimsLayout {
   static constexpr int maxbond = src_nt + 1;                       // [3] per rounding of the last step
   static constexpr int jac_sweeps = maxbond + 3;                   // most Jacobi sweeps since the last reset
   static constexpr int step = jac_sweeps + 1;                      // steps taken since the fields were set
-  static constexpr int size = step + 1;
+  // learned-rank rounding (randomized range finder) of the current bond
+  static constexpr int svd_n = step + 1;      // columns of the bond matrix the SVD stage sees (0: 2 rho_{k+1})
+  static constexpr int rrf = svd_n + 1;       // 0: exact SVD, 1: sketch in progress, 2: sketch accepted
+  static constexpr int rrf_l = rrf + 1;       // sketch width l = predicted rank + oversampling
+  static constexpr int rrf_tries = rrf_l + 1; // bonds sketched since the fields were set
+  static constexpr int fallbacks = rrf_tries + 1;  // sketches rejected (exact SVD taken)
+  static constexpr int size = fallbacks + 1;
 };
 
 // Per-shot double block layout (offsets in doubles, separate small array).
@@ -63,7 +71,11 @@ struct ShotRealLayout {
   static constexpr int tail2 = 1;     // [3]
   static constexpr int sigma_log = 4; // [3][MAXK][32]: leading singular values of the last step
   static constexpr int alg_flops = sigma_log + 3 * MPSW_MAXK * 32;  // [MPSW_KC_COUNT] per kernel class
-  static constexpr int size = alg_flops + 8;
+  static constexpr int mnorm2 = alg_flops + 8;   // ||M||_F^2 of the sketched bond matrix
+  static constexpr int rrf_tail = mnorm2 + 1;    // sum of the discarded sketched sigma^2
+  static constexpr int rrf_sig1 = rrf_tail + 1;  // largest sketched sigma
+  static constexpr int rrf_sum2 = rrf_sig1 + 1;  // sum of all sketched sigma^2 (= ||M Q||_F^2)
+  static constexpr int size = rrf_sum2 + 1;
 };
 
 // Capacities (doubles) and offsets of one engine's buffers inside a shot arena.
@@ -86,6 +98,13 @@ struct EngineLayout {
   int64_t off_perm, cap_perm; // column order of the last SVD QR (stored as doubles)
   int64_t off_sJ, cap_sJ;   // Jacobi accumulated rotations
   int64_t off_qrS, cap_qrS; // Householder working matrix
+  // randomized range finder (learned-rank rounding)
+  int64_t off_Om, cap_Om;   // Gaussian test matrix Omega (rt x l)
+  int64_t off_Ys, cap_Ys;   // row-space sketch / its orthonormal basis Q (2 rho x l)
+  int64_t off_Zs, cap_Zs;   // column-space iterate, then B = M Q (rt x l)
+  int64_t off_Mb, cap_Mb;   // copy of the bond matrix while its sketch is judged
+  int64_t off_G, cap_G;     // l x l Gram matrix / Cholesky factor
+  int64_t off_Tc, cap_Tc;   // core = W_r^T Q^T before it replaces the slot
   int64_t off_qrT, cap_qrT; // Householder tau
   int64_t stride;           // doubles per shot for this engine
   int maxdim;               // largest matrix side any factorization sees
@@ -119,6 +138,10 @@ struct DevCtx {
   int64_t dense_stride;
   int* err;
   int* sync;                                     // B * MPSW_SYNC_STRIDE
+  // learned-rank rounding
+  const float* mlp_w;                            // rank network parameters (MLP_NPARAM)
+  unsigned long long seed;                       // of the Gaussian test matrices
+  int rrf_over;                                  // oversampling p of the sketch width
 };
 
 __host__ __device__ inline int64_t mpsw_pow2(int e) { return (int64_t)1 << e; }

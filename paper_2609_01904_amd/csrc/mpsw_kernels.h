@@ -14,8 +14,14 @@ enum GemmOp {
   G_KRON_R1,           // Kronecker contraction, right-to-left, first GEMM
   G_KRON_R2,           // ... second GEMM
   G_DENSE,             // dense contraction step V_{k+1} = V_k G_k
-  G_US                 // U_r Sigma_r = M_k V_r
+  G_US,                // U_r Sigma_r = M_k V_r
+  G_RRF_Y,             // Y = M^T Omega (aux 0) or Y = M^T Z (aux 1): row-space sketch
+  G_RRF_Z,             // Z = M Q: column-space iterate (aux 0) or B = M Q (aux 1)
+  G_RRF_CORE           // Tc = core_small Q^T (r x l times l x 2 rho)
 };
+
+// Gates of the SVD-stage launches (OpArgs.gate) in the learned-rank rounding.
+enum Gate { GATE_ALWAYS = 0, GATE_SKETCH = 1, GATE_EXACT = 2, GATE_ACCEPTED = 3 };
 
 // Arithmetic of the contractions (k_gemm); storage is FP64 in every mode.
 enum GemmMode {
@@ -36,6 +42,7 @@ struct OpArgs {
   int step;    // step index (source sample)
   int shot;    // restrict to one shot (-1 = all)
   int mode;    // contraction arithmetic of k_gemm: GEMM_FP64, GEMM_FP32 or GEMM_BF16X3
+  int gate;    // Gate: run only while the bond's sketch state allows it
 };
 
 void launch_gemm(const DevCtx* d, const OpArgs& a, int grid_tiles, int grid_batch, int nshots, hipStream_t s);
@@ -50,6 +57,12 @@ void launch_applyv(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots
 void launch_jac(const DevCtx* d, const OpArgs& a, int b, int nwg, int nshots, size_t lds, int64_t lcap, hipStream_t s);
 void launch_jacfin(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
 void set_lds_limits(size_t bytes);
+void launch_formq(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, hipStream_t s);
+void launch_rrf_plan(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
+void launch_gauss(const DevCtx* d, const OpArgs& a, int64_t cap, int nshots, hipStream_t s);
+void launch_rrf_swap(const DevCtx* d, const OpArgs& a, int64_t cap, int nshots, hipStream_t s);
+void launch_rrf_accept(const DevCtx* d, const OpArgs& a, int64_t cap, int nshots, hipStream_t s);
+void launch_rrf_core(const DevCtx* d, const OpArgs& a, int64_t cap, int nshots, hipStream_t s);
 void launch_finish(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
 void launch_dense_init(const DevCtx* d, int nshots, hipStream_t s);
 void launch_zero_state(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);

@@ -189,6 +189,7 @@ struct Plan {
   std::vector<int64_t> Rmax;   // state bond caps (y feeding the Kronecker rounding)
   std::vector<int> D;          // c^2 bonds (empty when no Kronecker rounding)
   bool kron = false;
+  int64_t rrf_l = 0;           // widest sketch of the learned-rank rounding (0: exact only)
 };
 
 void add64(int64_t& off, int64_t& field_off, int64_t cap) {
@@ -262,8 +263,29 @@ void layout_engine(const Plan& p, EngineLayout& L) {
   L.cap_Vp = capVp; add64(off, L.off_Vp, capVp);
   L.cap_Yv = capYv; add64(off, L.off_Yv, capYv);
   L.cap_perm = 4096; add64(off, L.off_perm, 4096);
+  if (p.rrf_l > 0) {   // the sketch bases reuse the Householder buffers
+    int64_t mx = 1;
+    for (const auto& s : p.sw)
+      for (int k = 1; k < K; ++k) mx = std::max(mx, std::max(s.rt[k], 2 * s.rho[k + 1]));
+    capQRS = std::max(capQRS, mx * p.rrf_l);
+    capQRT = std::max(capQRT, (p.rrf_l + 16) * 16);
+  }
   L.cap_qrS = capQRS; add64(off, L.off_qrS, capQRS);
   L.cap_qrT = capQRT; add64(off, L.off_qrT, capQRT);
+  if (p.rrf_l > 0) {   // randomized range finder buffers
+    int64_t mrt = 1, m2r = 1, mchi = 1;
+    for (const auto& s : p.sw)
+      for (int k = 1; k < K; ++k) {
+        mrt = std::max(mrt, s.rt[k]);
+        m2r = std::max(m2r, 2 * s.rho[k + 1]);
+        mchi = std::max(mchi, s.rho[k]);
+      }
+    L.cap_Om = mrt * p.rrf_l; add64(off, L.off_Om, L.cap_Om);
+    L.cap_Ys = m2r * p.rrf_l; add64(off, L.off_Ys, L.cap_Ys);
+    L.cap_Zs = mrt * p.rrf_l; add64(off, L.off_Zs, L.cap_Zs);
+    L.cap_Mb = capM; add64(off, L.off_Mb, capM);
+    L.cap_Tc = mchi * m2r; add64(off, L.off_Tc, L.cap_Tc);
+  }
   L.stride = off;
   L.maxdim = maxdim;
 }
@@ -320,6 +342,9 @@ struct mpsw_state_s {
   // captured steps: one graph of three steps (a full turn of the psi slot
   // rotation) per rotation phase, replayed by mpsw_step in graph mode
   int gemm_mode = 0;                   // GemmMode of the step's contractions
+  bool learned = false;                // learned-rank rounding (rank network + sketch)
+  float* mlp_w = nullptr;              // rank network parameters on the device
+  bool have_model = false;
   bool graph_mode = false;
   int engine_gen = 0;                  // bumped whenever the step engine is rebuilt
   hipStream_t cap_stream = nullptr;
@@ -410,6 +435,9 @@ void fill_ctx(mpsw_state st, DevCtx& h, double* eng, const EngineLayout& L) {
   h.dense_stride = 2 * p2(st->K);
   h.err = st->err;
   h.sync = st->sync;
+  h.mlp_w = st->mlp_w;
+  h.seed = (unsigned long long)st->cfg[0].seed;
+  h.rrf_over = MPSW_RRF_OVER;
 }
 
 int upload_ctx(Engine& e, hipStream_t s) {
@@ -561,35 +589,96 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
       prof(st, MPSW_KC_QR, strm, [&] { launch_qrf(d, q, bw, nwg, nshots, (size_t)mcap * bw * 8, strm); });
     }
   }
+  const bool learned = st->learned && kind != K_DENSE && e.plan.rrf_l > 0;
   for (int k = K - 1; k >= 1; --k) {
-    const int64_t rows = std::max(s.rt[k], 2 * s.rho[k + 1]);   // rows of the factored orientation
-    const int64_t ccap = std::min(s.rt[k], 2 * s.rho[k + 1]);
-    OpArgs v{};
-    v.shot = -1;
-    v.site = k;
-    v.slot = out_slot;
-    v.aux = log_idx;
-    launch_sync_reset(d, nshots, strm);
-    const int bw1 = qr_panel(rows), bw2 = qr_panel(ccap);
-    OpArgs q = v;
-    q.op = 1;
-    prof(st, MPSW_KC_QR, strm, [&] { launch_qrf(d, q, bw1, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(ccap, bw1))), nshots,
-               (size_t)rows * bw1 * 8, strm); });
-    q.op = 2;
-    prof(st, MPSW_KC_QR, strm, [&] { launch_qrf(d, q, bw2, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(ccap, bw2))), nshots,
-               (size_t)ccap * bw2 * 8, strm); });
-    const int b = jac_block(ccap);
-    const int64_t nb = cdiv(ccap, b);
-    prof(st, MPSW_KC_JACOBI, strm, [&] { launch_jac(d, v, b, (int)std::max<int64_t>(1, (nb + (nb & 1)) / 2), nshots, (size_t)2 * b * (ccap + 1) * 8, ccap, strm); });
-    launch_jacfin(d, v, nshots, strm);
-    prof(st, MPSW_KC_APPLYV, strm, [&] { launch_applyv(d, v, bw1, std::max(1, cdiv(s.rho[k], 16)), nshots, strm); });
-    OpArgs g{};
-    g.mode = gmode;
-    g.shot = -1;
-    g.site = k;
-    g.slot = out_slot;
-    g.op = G_US;
-    prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(s.rt[k], s.rho[k]), 1, nshots, strm); });
+    // SVD stage of the bond matrix M (rt_k x ncols): QR preconditioning,
+    // Jacobi, truncation, V, U Sigma = M V.  `ncap` bounds the column count.
+    auto svd_stage = [&](int gate, int64_t ncap) {
+      const int64_t rows = std::max(s.rt[k], ncap);   // rows of the factored orientation
+      const int64_t ccap = std::min(s.rt[k], ncap);
+      OpArgs v{};
+      v.shot = -1;
+      v.site = k;
+      v.slot = out_slot;
+      v.aux = log_idx;
+      v.gate = gate;
+      launch_sync_reset(d, nshots, strm);
+      const int bw1 = qr_panel(rows), bw2 = qr_panel(ccap);
+      OpArgs q = v;
+      q.op = 1;
+      prof(st, MPSW_KC_QR, strm, [&] { launch_qrf(d, q, bw1, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(ccap, bw1))), nshots,
+                 (size_t)rows * bw1 * 8, strm); });
+      q.op = 2;
+      prof(st, MPSW_KC_QR, strm, [&] { launch_qrf(d, q, bw2, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(ccap, bw2))), nshots,
+                 (size_t)ccap * bw2 * 8, strm); });
+      const int b = jac_block(ccap);
+      const int64_t nb = cdiv(ccap, b);
+      prof(st, MPSW_KC_JACOBI, strm, [&] { launch_jac(d, v, b, (int)std::max<int64_t>(1, (nb + (nb & 1)) / 2), nshots, (size_t)2 * b * (ccap + 1) * 8, ccap, strm); });
+      launch_jacfin(d, v, nshots, strm);
+      prof(st, MPSW_KC_APPLYV, strm, [&] { launch_applyv(d, v, bw1, std::max(1, cdiv(s.rho[k], 16)), nshots, strm); });
+      OpArgs g{};
+      g.mode = gmode;
+      g.gate = gate;
+      g.shot = -1;
+      g.site = k;
+      g.slot = out_slot;
+      g.op = G_US;
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(s.rt[k], s.rho[k]), 1, nshots, strm); });
+    };
+    const int64_t n2cap = 2 * s.rho[k + 1];
+    if (learned) {
+      // randomized range finder at the width the rank network proposes
+      const int64_t lcap = std::min<int64_t>(e.plan.rrf_l, n2cap);
+      OpArgs r{};
+      r.shot = -1;
+      r.site = k;
+      r.slot = out_slot;
+      r.aux = log_idx;
+      r.gate = GATE_SKETCH;
+      launch_rrf_plan(d, r, nshots, strm);
+      launch_gauss(d, r, s.rt[k] * lcap, nshots, strm);
+      OpArgs g{};
+      g.mode = gmode;
+      g.gate = GATE_SKETCH;
+      g.shot = -1;
+      g.site = k;
+      auto orth = [&](int which, int64_t mcap) {   // Q of Y (0) or Z (1), in place
+        OpArgs q = r;
+        q.op = 3;
+        q.aux = which;
+        const int bw = qr_panel(mcap);
+        launch_sync_reset(d, nshots, strm);
+        prof(st, MPSW_KC_QR, strm, [&] { launch_qrf(d, q, bw, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(lcap, bw))), nshots,
+                   (size_t)mcap * bw * 8, strm); });
+        prof(st, MPSW_KC_APPLYQ, strm, [&] { launch_formq(d, q, bw, std::max(1, cdiv(lcap, 16)), nshots, strm); });
+      };
+      g.op = G_RRF_Y;
+      g.aux = 0;
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(n2cap, lcap), 1, nshots, strm); });
+      orth(0, n2cap);
+      g.op = G_RRF_Z;
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(s.rt[k], lcap), 1, nshots, strm); });
+      orth(1, s.rt[k]);
+      g.op = G_RRF_Y;
+      g.aux = 1;
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(n2cap, lcap), 1, nshots, strm); });
+      orth(0, n2cap);
+      g.op = G_RRF_Z;   // B = M Q
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(s.rt[k], lcap), 1, nshots, strm); });
+      launch_rrf_swap(d, r, s.rt[k] * n2cap, nshots, strm);
+      svd_stage(GATE_SKETCH, lcap);
+      launch_rrf_accept(d, r, s.rt[k] * n2cap, nshots, strm);
+      svd_stage(GATE_EXACT, n2cap);
+      g.op = G_RRF_CORE;
+      g.gate = GATE_ACCEPTED;
+      g.slot = out_slot;
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(s.rho[k], n2cap), 1, nshots, strm); });
+      OpArgs cr = r;
+      cr.gate = GATE_ACCEPTED;
+      launch_rrf_core(d, cr, s.rho[k] * n2cap, nshots, strm);
+    } else {
+      svd_stage(GATE_ALWAYS, n2cap);
+    }
     OpArgs ap{};
     ap.shot = -1;
     ap.site = k;
@@ -756,6 +845,7 @@ int build_step_engine(mpsw_state st) {
   e.plan.Rmax = R;
   e.plan.D = st->c2b;
   e.plan.kron = true;
+  e.plan.rrf_l = st->learned ? std::min<int64_t>(st->chi_cap + MPSW_RRF_OVER, MPSW_RRF_MAXL) : 0;
   EngineLayout L;
   layout_engine(e.plan, L);
   if (hipMalloc(&e.eng, (size_t)L.stride * st->B * sizeof(double)) != hipSuccess)
@@ -785,13 +875,14 @@ int create_group(const mpsw_config* cfgs, int nshots, void* stream, mpsw_state* 
       return fail(MPSW_EINVAL, "unknown precision");
     if (c.boundary != MPSW_PERIODIC && c.boundary != MPSW_OPEN) return fail(MPSW_EINVAL, "unknown boundary");
     if (c.rank_mode != MPSW_RANK_EXACT && c.rank_mode != MPSW_RANK_LEARNED) return fail(MPSW_EINVAL, "unknown rank mode");
-    if (c.n != c0.n || c.lambda != c0.lambda || c.precision != c0.precision || c.boundary != c0.boundary)
-      return fail(MPSW_EINVAL, "shots of one batch must share n, lambda, precision and boundary");
+    if (c.n != c0.n || c.lambda != c0.lambda || c.precision != c0.precision || c.boundary != c0.boundary ||
+        c.rank_mode != c0.rank_mode)
+      return fail(MPSW_EINVAL, "shots of one batch must share n, lambda, precision, boundary and rank mode");
   }
-  if (c0.rank_mode != MPSW_RANK_EXACT) return fail(MPSW_EINVAL, "this build implements the exact rank mode only");
   mpsw_state st = new mpsw_state_s();
   st->B = nshots;
   st->gemm_mode = (c0.precision == MPSW_FP32) ? GEMM_FP32 : (c0.precision == MPSW_BF16) ? GEMM_BF16X3 : GEMM_FP64;
+  st->learned = (c0.rank_mode == MPSW_RANK_LEARNED);
   st->n = c0.n;
   st->K = 2 * c0.n;
   st->cfg.assign(cfgs, cfgs + nshots);
@@ -925,6 +1016,7 @@ int mpsw_destroy(mpsw_state st) {
   hipFree(st->sync);
   hipFree(st->eng.eng);
   hipFree(st->eng.d);
+  hipFree(st->mlp_w);
   for (hipEvent_t ev : st->prof_ev) hipEventDestroy(ev);
   drop_graphs(st);
   if (st->cap_stream) hipStreamDestroy(st->cap_stream);
@@ -1074,6 +1166,7 @@ int mpsw_step(mpsw_state st, int k) {
   if (!st) return fail(MPSW_EINVAL, "null state");
   if (k < 0) return fail(MPSW_EINVAL, "k must be >= 0");
   if (!st->have_velocity) return fail(MPSW_ESTATE, "set the velocity before stepping");
+  if (st->learned && !st->have_model) return fail(MPSW_ESTATE, "set the rank model before stepping a learned-rank state");
   if (st->graph_mode) {
     int rc = ensure_cap_stream(st);
     if (rc != MPSW_OK) return rc;
@@ -1142,8 +1235,10 @@ int mpsw_group_step(mpsw_group g, int k) {
   if (!g) return fail(MPSW_EINVAL, "null group");
   if (k < 0) return fail(MPSW_EINVAL, "k must be >= 0");
   const int ns = (int)g->states.size();
-  for (mpsw_state st : g->states)
+  for (mpsw_state st : g->states) {
     if (!st->have_velocity) return fail(MPSW_ESTATE, "set the velocity of every state before stepping");
+    if (st->learned && !st->have_model) return fail(MPSW_ESTATE, "set the rank model of every learned-rank state");
+  }
   // order after the states' own pending work
   for (int i = 0; i < ns; ++i) {
     HIP_TRY(hipEventRecord(g->join[i], g->states[i]->stream));
@@ -1282,8 +1377,9 @@ int mpsw_get_stats(mpsw_state st, int shot, mpsw_stats* out) {
     out->max_exact_bond[i] = d[DL::maxbond + i];
     out->tail2[i] = r[RL::tail2 + i];
   }
-  out->fallbacks = 0;
+  out->fallbacks = d[DL::fallbacks];
   out->max_jacobi_sweeps = d[DL::jac_sweeps];
+  out->sketches = d[DL::rrf_tries];
   return MPSW_OK;
 }
 
@@ -1292,6 +1388,31 @@ int mpsw_get_stats(mpsw_state st, int shot, mpsw_stats* out) {
 //         (the identity merge when m <= n: Q = I, R = A);
 //   op 1: SVD of A (m x n, n even): out1 = V^T (r x n), out2 = U Sigma (m x r),
 //         r = min(m, n) (no truncation); returns r.
+int mpsw_rank_model_set(mpsw_state st, const float* w, int nw) {
+  if (!st || !w || nw != MLP_NPARAM) return fail(MPSW_EINVAL, "null argument or wrong parameter count");
+  if (!st->mlp_w) HIP_TRY(hipMalloc(&st->mlp_w, MLP_NPARAM * sizeof(float)));
+  HIP_TRY(hipMemcpy(st->mlp_w, w, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice));
+  st->have_model = true;
+  if (st->have_velocity) {   // the step engine's context points at the parameters
+    st->eng.h.mlp_w = st->mlp_w;
+    int rc = upload_ctx(st->eng, st->stream);
+    if (rc != MPSW_OK) return rc;
+    drop_graphs(st);
+  }
+  return MPSW_OK;
+}
+
+int mpsw_get_sigma_log(mpsw_state st, int shot, int rounding, double* out) {
+  if (!st || !out) return fail(MPSW_EINVAL, "null argument");
+  if (shot < 0 || shot >= st->B || rounding < 0 || rounding > 2) return fail(MPSW_EINVAL, "shot or rounding out of range");
+  HIP_TRY(hipStreamSynchronize(st->stream));
+  std::vector<double> r(RL::size);
+  HIP_TRY(hipMemcpy(r.data(), st->reals + (int64_t)shot * RL::size, RL::size * sizeof(double), hipMemcpyDeviceToHost));
+  for (int k = 0; k < st->K; ++k)
+    for (int i = 0; i < 32; ++i) out[k * 32 + i] = r[RL::sigma_log + (rounding * MPSW_MAXK + k) * 32 + i];
+  return MPSW_OK;
+}
+
 int mpsw_profile(mpsw_state st, int kclass) {
   if (!st || kclass < -1 || kclass >= MPSW_KC_COUNT) return fail(MPSW_EINVAL, "invalid state or kernel class");
   HIP_TRY(hipStreamSynchronize(st->stream));

@@ -23,7 +23,7 @@ EXPORTS = [
     "mpsw_get_stats", "mpsw_get_shape", "mpsw_destroy", "mpsw_last_error", "mpsw_debug_laplacian_mpo",
     "mpsw_debug_factor", "mpsw_profile", "mpsw_profile_read", "mpsw_set_graph_mode",
     "mpsw_group_create", "mpsw_group_step", "mpsw_group_destroy", "mpsw_mlp_grad", "mpsw_mlp_train",
-    "mpsw_mlp_forward",
+    "mpsw_mlp_forward", "mpsw_rank_model_set", "mpsw_get_sigma_log",
 ]
 MLP_NPARAM = 21121
 
@@ -47,7 +47,7 @@ class Config(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("nsites", ctypes.c_int), ("bonds", ctypes.c_int * 64),
                 ("max_exact_bond", ctypes.c_int * 3), ("tail2", ctypes.c_double * 3),
-                ("fallbacks", ctypes.c_int64), ("max_jacobi_sweeps", ctypes.c_int)]
+                ("fallbacks", ctypes.c_int64), ("max_jacobi_sweeps", ctypes.c_int), ("sketches", ctypes.c_int64)]
 
 
 class KProf(ctypes.Structure):
@@ -90,6 +90,8 @@ def load():
         "mpsw_mlp_grad": [P, P, I, ctypes.c_float, P, P, P],
         "mpsw_mlp_train": [P, P, I, I, ctypes.c_float, ctypes.c_float, P],
         "mpsw_mlp_forward": [P, I, P, P],
+        "mpsw_rank_model_set": [P, P, I],
+        "mpsw_get_sigma_log": [P, I, I, P],
         "mpsw_profile_read": [P, I, ctypes.POINTER(KProf)],
     }
     for name, args in sig.items():
@@ -201,8 +203,19 @@ class State:
         _check(load().mpsw_get_stats(self._h, shot, ctypes.byref(s)))
         return {"step": s.step, "bonds": list(s.bonds[: self.K + 1]),
                 "max_exact_bond": list(s.max_exact_bond), "tail2": list(s.tail2),
-                "fallbacks": s.fallbacks, "max_jacobi_sweeps": s.max_jacobi_sweeps}
+                "fallbacks": s.fallbacks, "max_jacobi_sweeps": s.max_jacobi_sweeps, "sketches": s.sketches}
 
+
+    def set_rank_model(self, w):
+        """Parameters of the rank network for the learned-rank rounding."""
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _check(load().mpsw_rank_model_set(self._h, w.ctypes.data_as(ctypes.c_void_p), int(w.size)))
+
+    def sigma_log(self, shot=0, rounding=0):
+        """Leading 32 singular values of every bond of one rounding in the last step (K x 32)."""
+        out = np.zeros((self.K, 32))
+        _check(load().mpsw_get_sigma_log(self._h, shot, rounding, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
 
     def set_graph_mode(self, on=True):
         """Replay captured HIP graphs (three steps per launch) in step()."""
