@@ -2,7 +2,10 @@
 
 One step = the three roundings of the time step (Laplacian MPO, c^2 Hadamard,
 MPS sum + source), each an L->R QR sweep plus an R->L truncated SVD sweep
-(Sec. 4.3), for every shot of the batch.  The workload is the n = 10 grid
+(Sec. 4.3), for every shot of the batch.  The default measures the chosen form
+(32 shots advanced together, FP32 contractions, FP64 factorisations) and, beside
+it, the plain form (one shot, FP64 throughout) with the relative L2 difference
+of shot 0 between the two.  The workload is the n = 10 grid
 (1024 x 1024, dh = 10 m, dt = 1 ms) over the seeded layered-fault velocity model
 (c^2 MPO cutoff 1e-6), chi_max = 128, eps = 1e-6, Ricker 15 Hz sources at depth
 index 1.  Timing starts from a developed wavefield (a seeded superposition of
@@ -77,14 +80,35 @@ def read_traffic(kclass, workload, batch):
         return None
 
 
-def make_state(mpsw, synth, workload, batch, precision):
+def train_rank_model(mpsw, synth, steps=80):
+    """Rank network trained on spectra of an exact run of the n=8, chi=64 workload."""
+    from paper_2609_01904_amd import rankfeat
+    cfg = synth.get_config("C2", steps=steps)
+    n, chi = cfg["n"], cfg["chi"]
+    st = mpsw.State(mpsw.make_config(n, chi, cfg["eps"], cfg["lam"]))
+    st.set_velocity_dense(cfg["c2"], cfg["eps_c"])
+    up, u = synth.wavefront_fields(n, seed=5)
+    st.set_fields(0, up, u)
+    st.set_source(0, cfg["ix"], cfg["iz"], cfg["wavelet_samples"])
+    X, y = rankfeat.log_run(st, steps, chi)
+    st.close()
+    w0 = rankfeat.init_params(seed=1)
+    w = mpsw.mlp_train(X, y, w0, epochs=400, lr=2e-3, alpha=4.0)
+    return w, len(y)
+
+
+def make_state(mpsw, synth, workload, batch, precision, rank="exact", model=None):
     cfg = synth.get_config(workload)
     n = cfg["n"]
     N = 1 << n
     prec = {"fp64": mpsw.MPSW_FP64, "fp32": mpsw.MPSW_FP32, "bf16": mpsw.MPSW_BF16}[precision]
-    cfgs = [mpsw.make_config(n, cfg["chi"], cfg["eps"], cfg["lam"], precision=prec) for _ in range(batch)]
+    rmode = mpsw.MPSW_RANK_LEARNED if rank == "learned" else mpsw.MPSW_RANK_EXACT
+    cfgs = [mpsw.make_config(n, cfg["chi"], cfg["eps"], cfg["lam"], precision=prec, rank_mode=rmode, seed=11)
+            for _ in range(batch)]
     st = mpsw.State(cfgs if batch > 1 else cfgs[0])
     st.set_velocity_dense(cfg["c2"], cfg["eps_c"])
+    if model is not None:
+        st.set_rank_model(model)
     fields = []
     up0, u0 = synth.wavefront_fields(n, seed=0)
     for b in range(batch):
@@ -142,11 +166,17 @@ def copy_calibration(torch):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=1, help="shots advanced together")
+    ap.add_argument("--batch", type=int, default=32, help="shots advanced together")
     ap.add_argument("--workload", default="C3")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"],
+                    help="contraction arithmetic (factorisations and truncation stay FP64)")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the single-shot FP64 reference run (plain form, rel-L2 of shot 0)")
+    ap.add_argument("--rank", default="exact", choices=["exact", "learned"],
+                    help="learned: rank network (trained here on spectra logged from a short exact run of the "
+                         "n=8, chi=64 layered-model workload) + randomized range finder with exact fallback")
     ap.add_argument("--graph", action="store_true",
                     help="replay captured HIP graphs (three steps per launch) in the timed region; "
                          "the roofline kernel is then timed over an equal eager region after it")
@@ -177,7 +207,11 @@ def main():
     import synth
 
     t_setup = time.perf_counter()
-    st, cfg, fields = make_state(mpsw, synth, args.workload, args.batch, args.precision)
+    model = None
+    if args.rank == "learned":
+        model, nrows = train_rank_model(mpsw, synth)
+        log(f"rank network trained on {nrows} logged bonds in {time.perf_counter() - t_setup:.1f} s")
+    st, cfg, fields = make_state(mpsw, synth, args.workload, args.batch, args.precision, args.rank, model)
     torch.cuda.synchronize()
     log(f"setup {time.perf_counter() - t_setup:.1f} s; bonds {st.bonds(0, 0)}")
 
@@ -209,7 +243,8 @@ def main():
     prof = st.profile_read(kclass)
     stats = [st.stats(b) for b in range(args.batch)]
     log(f"timed {args.steps} steps x {args.batch} shots in {el:.3f} s; bonds {stats[0]['bonds']}; "
-        f"max Jacobi sweeps {stats[0]['max_jacobi_sweeps']}")
+        f"max Jacobi sweeps {stats[0]['max_jacobi_sweeps']}; sketches {sum(s['sketches'] for s in stats)} "
+        f"fallbacks {sum(s['fallbacks'] for s in stats)}")
 
     value = args.batch * args.steps / el
     avg_ms = prof["total_ms"] / max(prof["launches"], 1)
@@ -231,10 +266,34 @@ def main():
         "config": {"workload": f"{args.workload}: n={cfg['n']} (1024x1024), chi_max={cfg['chi']}, "
                                f"eps={cfg['eps']}, layered-fault c^2 (cutoff {cfg['eps_c']}), "
                                f"start from a developed wavefield at the chi cap",
-                   "shots": args.batch, "precision": args.precision, "rank": "exact SVD",
+                   "shots": args.batch, "precision": args.precision,
+                   "rank": "exact SVD" if args.rank == "exact" else "learned rank + range finder, exact fallback",
                    "graph": bool(args.graph)},
         "roofline": roofline,
     }
+    if not args.no_plain:
+        # plain form: one shot, FP64 contractions, exact SVD, from shot 0's start,
+        # the same number of steps; its last `steps` steps are timed
+        total = int(stats[0]["step"])
+        u_form = st.to_dense(0, 0)
+        pl, _, _ = make_state(mpsw, synth, args.workload, 1, "fp64")
+        up, u, ix = fields[0]
+        pl.set_fields(0, up, u)
+        pl.set_source(0, ix, cfg["iz"], cfg["wavelet_samples"])
+        pl.step(total - args.steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pl.step(args.steps)
+        torch.cuda.synchronize()
+        pel = time.perf_counter() - t0
+        u_ref = pl.to_dense(0, 0)
+        pl.close()
+        err = float(np.linalg.norm(u_form - u_ref) / np.linalg.norm(u_ref))
+        out["plain_fp64"] = {"value": args.steps / pel, "unit": "steps/s", "ms_per_step": pel * 1e3 / args.steps,
+                             "shots": 1, "precision": "fp64", "rank": "exact SVD"}
+        out["rel_l2_vs_fp64"] = {"value": err, "steps": total,
+                                 "what": "shot 0 of this run vs the plain single-shot FP64 run after the same steps"}
+        log(f"plain FP64 single shot: {args.steps / pel:.2f} steps/s; rel-L2 of shot 0 vs it {err:.2e}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(synth, args.workload, fields, args.cpu_seconds)
     st.close()

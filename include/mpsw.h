@@ -180,10 +180,11 @@ int mpsw_profile_read(mpsw_state st, int kclass, mpsw_kprof* out);
 /* Learned-rank rounding (rank_mode MPSW_RANK_LEARNED): for every bond of the
  * SVD sweep the rank network (parameters w, MPSW_MLP_NPARAM floats, host
  * memory copied) proposes r from the bond's leading singular values at the
- * previous step; a randomized range finder of width r + 8 with one power
- * iteration sketches the bond matrix (Gaussian test matrix from the state's
- * seed), the SVD stage runs on the sketch, and a FP64 residual test keeps it
- * or runs the exact SVD (counted in mpsw_stats.fallbacks).  Required before
+ * previous step; when r is below chi_max and r + 8 at most 3/4 of the bond
+ * matrix's smaller side, a randomized range finder of width r + 8 with one
+ * power iteration sketches the bond matrix (Gaussian test matrix from the
+ * state's seed), the SVD stage runs on the sketch, and a FP64 residual test
+ * keeps it or runs the exact SVD (counted in mpsw_stats.fallbacks).  Required before
  * stepping a learned-rank state.  Errors: EINVAL, EHIP. */
 int mpsw_rank_model_set(mpsw_state st, const float* w, int nw);
 

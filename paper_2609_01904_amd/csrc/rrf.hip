@@ -78,8 +78,10 @@ __global__ __launch_bounds__(MLP_NH) void k_rrf_plan(const DevCtx* __restrict__ 
     for (int i = 0; i < MLP_NH; ++i) o += h2[i];
     const int rhat = max(1, min(chi, (int)ceilf(o * (float)chi)));
     const int l = rhat + c.rrf_over;
-    // a sketch pays off only well below the full width, and needs a sigma log
-    const int ok = (lg[0] > 0.0) && (l <= MPSW_RRF_MAXL) && (4 * l <= 3 * cc) && m >= l && nn >= l;
+    // a sketch pays off only well below the full width and below the cap (a
+    // capped bond's flat tail rarely lets the residual test certify the
+    // capped error), and needs a sigma log
+    const int ok = (lg[0] > 0.0) && (rhat < chi) && (l <= MPSW_RRF_MAXL) && (4 * l <= 3 * cc) && m >= l && nn >= l;
     dm[DL::rrf] = ok ? 1 : 0;
     dm[DL::rrf_l] = ok ? l : 0;
     dm[DL::svd_n] = 0;
