@@ -172,6 +172,7 @@ def main():
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"],
                     help="contraction arithmetic (factorisations and truncation stay FP64)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the single-shot FP64 reference run (plain form, rel-L2 of shot 0)")
     ap.add_argument("--rank", default="exact", choices=["exact", "learned"],
@@ -215,6 +216,12 @@ def main():
     torch.cuda.synchronize()
     log(f"setup {time.perf_counter() - t_setup:.1f} s; bonds {st.bonds(0, 0)}")
 
+    tuned = None
+    if not args.no_tune:   # launch shapes for this bucket, the state is restored afterwards
+        t0 = time.perf_counter()
+        tuned = st.autotune(2)
+        log(f"autotune: QR workgroups per shot <= {tuned[0]}, Jacobi block {tuned[1] or 'rule'} "
+            f"({time.perf_counter() - t0:.1f} s)")
     if args.graph:
         st.set_graph_mode(True)
     st.step(max(args.warmup, 3 if args.graph else 0))
@@ -268,7 +275,9 @@ def main():
                                f"start from a developed wavefield at the chi cap",
                    "shots": args.batch, "precision": args.precision,
                    "rank": "exact SVD" if args.rank == "exact" else "learned rank + range finder, exact fallback",
-                   "graph": bool(args.graph)},
+                   "graph": bool(args.graph),
+                   "tuned": None if tuned is None else {"qr_workgroups_per_shot": tuned[0],
+                                                         "jacobi_block": tuned[1] or "rule"}},
         "roofline": roofline,
     }
     if not args.no_plain:
@@ -280,6 +289,8 @@ def main():
         up, u, ix = fields[0]
         pl.set_fields(0, up, u)
         pl.set_source(0, ix, cfg["iz"], cfg["wavelet_samples"])
+        if not args.no_tune:
+            pl.autotune(2)
         pl.step(total - args.steps)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

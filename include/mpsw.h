@@ -177,6 +177,15 @@ int mpsw_profile(mpsw_state st, int kclass);
 /* Read the counters of class `kclass`.  Synchronises.  Errors: EINVAL, EHIP. */
 int mpsw_profile_read(mpsw_state st, int kclass, mpsw_kprof* out);
 
+/* Autotuner of the launch shapes for this state's bucket (grid, chi cap,
+ * shot count, precision): times `steps` steps from the current state for
+ * each candidate Jacobi block width (rule, 8, 16, 32 columns) and then each
+ * cap on the workgroups per shot of a QR factorisation (32, 16, 8, 4), keeps
+ * the fastest pair, and restores the state exactly as it was (fields, bonds,
+ * step counters).  The chosen values are returned if the pointers are not
+ * NULL.  Synchronises.  Errors: EINVAL, ESTATE, ENOMEM, EHIP. */
+int mpsw_autotune(mpsw_state st, int steps, int* qr_nwg, int* jac_block);
+
 /* Learned-rank rounding (rank_mode MPSW_RANK_LEARNED): for every bond of the
  * SVD sweep the rank network (parameters w, MPSW_MLP_NPARAM floats, host
  * memory copied) proposes r from the bond's leading singular values at the

@@ -342,6 +342,8 @@ struct mpsw_state_s {
   // captured steps: one graph of three steps (a full turn of the psi slot
   // rotation) per rotation phase, replayed by mpsw_step in graph mode
   int gemm_mode = 0;                   // GemmMode of the step's contractions
+  int tune_qr_nwg = 32;                // most workgroups per shot of a QR factorisation
+  int tune_jac_b = 0;                  // Jacobi block width (0: rule from the column count)
   bool learned = false;                // learned-rank rounding (rank network + sketch)
   float* mlp_w = nullptr;              // rank network parameters on the device
   bool have_model = false;
@@ -477,10 +479,11 @@ int qr_panel(int64_t mcap) {
 // About 16 blocks per sweep spread a sweep over 8 workgroups; every block
 // pair's rotations are a sequence of b-wide steps, so smaller blocks only add
 // rounds (and barriers) without shortening the sequence.
-int jac_block(int64_t lcap) {
+int jac_block(int64_t lcap, int prefer = 0) {
   const size_t lim = lds_limit() - 1024;   // static LDS of the kernel
-  int want = 4;   // at most 16: one wave per column pair of a step
+  int want = 4;   // 32 groups of 16 lanes: at most 32 pairs per step
   while (want < 16 && want * 16 < lcap) want <<= 1;
+  if (prefer >= 1 && prefer <= 32) want = prefer;   // autotuned
   for (int b = want; b >= 1; b >>= 1)
     if ((size_t)2 * b * (lcap + 1) * 8 <= lim) return b;
   return 0;
@@ -579,7 +582,7 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
     if (!last) {
       const int64_t mcap = 2 * s.rt[k], ncap = s.rin[k + 1];
       const int bw = qr_panel(mcap);
-      const int nwg = (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(ncap, bw)));
+      const int nwg = (int)std::min<int64_t>(st->tune_qr_nwg, std::max<int64_t>(1, cdiv(ncap, bw)));
       OpArgs q{};
       q.shot = -1;
       q.site = k;
@@ -606,12 +609,12 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
       const int bw1 = qr_panel(rows), bw2 = qr_panel(ccap);
       OpArgs q = v;
       q.op = 1;
-      prof(st, MPSW_KC_QR, strm, [&] { launch_qrf(d, q, bw1, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(ccap, bw1))), nshots,
+      prof(st, MPSW_KC_QR, strm, [&] { launch_qrf(d, q, bw1, (int)std::min<int64_t>(st->tune_qr_nwg, std::max<int64_t>(1, cdiv(ccap, bw1))), nshots,
                  (size_t)rows * bw1 * 8, strm); });
       q.op = 2;
-      prof(st, MPSW_KC_QR, strm, [&] { launch_qrf(d, q, bw2, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(ccap, bw2))), nshots,
+      prof(st, MPSW_KC_QR, strm, [&] { launch_qrf(d, q, bw2, (int)std::min<int64_t>(st->tune_qr_nwg, std::max<int64_t>(1, cdiv(ccap, bw2))), nshots,
                  (size_t)ccap * bw2 * 8, strm); });
-      const int b = jac_block(ccap);
+      const int b = jac_block(ccap, st->tune_jac_b);
       const int64_t nb = cdiv(ccap, b);
       prof(st, MPSW_KC_JACOBI, strm, [&] { launch_jac(d, v, b, (int)std::max<int64_t>(1, (nb + (nb & 1)) / 2), nshots, (size_t)2 * b * (ccap + 1) * 8, ccap, strm); });
       launch_jacfin(d, v, nshots, strm);
@@ -648,7 +651,7 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
         q.aux = which;
         const int bw = qr_panel(mcap);
         launch_sync_reset(d, nshots, strm);
-        prof(st, MPSW_KC_QR, strm, [&] { launch_qrf(d, q, bw, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(lcap, bw))), nshots,
+        prof(st, MPSW_KC_QR, strm, [&] { launch_qrf(d, q, bw, (int)std::min<int64_t>(st->tune_qr_nwg, std::max<int64_t>(1, cdiv(lcap, bw))), nshots,
                    (size_t)mcap * bw * 8, strm); });
         prof(st, MPSW_KC_APPLYQ, strm, [&] { launch_formq(d, q, bw, std::max(1, cdiv(lcap, 16)), nshots, strm); });
       };
@@ -1388,6 +1391,82 @@ int mpsw_get_stats(mpsw_state st, int shot, mpsw_stats* out) {
 //         (the identity merge when m <= n: Q = I, R = A);
 //   op 1: SVD of A (m x n, n even): out1 = V^T (r x n), out2 = U Sigma (m x r),
 //         r = min(m, n) (no truncation); returns r.
+int mpsw_autotune(mpsw_state st, int steps, int* qr_nwg, int* jac_block_out) {
+  if (!st || steps < 1) return fail(MPSW_EINVAL, "null state or steps < 1");
+  if (!st->have_velocity) return fail(MPSW_ESTATE, "set the velocity before tuning");
+  if (st->learned && !st->have_model) return fail(MPSW_ESTATE, "set the rank model before tuning");
+  HIP_TRY(hipStreamSynchronize(st->stream));
+  // snapshot of everything a step changes: MPS arena, dims, reals, rotation
+  const size_t nm = (size_t)st->mps_stride * st->B, nd = (size_t)DL::size * st->B, nr = (size_t)RL::size * st->B;
+  double *sm = nullptr, *sr = nullptr;
+  int* sd = nullptr;
+  auto cleanup = [&]() {
+    hipFree(sm);
+    hipFree(sd);
+    hipFree(sr);
+  };
+  if (hipMalloc(&sm, nm * 8) != hipSuccess || hipMalloc(&sd, nd * 4) != hipSuccess || hipMalloc(&sr, nr * 8) != hipSuccess) {
+    cleanup();
+    return fail(MPSW_ENOMEM, "tuning snapshot");
+  }
+  const int cur = st->cur, prev = st->prev, nxt = st->nxt;
+  const int64_t step0 = st->step;
+  const bool graph = st->graph_mode;
+  st->graph_mode = false;
+  auto save = [&]() {
+    return hipMemcpy(sm, st->mps, nm * 8, hipMemcpyDeviceToDevice) == hipSuccess &&
+           hipMemcpy(sd, st->dims, nd * 4, hipMemcpyDeviceToDevice) == hipSuccess &&
+           hipMemcpy(sr, st->reals, nr * 8, hipMemcpyDeviceToDevice) == hipSuccess;
+  };
+  auto restore = [&]() {
+    st->cur = cur; st->prev = prev; st->nxt = nxt; st->step = step0;
+    return hipMemcpy(st->mps, sm, nm * 8, hipMemcpyDeviceToDevice) == hipSuccess &&
+           hipMemcpy(st->dims, sd, nd * 4, hipMemcpyDeviceToDevice) == hipSuccess &&
+           hipMemcpy(st->reals, sr, nr * 8, hipMemcpyDeviceToDevice) == hipSuccess &&
+           hipDeviceSynchronize() == hipSuccess;
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float best = 1e30f;
+  int best_q = st->tune_qr_nwg, best_b = st->tune_jac_b;
+  bool ok = save() && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  auto trial = [&](int q, int b) {
+    if (!ok) return;
+    st->tune_qr_nwg = q;
+    st->tune_jac_b = b;
+    ok = restore();
+    if (!ok) return;
+    hipEventRecord(e0, st->stream);
+    for (int i = 0; i < steps; ++i) enqueue_step(st, st->stream);
+    hipEventRecord(e1, st->stream);
+    ok = hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.0f;
+    if (ok) ok = hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    if (ok && ms < best) {
+      best = ms;
+      best_q = q;
+      best_b = b;
+    }
+  };
+  // one factor at a time: the Jacobi block width, then the QR workgroups
+  for (int b : {0, 8, 16, 32}) trial(32, b);
+  const int bb = best_b;
+  for (int q : {16, 8, 4}) trial(q, bb);
+  st->tune_qr_nwg = best_q;
+  st->tune_jac_b = best_b;
+  if (ok) ok = restore();
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  cleanup();
+  st->graph_mode = graph;
+  drop_graphs(st);
+  if (!ok) return fail(MPSW_EHIP, "tuning run failed");
+  int rc = check_dev_err(st);
+  if (rc != MPSW_OK) return rc;
+  if (qr_nwg) *qr_nwg = best_q;
+  if (jac_block_out) *jac_block_out = best_b;
+  return MPSW_OK;
+}
+
 int mpsw_rank_model_set(mpsw_state st, const float* w, int nw) {
   if (!st || !w || nw != MLP_NPARAM) return fail(MPSW_EINVAL, "null argument or wrong parameter count");
   if (!st->mlp_w) HIP_TRY(hipMalloc(&st->mlp_w, MLP_NPARAM * sizeof(float)));

@@ -23,7 +23,7 @@ EXPORTS = [
     "mpsw_get_stats", "mpsw_get_shape", "mpsw_destroy", "mpsw_last_error", "mpsw_debug_laplacian_mpo",
     "mpsw_debug_factor", "mpsw_profile", "mpsw_profile_read", "mpsw_set_graph_mode",
     "mpsw_group_create", "mpsw_group_step", "mpsw_group_destroy", "mpsw_mlp_grad", "mpsw_mlp_train",
-    "mpsw_mlp_forward", "mpsw_rank_model_set", "mpsw_get_sigma_log",
+    "mpsw_mlp_forward", "mpsw_rank_model_set", "mpsw_get_sigma_log", "mpsw_autotune",
 ]
 MLP_NPARAM = 21121
 
@@ -92,6 +92,7 @@ def load():
         "mpsw_mlp_forward": [P, I, P, P],
         "mpsw_rank_model_set": [P, P, I],
         "mpsw_get_sigma_log": [P, I, I, P],
+        "mpsw_autotune": [P, I, ctypes.POINTER(I), ctypes.POINTER(I)],
         "mpsw_profile_read": [P, I, ctypes.POINTER(KProf)],
     }
     for name, args in sig.items():
@@ -216,6 +217,12 @@ class State:
         out = np.zeros((self.K, 32))
         _check(load().mpsw_get_sigma_log(self._h, shot, rounding, out.ctypes.data_as(ctypes.c_void_p)))
         return out
+
+    def autotune(self, steps=2):
+        """Pick the launch shapes by timing `steps` steps per candidate; the state is restored."""
+        q, b = ctypes.c_int(), ctypes.c_int()
+        _check(load().mpsw_autotune(self._h, int(steps), ctypes.byref(q), ctypes.byref(b)))
+        return q.value, b.value
 
     def set_graph_mode(self, on=True):
         """Replay captured HIP graphs (three steps per launch) in step()."""

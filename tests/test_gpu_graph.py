@@ -112,3 +112,29 @@ def test_group_of_mixed_grids_matches_eager(mpsw):
     grp.close()
     for st in grouped + single:
         st.close()
+
+
+def test_autotune_restores_state_and_keeps_results(mpsw):
+    import torch
+    n, eps, lam = 5, 1e-9, 0.5
+    N = 1 << n
+    c2 = synth.layered_fault_velocity(n, dh=40.0) * 1e-8
+    wav = synth.ricker(40, 0.004, 20.0)
+    st = _state(mpsw, n, [32, 16], eps, lam, c2, [(N // 2, 1), (3, 2)], wav)
+    st.step(5)
+    torch.cuda.synchronize()
+    before = [st.to_dense(s, w) for s in range(2) for w in (0, 1)]
+    bonds = [st.bonds(s, 0) for s in range(2)]
+    q, b = st.autotune(2)
+    _say("autotune chose", q, b)
+    assert q in (32, 16, 8, 4) and b in (0, 8, 16, 32)
+    after = [st.to_dense(s, w) for s in range(2) for w in (0, 1)]
+    assert all(np.array_equal(x, y) for x, y in zip(before, after))
+    assert [st.bonds(s, 0) for s in range(2)] == bonds
+    assert st.stats(0)["step"] == 5
+    st.step(10)
+    ds = S.DenseStepper(n, lam, eps, 32, st.to_dense(0, 2), src=(N // 2, 1), wavelet=wav)
+    for _ in range(15):
+        ds.step()
+    assert rel(st.to_dense(0, 0), ds.dense()) < 1e-10
+    st.close()
