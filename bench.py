@@ -170,7 +170,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=32, help="shots advanced together")
     ap.add_argument("--workload", default="C3")
-    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"],
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"],
                     help="contraction arithmetic (factorisations and truncation stay FP64)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-plain", action="store_true",

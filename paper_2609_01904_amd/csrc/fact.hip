@@ -720,15 +720,13 @@ __device__ __forceinline__ bool jacobi_angle(double al, double be, double ga, do
   return true;
 }
 
+// Columns of 16 EPL rows (zero padded in LDS beyond the live length, so no
+// element needs a bounds check).  The first column may live in registers (x).
 template <int EPL>
-__device__ __forceinline__ double rotate_pair(double* ap, double* aq, int gl, int Lc, double tol2, double floor2) {
-  double x[EPL], y[EPL];
+__device__ __forceinline__ double rotate_reg(double (&x)[EPL], double* aq, int gl, double tol2, double floor2) {
+  double y[EPL];
 #pragma unroll
-  for (int e = 0; e < EPL; ++e) {
-    const int i = gl + 16 * e;
-    x[e] = (i < Lc) ? ap[i] : 0.0;
-    y[e] = (i < Lc) ? aq[i] : 0.0;
-  }
+  for (int e = 0; e < EPL; ++e) y[e] = aq[gl + 16 * e];
   // two accumulators per sum halve the dependent chains
   double al0 = 0.0, be0 = 0.0, ga0 = 0.0, al1 = 0.0, be1 = 0.0, ga1 = 0.0;
 #pragma unroll
@@ -747,12 +745,21 @@ __device__ __forceinline__ double rotate_pair(double* ap, double* aq, int gl, in
   if (!jacobi_angle(al, be, ga, tol2, floor2, rel2, cs, sn)) return rel2;
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
-    const int i = gl + 16 * e;
-    if (i < Lc) {
-      ap[i] = cs * x[e] - sn * y[e];
-      aq[i] = sn * x[e] + cs * y[e];
-    }
+    const double xe = x[e], ye = y[e];
+    x[e] = cs * xe - sn * ye;
+    aq[gl + 16 * e] = sn * xe + cs * ye;
   }
+  return rel2;
+}
+
+template <int EPL>
+__device__ __forceinline__ double rotate_pair(double* ap, double* aq, int gl, int Lc, double tol2, double floor2) {
+  double x[EPL];
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) x[e] = ap[gl + 16 * e];
+  const double rel2 = rotate_reg<EPL>(x, aq, gl, tol2, floor2);
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) ap[gl + 16 * e] = x[e];
   return rel2;
 }
 
@@ -807,7 +814,15 @@ __global__ __launch_bounds__(JNT) void k_jac(const DevCtx* __restrict__ cp, OpAr
   if (!ok && w == 0 && t == 0) raise_err(c, (pact > P || b > JNT / 16) ? MPSW_DEV_ERR_GRID : MPSW_DEV_ERR_CAP);
   double* A = E + c.L.off_sA;
   extern __shared__ double blk[];   // 2b columns, stride ldl
-  const int ldl = Lc + 1;
+  // EPL > 0: columns padded with zeros to 16 EPL rows (rotations keep the
+  // padding zero); the odd stride spreads the columns over the LDS banks
+  const int ldl = (EPL > 0) ? 16 * EPL + 1 : Lc + 1;
+  if (EPL > 0 && Lc > 16 * EPL) {
+    if (w == 0 && t == 0) raise_err(c, MPSW_DEV_ERR_CAP);
+    return;
+  }
+  for (int e = t; e < 2 * b * ldl; e += blockDim.x) blk[e] = 0.0;
+  __syncthreads();
   __shared__ int nrot;
   __shared__ unsigned int maxrel;   // float bits of the largest squared cosine
   __shared__ double fro_red[16];
@@ -863,12 +878,32 @@ __global__ __launch_bounds__(JNT) void k_jac(const DevCtx* __restrict__ cp, OpAr
         } else if (np_ > 0 && nq_ > 0) {   // cross pairs only
           const int na = max(np_, nq_), ns = min(np_, nq_);
           const int a0 = (np_ >= nq_) ? 0 : np_, s0 = (np_ >= nq_) ? np_ : 0;
-          for (int s = 0; s < na; ++s) {
+          if constexpr (EPL > 0) {
+            // group g keeps its column of the smaller block in registers for
+            // the whole round; the other block's columns pass through LDS
+            double x[EPL];
+            double* ap = blk + (s0 + g) * ldl;
             if (g < ns) {
-              const int p = s0 + g, q = a0 + (g + s) % na;
-              note(rotate_pair<EPL>(blk + p * ldl, blk + q * ldl, gl, Lc, tol2, floor2));
+#pragma unroll
+              for (int e = 0; e < EPL; ++e) x[e] = ap[gl + 16 * e];
+            }
+            for (int s = 0; s < na; ++s) {
+              if (g < ns) note(rotate_reg<EPL>(x, blk + (a0 + (g + s) % na) * ldl, gl, tol2, floor2));
+              __syncthreads();
+            }
+            if (g < ns) {
+#pragma unroll
+              for (int e = 0; e < EPL; ++e) ap[gl + 16 * e] = x[e];
             }
             __syncthreads();
+          } else {
+            for (int s = 0; s < na; ++s) {
+              if (g < ns) {
+                const int p = s0 + g, q = a0 + (g + s) % na;
+                note(rotate_pair<EPL>(blk + p * ldl, blk + q * ldl, gl, Lc, tol2, floor2));
+              }
+              __syncthreads();
+            }
           }
         }
         bulk_copy<8>(ncol * Lc, t, blockDim.x, [&](int e) { return blk[(e / Lc) * ldl + (e % Lc)]; },
@@ -1038,14 +1073,23 @@ void launch_formq(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots,
     hipLaunchKernelGGL(k_formq<4>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
 }
 
+// Rows a Jacobi column occupies in LDS for a column length of at most lcap.
+int jac_rows(int64_t lcap) {
+  for (int r = 32; r <= 512; r <<= 1)
+    if (lcap <= r) return r;
+  return (int)lcap;
+}
+
 void launch_jac(const DevCtx* d, const OpArgs& a, int b, int nwg, int nshots, size_t lds, int64_t lcap, hipStream_t s) {
+  (void)lds;
   const dim3 g(nwg, 1, nshots), blk(JNT);
-  if (lcap <= 32) hipLaunchKernelGGL(k_jac<2>, g, blk, lds, s, d, a, b);
-  else if (lcap <= 64) hipLaunchKernelGGL(k_jac<4>, g, blk, lds, s, d, a, b);
-  else if (lcap <= 128) hipLaunchKernelGGL(k_jac<8>, g, blk, lds, s, d, a, b);
-  else if (lcap <= 256) hipLaunchKernelGGL(k_jac<16>, g, blk, lds, s, d, a, b);
-  else if (lcap <= 512) hipLaunchKernelGGL(k_jac<32>, g, blk, lds, s, d, a, b);
-  else hipLaunchKernelGGL(k_jac<0>, g, blk, lds, s, d, a, b);
+  const size_t bytes = (size_t)2 * b * (jac_rows(lcap) + 1) * sizeof(double);
+  if (lcap <= 32) hipLaunchKernelGGL(k_jac<2>, g, blk, bytes, s, d, a, b);
+  else if (lcap <= 64) hipLaunchKernelGGL(k_jac<4>, g, blk, bytes, s, d, a, b);
+  else if (lcap <= 128) hipLaunchKernelGGL(k_jac<8>, g, blk, bytes, s, d, a, b);
+  else if (lcap <= 256) hipLaunchKernelGGL(k_jac<16>, g, blk, bytes, s, d, a, b);
+  else if (lcap <= 512) hipLaunchKernelGGL(k_jac<32>, g, blk, bytes, s, d, a, b);
+  else hipLaunchKernelGGL(k_jac<0>, g, blk, bytes, s, d, a, b);
 }
 
 void launch_jacfin(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s) {

@@ -55,6 +55,7 @@ void launch_qrf(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, s
 void launch_applyq(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, hipStream_t s);
 void launch_applyv(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, hipStream_t s);
 void launch_jac(const DevCtx* d, const OpArgs& a, int b, int nwg, int nshots, size_t lds, int64_t lcap, hipStream_t s);
+int jac_rows(int64_t lcap);
 void launch_jacfin(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
 void set_lds_limits(size_t bytes);
 void launch_formq(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, hipStream_t s);

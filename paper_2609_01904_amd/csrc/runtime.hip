@@ -485,7 +485,7 @@ int jac_block(int64_t lcap, int prefer = 0) {
   while (want < 16 && want * 16 < lcap) want <<= 1;
   if (prefer >= 1 && prefer <= 32) want = prefer;   // autotuned
   for (int b = want; b >= 1; b >>= 1)
-    if ((size_t)2 * b * (lcap + 1) * 8 <= lim) return b;
+    if ((size_t)2 * b * (jac_rows(lcap) + 1) * 8 <= lim) return b;
   return 0;
 }
 
