@@ -214,7 +214,9 @@ def main():
         log(f"rank network trained on {nrows} logged bonds in {time.perf_counter() - t_setup:.1f} s")
     st, cfg, fields = make_state(mpsw, synth, args.workload, args.batch, args.precision, args.rank, model)
     torch.cuda.synchronize()
-    log(f"setup {time.perf_counter() - t_setup:.1f} s; bonds {st.bonds(0, 0)}")
+    free, total = torch.cuda.mem_get_info()
+    log(f"setup {time.perf_counter() - t_setup:.1f} s; bonds {st.bonds(0, 0)}; "
+        f"device memory in use {(total - free) / 2**30:.1f} of {total / 2**30:.0f} GiB")
 
     tuned = None
     if not args.no_tune:   # launch shapes for this bucket, the state is restored afterwards

@@ -48,7 +48,13 @@ enum {
   MPSW_ENONFINITE = -6  /* a non-finite value was produced (detected at a sync) */
 };
 
-enum { MPSW_FP64 = 0, MPSW_FP32 = 1, MPSW_BF16 = 2 };          /* contraction precision */
+/* Contraction precision.  QR, Jacobi SVD, truncation and storage stay FP64.
+   MPSW_FP32: operands rounded to FP32, FP32 matrix-core products.
+   MPSW_BF16: each operand split into three BF16 parts (hi + mid + lo), six of
+   the nine partial products on BF16 matrix cores (the refinement terms carry
+   what one BF16 part drops).  In both, FP32 sums of 16-deep slices are
+   accumulated in FP64. */
+enum { MPSW_FP64 = 0, MPSW_FP32 = 1, MPSW_BF16 = 2 };
 enum { MPSW_PERIODIC = 0, MPSW_OPEN = 1 };                     /* shift boundary */
 enum { MPSW_RANK_EXACT = 0, MPSW_RANK_LEARNED = 1 };           /* truncation rank mode */
 

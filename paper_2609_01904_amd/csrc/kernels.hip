@@ -301,28 +301,35 @@ __global__ __launch_bounds__(256) void k_gemm(const DevCtx* __restrict__ cp, OpA
               acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)av, (float)bv, acc32[i][j], 0, 0, 0);
           }
       }
-    } else {   // BF16 x 3
-      gs4 ahi[2], alo[2], bhi[2], blo[2];
+    } else {   // BF16 x 6: three BF16 parts per operand, six of the nine partial products
+      gs4 ap[3][2], bp[3][2];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const float x = (float)As[4 * lq + q][wm + 16 * i + li];
-          const short h = bf16_rne(x);
-          ahi[i][q] = h;
-          alo[i][q] = bf16_rne(x - bf16_val(h));
-          const float y = (float)Bs[4 * lq + q][wn + 16 * i + li];
-          const short hy = bf16_rne(y);
-          bhi[i][q] = hy;
-          blo[i][q] = bf16_rne(y - bf16_val(hy));
+          float x = (float)As[4 * lq + q][wm + 16 * i + li];
+          float y = (float)Bs[4 * lq + q][wn + 16 * i + li];
+#pragma unroll
+          for (int p = 0; p < 3; ++p) {
+            const short hx = bf16_rne(x), hy = bf16_rne(y);
+            ap[p][i][q] = hx;
+            bp[p][i][q] = hy;
+            x -= bf16_val(hx);
+            y -= bf16_val(hy);
+          }
         }
+      // smallest terms first: lo.hi, hi.lo (2^-18), mid.mid, mid.hi, hi.mid (2^-9), hi.hi;
+      // the dropped mid.lo, lo.mid, lo.lo are below 2^-26 of the product
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo[i], bhi[j], acc32[i][j], 0, 0, 0);
-          acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[i], blo[j], acc32[i][j], 0, 0, 0);
-          acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[i], bhi[j], acc32[i][j], 0, 0, 0);
+          acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ap[2][i], bp[0][j], acc32[i][j], 0, 0, 0);
+          acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ap[0][i], bp[2][j], acc32[i][j], 0, 0, 0);
+          acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ap[1][i], bp[1][j], acc32[i][j], 0, 0, 0);
+          acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ap[1][i], bp[0][j], acc32[i][j], 0, 0, 0);
+          acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ap[0][i], bp[1][j], acc32[i][j], 0, 0, 0);
+          acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ap[0][i], bp[0][j], acc32[i][j], 0, 0, 0);
         }
     }
     if (MODE != GEMM_FP64) {   // FP32 sums of one 16-deep slice, accumulated across slices in FP64
@@ -539,7 +546,7 @@ void launch_gemm(const DevCtx* d, const OpArgs& a, int grid_tiles, int grid_batc
   if (grid_tiles <= 0 || grid_batch <= 0) return;
   const dim3 g(grid_tiles, grid_batch, nshots);
   if (a.mode == GEMM_FP32) hipLaunchKernelGGL(k_gemm<GEMM_FP32>, g, dim3(256), 0, s, d, a);
-  else if (a.mode == GEMM_BF16X3) hipLaunchKernelGGL(k_gemm<GEMM_BF16X3>, g, dim3(256), 0, s, d, a);
+  else if (a.mode == GEMM_BF16X6) hipLaunchKernelGGL(k_gemm<GEMM_BF16X6>, g, dim3(256), 0, s, d, a);
   else hipLaunchKernelGGL(k_gemm<GEMM_FP64>, g, dim3(256), 0, s, d, a);
 }
 void launch_prepare(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s) {

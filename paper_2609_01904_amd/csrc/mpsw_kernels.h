@@ -27,7 +27,7 @@ enum Gate { GATE_ALWAYS = 0, GATE_SKETCH = 1, GATE_EXACT = 2, GATE_ACCEPTED = 3 
 enum GemmMode {
   GEMM_FP64 = 0,   // FP64 matrix cores
   GEMM_FP32 = 1,   // operands rounded to FP32, FP32 matrix cores, FP32 accumulation
-  GEMM_BF16X3 = 2  // operands split x = hi + lo in BF16, hi*hi + hi*lo + lo*hi, FP32 accumulation
+  GEMM_BF16X6 = 2  // operands split x = hi + mid + lo in BF16, six of the nine partial products, FP32 accumulation
 };
 
 // Rounding input kinds (k_prepare / k_init_R).
@@ -41,7 +41,7 @@ struct OpArgs {
   int aux;     // op-specific flag (buffer select, rounding index)
   int step;    // step index (source sample)
   int shot;    // restrict to one shot (-1 = all)
-  int mode;    // contraction arithmetic of k_gemm: GEMM_FP64, GEMM_FP32 or GEMM_BF16X3
+  int mode;    // contraction arithmetic of k_gemm: GEMM_FP64, GEMM_FP32 or GEMM_BF16X6
   int gate;    // Gate: run only while the bond's sketch state allows it
 };
 

@@ -884,7 +884,7 @@ int create_group(const mpsw_config* cfgs, int nshots, void* stream, mpsw_state* 
   }
   mpsw_state st = new mpsw_state_s();
   st->B = nshots;
-  st->gemm_mode = (c0.precision == MPSW_FP32) ? GEMM_FP32 : (c0.precision == MPSW_BF16) ? GEMM_BF16X3 : GEMM_FP64;
+  st->gemm_mode = (c0.precision == MPSW_FP32) ? GEMM_FP32 : (c0.precision == MPSW_BF16) ? GEMM_BF16X6 : GEMM_FP64;
   st->learned = (c0.rank_mode == MPSW_RANK_LEARNED);
   st->n = c0.n;
   st->K = 2 * c0.n;
