@@ -841,10 +841,14 @@ __global__ __launch_bounds__(JNT) void k_jac(const DevCtx* __restrict__ cp, OpAr
   // the eigen stage of an SVD of a c x c factor, 9 c^3 by the standard count
   if (ok && w == 0 && t == 0) count_flops(c, shot, MPSW_KC_JACOBI, 9.0 * (double)cc * cc * cc);
   const int g = t >> 4, gl = t & 15, ng = JNT / 16;
-  auto note = [&](double rel2) {   // one lane per group
-    if (gl == 0 && rel2 >= 0.0) {
-      if (rel2 > tol2) atomicAdd(&nrot, 1);
-      atomicMax(&maxrel, __float_as_uint((float)fmin(rel2, 1.0)));
+  // rotations applied and the largest squared cosine seen, kept per group in
+  // registers and merged once per round
+  int myrot = 0;
+  float mymax = 0.0f;
+  auto note = [&](double rel2) {
+    if (rel2 >= 0.0) {
+      myrot += (rel2 > tol2) ? 1 : 0;
+      mymax = fmaxf(mymax, (float)fmin(rel2, 1.0));
     }
   };
   for (int sweep = 0; sweep < MPSW_MAX_SWEEPS; ++sweep) {
@@ -863,39 +867,61 @@ __global__ __launch_bounds__(JNT) void k_jac(const DevCtx* __restrict__ cp, OpAr
                      [&](int e) { return A[(int64_t)gcol(e / Lc) * Lc + (e % Lc)]; },
                      [&](int e, double v) { blk[(e / Lc) * ldl + (e % Lc)] = v; });
         __syncthreads();
-        if (rnd == 0) {   // all pairs among the loaded columns, round-robin
-          const int npl = ncol + (ncol & 1);
-          for (int ir = 0; ir < npl - 1; ++ir) {
-            for (int pi = g; pi < npl / 2; pi += ng) {
+        if (rnd == 0) {
+          // internal pairs of both blocks at once: two round-robin
+          // tournaments, the first hp pair slots for block P, the rest for Q
+          const int npp = np_ + (np_ & 1), nqq = nq_ + (nq_ & 1);
+          const int hp = npp / 2, hq = nqq / 2;
+          const int nst = max(npp, nqq) - 1;
+          for (int ir = 0; ir < nst; ++ir) {
+            for (int pi = g; pi < hp + hq; pi += ng) {
+              const bool inq = (pi >= hp);
+              const int nn = inq ? nqq : npp, cnt = inq ? nq_ : np_, off = inq ? np_ : 0;
+              const int pj = inq ? pi - hp : pi;
+              if (ir >= nn - 1) continue;
               int p, q;
-              if (pi == 0) { p = ir; q = npl - 1; }
-              else { p = (ir + pi) % (npl - 1); q = (ir - pi + (npl - 1)) % (npl - 1); }
-              if (p >= ncol || q >= ncol) continue;
-              note(rotate_pair<EPL>(blk + p * ldl, blk + q * ldl, gl, Lc, tol2, floor2));
+              if (pj == 0) { p = ir; q = nn - 1; }
+              else { p = (ir + pj) % (nn - 1); q = (ir - pj + (nn - 1)) % (nn - 1); }
+              if (p >= cnt || q >= cnt) continue;
+              note(rotate_pair<EPL>(blk + (off + p) * ldl, blk + (off + q) * ldl, gl, Lc, tol2, floor2));
             }
             __syncthreads();
           }
-        } else if (np_ > 0 && nq_ > 0) {   // cross pairs only
+        }
+        if (np_ > 0 && nq_ > 0) {   // the b x b cross pairs
           const int na = max(np_, nq_), ns = min(np_, nq_);
           const int a0 = (np_ >= nq_) ? 0 : np_, s0 = (np_ >= nq_) ? np_ : 0;
           if constexpr (EPL > 0) {
-            // group g keeps its column of the smaller block in registers for
-            // the whole round; the other block's columns pass through LDS
+            // Group g keeps column g of the smaller block in registers.  The
+            // larger block is cut into chunks of 4 columns; in phase ph wave v
+            // (groups 4v..4v+3) owns chunk (v + ph) mod nc alone and its four
+            // groups meet the chunk's four columns in four steps, handing
+            // columns to each other within the wave, so the workgroup only
+            // synchronises between phases.  Active waves are v < ceil(ns/4)
+            // <= nc, so no two waves own one chunk.
             double x[EPL];
+            const bool act = g < ns;
             double* ap = blk + (s0 + g) * ldl;
-            if (g < ns) {
+            if (act) {
 #pragma unroll
               for (int e = 0; e < EPL; ++e) x[e] = ap[gl + 16 * e];
             }
-            for (int s = 0; s < na; ++s) {
-              if (g < ns) note(rotate_reg<EPL>(x, blk + (a0 + (g + s) % na) * ldl, gl, tol2, floor2));
+            const int nc = (na + 3) >> 2, wq = g >> 2, gi = g & 3;
+            for (int ph = 0; ph < nc; ++ph) {
+              const int ch = (wq + ph) % nc;
+              for (int st = 0; st < 4; ++st) {
+                const int col = 4 * ch + ((gi + st) & 3);
+                if (act && col < na) note(rotate_reg<EPL>(x, blk + (a0 + col) * ldl, gl, tol2, floor2));
+                // the column just written is read by the neighbouring group of
+                // this wave in the next step
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+              }
               __syncthreads();
             }
-            if (g < ns) {
+            if (act) {
 #pragma unroll
               for (int e = 0; e < EPL; ++e) ap[gl + 16 * e] = x[e];
             }
-            __syncthreads();
           } else {
             for (int s = 0; s < na; ++s) {
               if (g < ns) {
@@ -906,6 +932,13 @@ __global__ __launch_bounds__(JNT) void k_jac(const DevCtx* __restrict__ cp, OpAr
             }
           }
         }
+        if (gl == 0 && (myrot > 0 || mymax > 0.0f)) {
+          atomicAdd(&nrot, myrot);
+          atomicMax(&maxrel, __float_as_uint(mymax));
+        }
+        myrot = 0;
+        mymax = 0.0f;
+        __syncthreads();
         bulk_copy<8>(ncol * Lc, t, blockDim.x, [&](int e) { return blk[(e / Lc) * ldl + (e % Lc)]; },
                      [&](int e, double v) { A[(int64_t)gcol(e / Lc) * Lc + (e % Lc)] = v; });
         if (t == 0) {
