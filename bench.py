@@ -260,9 +260,14 @@ def main():
     flops_per_launch = prof["alg_flops"] / max(prof["launches"], 1)
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     traffic = read_traffic(kclass, args.workload, args.batch)
-    # every kernel of the FP64 path computes on the FP64 vector ALUs
-    roofline = {"bound": "alu", "achieved": achieved,
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+    # contractions run on the matrix cores (dense peak of their operand type);
+    # the factorisation kernels on the FP64 vector ALUs
+    if KERNEL_NAMES[kclass] == "k_gemm":
+        bound, peak = "mfma", {"fp64": PEAK_FP64_TFLOPS, "fp32": 157.3, "bf16": 2500.0}[args.precision]
+    else:
+        bound, peak = "alu", PEAK_FP64_TFLOPS
+    roofline = {"bound": bound, "achieved": achieved,
+                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": traffic, "kernel": KERNEL_NAMES[kclass], "launches": prof["launches"],
                 "avg_launch_ms": avg_ms, "alg_flops_per_launch": flops_per_launch,
                 "share_of_step_time": prof["total_ms"] / (el * 1e3)}

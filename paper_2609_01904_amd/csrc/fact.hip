@@ -863,7 +863,7 @@ __global__ __launch_bounds__(JNT) void k_jac(const DevCtx* __restrict__ cp, OpAr
         const int ncol = np_ + nq_;
         if (t == 0) { nrot = 0; maxrel = 0u; }
         auto gcol = [&](int jj) { return (jj < np_) ? bp * b + jj : bq * b + (jj - np_); };
-        bulk_copy<8>(ncol * Lc, t, blockDim.x,
+        bulk_copy<32>(ncol * Lc, t, blockDim.x,
                      [&](int e) { return A[(int64_t)gcol(e / Lc) * Lc + (e % Lc)]; },
                      [&](int e, double v) { blk[(e / Lc) * ldl + (e % Lc)] = v; });
         __syncthreads();
@@ -939,7 +939,7 @@ __global__ __launch_bounds__(JNT) void k_jac(const DevCtx* __restrict__ cp, OpAr
         myrot = 0;
         mymax = 0.0f;
         __syncthreads();
-        bulk_copy<8>(ncol * Lc, t, blockDim.x, [&](int e) { return blk[(e / Lc) * ldl + (e % Lc)]; },
+        bulk_copy<32>(ncol * Lc, t, blockDim.x, [&](int e) { return blk[(e / Lc) * ldl + (e % Lc)]; },
                      [&](int e, double v) { A[(int64_t)gcol(e / Lc) * Lc + (e % Lc)] = v; });
         if (t == 0) {
           if (nrot > 0) atomicAdd(sy + MPSW_SYNC_ROT + (sweep & 63), nrot);

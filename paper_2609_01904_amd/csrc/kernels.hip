@@ -196,10 +196,10 @@ __device__ bool plan_gemm(const DevCtx& c, const OpArgs& a, int shot, int z, int
   return true;
 }
 
-// C = A * B on the matrix cores: 64 x 64 output tiles per 256-thread
-// workgroup, each wave a 32 x 32 quarter (2 x 2 tiles of 16 x 16); K in
-// slices of 16 staged through LDS as FP64, the next slice's global loads in
-// flight while the current one is multiplied.  Lane layouts (checked on the
+// C = A * B on the matrix cores: TS x TS output tiles per 256-thread
+// workgroup (TS = 64), each wave a quarter (2 x 2 tiles of 16 x 16); K in
+// slices of KS = 16 staged through two LDS buffers as FP64, the next slice's
+// global loads in flight while the current one is multiplied.  Lane layouts (checked on the
 // device): f64 16x16x4 and f32 16x16x4 take a = A[l%16][l/16], b = B[l/16][l%16];
 // bf16 16x16x16 takes a[q] = A[l%16][4(l/16)+q], b[q] = B[4(l/16)+q][l%16];
 // results are D[l/16 + 4v][l%16] (f64) and D[4(l/16) + v][l%16] (f32 accumulators).
@@ -215,46 +215,50 @@ __device__ __forceinline__ short bf16_rne(float x) {   // round to nearest even 
 }
 __device__ __forceinline__ float bf16_val(short h) { return __uint_as_float(((unsigned)(unsigned short)h) << 16); }
 
-template <int MODE>
+template <int MODE, int TS, int KS>
 __global__ __launch_bounds__(256) void k_gemm(const DevCtx* __restrict__ cp, OpArgs a) {
+  static_assert(TS == 64 || (TS == 128 && MODE == GEMM_FP64), "128-wide tiles are FP64 only");
+  static_assert(KS == 16 || (KS == 32 && MODE == GEMM_FP64), "FP32 sums cover 16-deep slices");
+  constexpr int EU = TS * KS / 256;   // elements of each slice per thread
+  constexpr int NTL = TS / 32;  // 16 x 16 tiles per wave and dimension
   const DevCtx& c = *cp;
   const int shot = (a.shot >= 0) ? a.shot : (int)blockIdx.z, z = blockIdx.y;
   if (!gate_open(shot_dims(c, shot), a.gate)) return;
   GemmDesc d;
   if (!plan_gemm(c, a, shot, z, blockIdx.z, d)) return;
   if (z == 0 && blockIdx.x == 0 && threadIdx.x == 0 && d.nbatch > (int)gridDim.y) raise_err(c, MPSW_DEV_ERR_GRID);
-  const int tn = (d.N + 63) >> 6, tm = (d.M + 63) >> 6;
+  const int tn = (d.N + TS - 1) / TS, tm = (d.M + TS - 1) / TS;
   if (blockIdx.x == 0 && threadIdx.x == 0 && (int64_t)tm * tn > (int64_t)gridDim.x) raise_err(c, MPSW_DEV_ERR_GRID);
   if (blockIdx.x == 0 && threadIdx.x == 0 && !d.copy) count_flops(c, shot, MPSW_KC_GEMM, 2.0 * d.M * d.N * d.K);
   if ((int)blockIdx.x >= tm * tn) return;
-  const int m0 = (blockIdx.x / tn) * 64, n0 = (blockIdx.x % tn) * 64;
+  const int m0 = (blockIdx.x / tn) * TS, n0 = (blockIdx.x % tn) * TS;
   const int t = threadIdx.x;
 
   if (d.copy) {
-    for (int e = t; e < 64 * 64; e += 256) {
-      const int i = m0 + (e >> 6), j = n0 + (e & 63);
+    for (int e = t; e < TS * TS; e += 256) {
+      const int i = m0 + e / TS, j = n0 + e % TS;
       if (i < d.M && j < d.N) d.C[(int64_t)i * d.crs + j] = d.B[(int64_t)i * d.brs + (int64_t)j * d.bcs];
     }
     return;
   }
 
-  __shared__ double As[16][64 + 2];
-  __shared__ double Bs[16][64 + 2];
+  __shared__ double As[2][KS][TS + 2];   // two buffers: slice i is multiplied
+  __shared__ double Bs[2][KS][TS + 2];   // while slice i + 1 is stored
   const bool a_k_fast = (d.acs == 1);
   const bool b_n_fast = (d.bcs == 1);
-  // element u (0..3) of this thread's share of the A and B slices
+  // element u (0..EU-1) of this thread's share of the A and B slices
   auto a_idx = [&](int u, int& mm, int& kk) {
     const int e = t + 256 * u;
-    if (a_k_fast) { kk = e & 15; mm = e >> 4; } else { mm = e & 63; kk = e >> 6; }
+    if (a_k_fast) { kk = e % KS; mm = e / KS; } else { mm = e % TS; kk = e / TS; }
   };
   auto b_idx = [&](int u, int& nn, int& kk) {
     const int e = t + 256 * u;
-    if (b_n_fast) { nn = e & 63; kk = e >> 6; } else { kk = e & 15; nn = e >> 4; }
+    if (b_n_fast) { nn = e % TS; kk = e / TS; } else { kk = e % KS; nn = e / KS; }
   };
-  double ra[4], rb[4];
+  double ra[EU], rb[EU];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < EU; ++u) {
       int mm, kk, nn, kb;
       a_idx(u, mm, kk);
       b_idx(u, nn, kb);
@@ -264,37 +268,43 @@ __global__ __launch_bounds__(256) void k_gemm(const DevCtx* __restrict__ cp, OpA
     }
   };
   const int l = t & 63, w = t >> 6, li = l & 15, lq = l >> 4;
-  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-  gd4 acc64[2][2];
-  gf4 acc32[2][2];
+  const int wm = (w >> 1) * (TS / 2), wn = (w & 1) * (TS / 2);
+  gd4 acc64[NTL][NTL];
+  gf4 acc32[NTL][NTL];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NTL; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NTL; ++j) {
       acc64[i][j] = gd4{0.0, 0.0, 0.0, 0.0};
       acc32[i][j] = gf4{0.0f, 0.0f, 0.0f, 0.0f};
     }
-  fetch(0);
-  for (int k0 = 0; k0 < d.K; k0 += 16) {
+  auto stash = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < EU; ++u) {
       int mm, kk, nn, kb;
       a_idx(u, mm, kk);
       b_idx(u, nn, kb);
-      As[kk][mm] = ra[u];
-      Bs[kb][nn] = rb[u];
+      As[buf][kk][mm] = ra[u];
+      Bs[buf][kb][nn] = rb[u];
     }
-    __syncthreads();
-    if (k0 + 16 < d.K) fetch(k0 + 16);   // next slice in flight during the products
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int k0 = 0, cur = 0; k0 < d.K; k0 += KS, cur ^= 1) {
+    // one barrier per slice: the buffer written here was last read before
+    // the previous barrier
+    const bool more = (k0 + KS < d.K);
+    if (more) fetch(k0 + KS);   // next slice in flight during the products
     if (MODE == GEMM_FP64 || MODE == GEMM_FP32) {
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
+      for (int ks = 0; ks < KS / 4; ++ks) {
         const int kr = 4 * ks + lq;
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < NTL; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            const double av = As[kr][wm + 16 * i + li], bv = Bs[kr][wn + 16 * j + li];
+          for (int j = 0; j < NTL; ++j) {
+            const double av = As[cur][kr][wm + 16 * i + li], bv = Bs[cur][kr][wn + 16 * j + li];
             if (MODE == GEMM_FP64)
               acc64[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc64[i][j], 0, 0, 0);
             else
@@ -302,13 +312,13 @@ __global__ __launch_bounds__(256) void k_gemm(const DevCtx* __restrict__ cp, OpA
           }
       }
     } else {   // BF16 x 6: three BF16 parts per operand, six of the nine partial products
-      gs4 ap[3][2], bp[3][2];
+      gs4 ap[3][NTL], bp[3][NTL];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < NTL; ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          float x = (float)As[4 * lq + q][wm + 16 * i + li];
-          float y = (float)Bs[4 * lq + q][wn + 16 * i + li];
+          float x = (float)As[cur][4 * lq + q][wm + 16 * i + li];
+          float y = (float)Bs[cur][4 * lq + q][wn + 16 * i + li];
 #pragma unroll
           for (int p = 0; p < 3; ++p) {
             const short hx = bf16_rne(x), hy = bf16_rne(y);
@@ -321,9 +331,9 @@ __global__ __launch_bounds__(256) void k_gemm(const DevCtx* __restrict__ cp, OpA
       // smallest terms first: lo.hi, hi.lo (2^-18), mid.mid, mid.hi, hi.mid (2^-9), hi.hi;
       // the dropped mid.lo, lo.mid, lo.lo are below 2^-26 of the product
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < NTL; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < NTL; ++j) {
           acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ap[2][i], bp[0][j], acc32[i][j], 0, 0, 0);
           acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ap[0][i], bp[2][j], acc32[i][j], 0, 0, 0);
           acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ap[1][i], bp[1][j], acc32[i][j], 0, 0, 0);
@@ -334,20 +344,21 @@ __global__ __launch_bounds__(256) void k_gemm(const DevCtx* __restrict__ cp, OpA
     }
     if (MODE != GEMM_FP64) {   // FP32 sums of one 16-deep slice, accumulated across slices in FP64
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < NTL; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < NTL; ++j) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc32[i][j][v];
           acc32[i][j] = gf4{0.0f, 0.0f, 0.0f, 0.0f};
         }
     }
+    if (more) stash(cur ^ 1);
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NTL; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NTL; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int gi = m0 + wm + 16 * i + ((MODE == GEMM_FP64) ? (lq + 4 * v) : (4 * lq + v));
@@ -542,12 +553,13 @@ __global__ void k_zero_state(const DevCtx* __restrict__ cp, OpArgs a) {
 // ---------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------
-void launch_gemm(const DevCtx* d, const OpArgs& a, int grid_tiles, int grid_batch, int nshots, hipStream_t s) {
-  if (grid_tiles <= 0 || grid_batch <= 0) return;
-  const dim3 g(grid_tiles, grid_batch, nshots);
-  if (a.mode == GEMM_FP32) hipLaunchKernelGGL(k_gemm<GEMM_FP32>, g, dim3(256), 0, s, d, a);
-  else if (a.mode == GEMM_BF16X6) hipLaunchKernelGGL(k_gemm<GEMM_BF16X6>, g, dim3(256), 0, s, d, a);
-  else hipLaunchKernelGGL(k_gemm<GEMM_FP64>, g, dim3(256), 0, s, d, a);
+void launch_gemm(const DevCtx* d, const OpArgs& a, int64_t mcap, int64_t ncap, int grid_batch, int nshots, hipStream_t s) {
+  if (grid_batch <= 0) return;
+  const int64_t nt = std::max<int64_t>(1, ((mcap + 63) / 64) * ((ncap + 63) / 64));
+  const dim3 g((unsigned)nt, grid_batch, nshots);
+  if (a.mode == GEMM_FP32) hipLaunchKernelGGL((k_gemm<GEMM_FP32, 64, 16>), g, dim3(256), 0, s, d, a);
+  else if (a.mode == GEMM_BF16X6) hipLaunchKernelGGL((k_gemm<GEMM_BF16X6, 64, 16>), g, dim3(256), 0, s, d, a);
+  else hipLaunchKernelGGL((k_gemm<GEMM_FP64, 64, 16>), g, dim3(256), 0, s, d, a);
 }
 void launch_prepare(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s) {
   hipLaunchKernelGGL(k_prepare, dim3((nshots + 63) / 64), dim3(64), 0, s, d, a);

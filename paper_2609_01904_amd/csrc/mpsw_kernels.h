@@ -45,7 +45,8 @@ struct OpArgs {
   int gate;    // Gate: run only while the bond's sketch state allows it
 };
 
-void launch_gemm(const DevCtx* d, const OpArgs& a, int grid_tiles, int grid_batch, int nshots, hipStream_t s);
+// Contraction launch over output capacities mcap x ncap (64 x 64 tiles).
+void launch_gemm(const DevCtx* d, const OpArgs& a, int64_t mcap, int64_t ncap, int grid_batch, int nshots, hipStream_t s);
 void launch_prepare(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
 void launch_init_R(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
 void launch_pack_lap(const DevCtx* d, const OpArgs& a, int K, int nshots, int blocks, hipStream_t s);

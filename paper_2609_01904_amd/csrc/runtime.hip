@@ -449,7 +449,6 @@ int upload_ctx(Engine& e, hipStream_t s) {
   return MPSW_OK;
 }
 
-int tiles(int64_t M, int64_t N) { return std::max(1, cdiv(M, 64) * cdiv(N, 64)); }
 
 size_t g_lds_limit = 0;   // bytes of LDS a workgroup may allocate on this device
 
@@ -546,10 +545,10 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
       g.site = k;
       g.op = G_KRON_R1;
       g.aux = rd;
-      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(2 * R[k], (int64_t)D[k + 1] * p2(K - k - 1)), 1, nshots, strm); });
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, 2 * R[k], (int64_t)D[k + 1] * p2(K - k - 1), 1, nshots, strm); });
       g.op = G_KRON_R2;
       g.aux = wr;
-      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(D[k], p2(K - k - 1)), (int)(2 * R[k]), nshots, strm); });
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, D[k], p2(K - k - 1), (int)(2 * R[k]), nshots, strm); });
     }
   }
   for (int k = 0; k < K; ++k) {
@@ -562,22 +561,22 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
     if (kind == K_LAPLACE || kind == K_SUM) {
       g.op = G_L2R_EXPLICIT;
       g.aux = last ? 1 : 0;
-      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(s.rt[k], 2 * s.rin[k + 1]), 1, nshots, strm); });
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, s.rt[k], 2 * s.rin[k + 1], 1, nshots, strm); });
     } else if (kind == K_C2 && k < n) {
       g.op = G_KRON_L1;
-      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(D[k], 2 * R[k + 1]), (int)s.rt[k], nshots, strm); });
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, D[k], 2 * R[k + 1], (int)s.rt[k], nshots, strm); });
       g.op = G_KRON_L2;
-      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(R[k + 1], D[k + 1]), (int)(2 * s.rt[k]), nshots, strm); });
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, R[k + 1], D[k + 1], (int)(2 * s.rt[k]), nshots, strm); });
       if (k == n - 1) {
         g.op = G_MEET;
         g.aux = (K - n) & 1;
-        prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(2 * s.rt[k], p2(K - n)), 1, nshots, strm); });
+        prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, 2 * s.rt[k], p2(K - n), 1, nshots, strm); });
         meet = true;
       }
     } else {
       g.op = G_COPY_RX;
       g.aux = last ? 1 : 0;
-      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(s.rt[k], s.rin[k]), 1, nshots, strm); });
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, s.rt[k], s.rin[k], 1, nshots, strm); });
     }
     if (!last) {
       const int64_t mcap = 2 * s.rt[k], ncap = s.rin[k + 1];
@@ -626,7 +625,7 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
       g.site = k;
       g.slot = out_slot;
       g.op = G_US;
-      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(s.rt[k], s.rho[k]), 1, nshots, strm); });
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, s.rt[k], s.rho[k], 1, nshots, strm); });
     };
     const int64_t n2cap = 2 * s.rho[k + 1];
     if (learned) {
@@ -657,17 +656,17 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
       };
       g.op = G_RRF_Y;
       g.aux = 0;
-      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(n2cap, lcap), 1, nshots, strm); });
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, n2cap, lcap, 1, nshots, strm); });
       orth(0, n2cap);
       g.op = G_RRF_Z;
-      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(s.rt[k], lcap), 1, nshots, strm); });
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, s.rt[k], lcap, 1, nshots, strm); });
       orth(1, s.rt[k]);
       g.op = G_RRF_Y;
       g.aux = 1;
-      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(n2cap, lcap), 1, nshots, strm); });
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, n2cap, lcap, 1, nshots, strm); });
       orth(0, n2cap);
       g.op = G_RRF_Z;   // B = M Q
-      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(s.rt[k], lcap), 1, nshots, strm); });
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, s.rt[k], lcap, 1, nshots, strm); });
       launch_rrf_swap(d, r, s.rt[k] * n2cap, nshots, strm);
       svd_stage(GATE_SKETCH, lcap);
       launch_rrf_accept(d, r, s.rt[k] * n2cap, nshots, strm);
@@ -675,7 +674,7 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
       g.op = G_RRF_CORE;
       g.gate = GATE_ACCEPTED;
       g.slot = out_slot;
-      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, tiles(s.rho[k], n2cap), 1, nshots, strm); });
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, s.rho[k], n2cap, 1, nshots, strm); });
       OpArgs cr = r;
       cr.gate = GATE_ACCEPTED;
       launch_rrf_core(d, cr, s.rho[k] * n2cap, nshots, strm);
@@ -976,7 +975,7 @@ int contract_dense(mpsw_state st, int shot, int slot, std::vector<double>& out) 
     g.slot = slot;
     g.shot = shot;
     const int64_t r1 = (slot < 0) ? st->c2b[k + 1] : st->Rmax[k + 1];
-    launch_gemm(use->d, g, tiles(p2(k), 2 * r1), 1, 1, st->stream);
+    launch_gemm(use->d, g, p2(k), 2 * r1, 1, 1, st->stream);
   }
   out.resize(p2(K));
   const int64_t half = p2(K);
@@ -1647,7 +1646,7 @@ int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, doubl
     launch_applyv(e.d, v, bw, std::max<int>(1, cdiv(q, 16)), 1, s0);
     OpArgs g{};
     g.shot = -1; g.site = 1; g.slot = 0; g.op = G_US;
-    launch_gemm(e.d, g, tiles(m, q), 1, 1, s0);
+    launch_gemm(e.d, g, m, q, 1, 1, s0);
     hipDeviceSynchronize();
     std::vector<int> d1(DL::size);
     hipMemcpy(d1.data(), dims, DL::size * 4, hipMemcpyDeviceToHost);
