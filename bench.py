@@ -163,6 +163,47 @@ def copy_calibration(torch):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}))
 
 
+def precision_trajectory(mpsw, synth, torch, args):
+    """FP64, FP32 and BF16 contractions on the same shot from rest, stepped
+    together as one group; rel-L2 of FP32 and BF16 against FP64 at the given
+    steps (the FP64 fields can be saved and held against the oracle)."""
+    cfg = synth.get_config(args.workload)
+    n = cfg["n"]
+    precs = [("fp64", mpsw.MPSW_FP64), ("fp32", mpsw.MPSW_FP32), ("bf16", mpsw.MPSW_BF16)]
+    states = []
+    for _, p in precs:
+        st = mpsw.State(mpsw.make_config(n, cfg["chi"], cfg["eps"], cfg["lam"], precision=p))
+        st.set_velocity_dense(cfg["c2"], cfg["eps_c"])
+        st.set_source(0, cfg["ix"], cfg["iz"], cfg["wavelet_samples"])
+        states.append(st)
+    grp = mpsw.Group(states)
+    marks = sorted(set(int(x) for x in args.trajectory.split(",")))
+    if args.save:
+        os.makedirs(args.save, exist_ok=True)
+        np.save(os.path.join(args.save, "gpu_c2r.npy"), states[0].to_dense(0, 2))
+    rows, done, t0 = [], 0, time.perf_counter()
+    for mark in marks:
+        while done < mark:
+            k = min(50, mark - done)
+            grp.step(k)
+            torch.cuda.synchronize()
+            done += k
+            log(f"trajectory: step {done} ({time.perf_counter() - t0:.0f} s), bonds {states[0].bonds(0, 0)}")
+        u = [st.to_dense(0, 0) for st in states]
+        nb = float(np.linalg.norm(u[0]))
+        row = {"step": mark, "bonds_fp64": states[0].bonds(0, 0)}
+        for (name, _), v in zip(precs[1:], u[1:]):
+            row[f"rel_l2_{name}_vs_fp64"] = float(np.linalg.norm(v - u[0])) / nb if nb > 0 else 0.0
+        rows.append(row)
+        if args.save:
+            np.save(os.path.join(args.save, f"gpu_fp64_u{mark}.npy"), u[0])
+    print(json.dumps({"workload": args.workload, "trajectory": rows,
+                      "seconds": time.perf_counter() - t0}), flush=True)
+    grp.close()
+    for st in states:
+        st.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +226,11 @@ def main():
                     help="kernel class for the roofline (-1: the one with most time)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--trajectory", default=None, metavar="STEPS",
+                    help="precision run instead of the throughput measurement: one shot of the "
+                         "workload from rest in FP64, FP32 and BF16 contractions (one group), the "
+                         "relative L2 of FP32 and BF16 against FP64 at these comma-separated steps")
+    ap.add_argument("--save", default=None, help="directory for the trajectory's FP64 fields (.npy)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (byte-counter calibration)")
     args = ap.parse_args()
@@ -206,6 +252,10 @@ def main():
 
     from paper_2609_01904_amd import mpsw
     import synth
+
+    if args.trajectory:
+        precision_trajectory(mpsw, synth, torch, args)
+        return
 
     t_setup = time.perf_counter()
     model = None

@@ -62,7 +62,12 @@ struct ShotDimsLayout {
   static constexpr int rrf_l = rrf + 1;       // sketch width l = predicted rank + oversampling
   static constexpr int rrf_tries = rrf_l + 1; // bonds sketched since the fields were set
   static constexpr int fallbacks = rrf_tries + 1;  // sketches rejected (exact SVD taken)
-  static constexpr int size = fallbacks + 1;
+  // per rounding and bond: after a rejected sketch the bond takes the exact
+  // SVD until step rrf_skip, and the wait rrf_back doubles (1, 2, ..., 64)
+  // with every further rejection; an accepted sketch resets it
+  static constexpr int rrf_skip = fallbacks + 1;            // [3][MAXK]
+  static constexpr int rrf_back = rrf_skip + 3 * MPSW_MAXK; // [3][MAXK]
+  static constexpr int size = rrf_back + 3 * MPSW_MAXK;
 };
 
 // Per-shot double block layout (offsets in doubles, separate small array).

@@ -81,7 +81,9 @@ __global__ __launch_bounds__(MLP_NH) void k_rrf_plan(const DevCtx* __restrict__ 
     // a sketch pays off only well below the full width and below the cap (a
     // capped bond's flat tail rarely lets the residual test certify the
     // capped error), and needs a sigma log
-    const int ok = (lg[0] > 0.0) && (rhat < chi) && (l <= MPSW_RRF_MAXL) && (4 * l <= 3 * cc) && m >= l && nn >= l;
+    const bool waiting = (a.aux >= 0 && a.aux < 3) && dm[DL::step] < dm[DL::rrf_skip + a.aux * MPSW_MAXK + k];
+    const int ok = (lg[0] > 0.0) && (rhat < chi) && (l <= MPSW_RRF_MAXL) && (4 * l <= 3 * cc) && m >= l && nn >= l &&
+                   !waiting;
     dm[DL::rrf] = ok ? 1 : 0;
     dm[DL::rrf_l] = ok ? l : 0;
     dm[DL::svd_n] = 0;
@@ -202,6 +204,16 @@ __global__ void k_rrf_settle(const DevCtx* __restrict__ cp, OpArgs a) {
   const bool accept = capped ? (res2 <= 0.21 * tail) : (r < l && res2 <= (eps * s1) * (eps * s1));
   dm[DL::rrf] = accept ? 2 : 0;
   if (!accept) dm[DL::svd_n] = 0;
+  if (a.aux >= 0 && a.aux < 3) {
+    const int jk = a.aux * MPSW_MAXK + k;
+    if (accept) {
+      dm[DL::rrf_back + jk] = 0;
+    } else {
+      const int b = min(64, max(1, 2 * dm[DL::rrf_back + jk]));
+      dm[DL::rrf_back + jk] = b;
+      dm[DL::rrf_skip + jk] = dm[DL::step] + 1 + b;
+    }
+  }
 }
 
 // core slot <- Tc (r x 2 rho), after the sketch was accepted.

@@ -1116,8 +1116,9 @@ int mpsw_set_fields(mpsw_state st, int shot, const double* u_prev, const double*
     int rc = dense_to_mps(st, fields[t], st->cfg[shot].eps, st->cfg[shot].chi_max, shot, slots[t], false);
     if (rc != MPSW_OK) return rc;
   }
-  const int zero = 0;   // this shot's source clock restarts
+  const int zero = 0;   // this shot's source clock restarts, and so do the sketch back-offs
   HIP_TRY(hipMemcpy(st->dims + (int64_t)shot * DL::size + DL::step, &zero, sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(st->dims + (int64_t)shot * DL::size + DL::rrf_skip, 0, sizeof(int) * 6 * MPSW_MAXK));
   st->step = 0;
   return MPSW_OK;
 }

@@ -71,8 +71,11 @@ def test_learned_rank_within_truncation_error_of_exact(mpsw, frac):
         assert rel(b, a) < 1e-5
     st = ln.stats(0)
     if frac < 0.05:
-        assert st["sketches"] > 0   # width 1 + 8 is below most ranks: almost every sketch is rejected
-        assert st["fallbacks"] >= 0.25 * st["sketches"]
+        # width 1 + 8 is below the ranks once the field has spread: sketches
+        # are rejected and the exact SVD takes over (a rejected bond then
+        # waits 1, 2, 4, ... steps before it is sketched again)
+        assert st["sketches"] > 0
+        assert st["fallbacks"] >= 10
     # the exact run itself against the FP64 oracle
     ds = S.DenseStepper(n, cfg["lam"], eps, chi, ex.to_dense(0, 2), src=((1 << n) // 2, 1),
                         wavelet=synth.ricker(steps, cfg["dt"], 40.0))
