@@ -163,6 +163,73 @@ def copy_calibration(torch):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}))
 
 
+def mixed_batch(mpsw, synth, torch, args):
+    """The batched-shots workload: 64 shots on grids n in {8, 9, 10} with chi
+    caps in {32, 64, 128} (seeded), one state per grid size holding its shots,
+    all states stepped by one group graph.  The shots start from rest; the
+    first `warmup` steps are untimed, then each state's launch shapes are
+    autotuned, then `steps` steps are timed."""
+    shots = synth.batch_shots(64, seed=1, steps=args.warmup + args.steps)
+    prec = {"fp64": mpsw.MPSW_FP64, "fp32": mpsw.MPSW_FP32, "bf16": mpsw.MPSW_BF16}[args.precision]
+    states, counts = [], {}
+    t0 = time.perf_counter()
+    for n in sorted(set(sh["n"] for sh in shots)):
+        mine = [sh for sh in shots if sh["n"] == n]
+        counts[n] = len(mine)
+        cfg = synth.get_config("C3", n=n)
+        lam = mine[0]["dt"] / mine[0]["dh"]
+        st = mpsw.State([mpsw.make_config(n, sh["chi"], sh["eps"], lam, precision=prec) for sh in mine])
+        st.set_velocity_dense(cfg["c2"], cfg["eps_c"])
+        for i, sh in enumerate(mine):
+            st.set_source(i, sh["ix"], sh["iz"], sh["wavelet_samples"])
+        states.append(st)
+    grp = mpsw.Group(states)
+    done = 0
+    while done < args.warmup:
+        k = min(100, args.warmup - done)
+        grp.step(k)
+        torch.cuda.synchronize()
+        done += k
+        log(f"mixed batch: warm-up step {done}")
+    tuned = {}
+    if not args.no_tune:
+        for st in states:
+            tuned[st.K // 2] = st.autotune(2)
+        log(f"autotuned (QR workgroups per shot, Jacobi block) per grid n: {tuned}")
+    grp.close()
+    grp = mpsw.Group(states)   # captured with the tuned shapes
+    grp.step(3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    left = args.steps - 3
+    while left > 0:
+        k = min(99, left)
+        grp.step(k)
+        torch.cuda.synchronize()
+        left -= k
+        log(f"mixed batch: {args.steps - left} of {args.steps} timed steps ({time.perf_counter() - t1:.0f} s)")
+    el = time.perf_counter() - t1
+    timed = args.steps - 3
+    nshot = len(shots)
+    out = {
+        "metric": "aggregate shot-steps/s, 64 shots on mixed grids in one graph",
+        "value": nshot * timed / el, "unit": "shot-steps/s", "n_gpus": 1, "steps": timed,
+        "warmup": args.warmup + 3, "ms_per_step": el * 1e3 / timed, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[args.precision], "data": "synthetic",
+        "config": {"workload": "C4: 64 Ricker shots (f0 ~ U[8, 25] Hz, x ~ U, depth 10 m), n ~ U{8, 9, 10}, "
+                               "chi ~ U{32, 64, 128}, eps=1e-06, layered-fault c^2 per grid",
+                   "shots_per_grid": {str(k): v for k, v in counts.items()},
+                   "tuned": {str(k): list(v) for k, v in tuned.items()}, "graph": True},
+        "max_bonds": {str(st.K // 2): max(max(st.bonds(b, 0)) for b in range(st.nshots)) for st in states},
+        "setup_and_warmup_s": t1 - t0,
+    }
+    print(json.dumps(out), flush=True)
+    grp.close()
+    for st in states:
+        st.close()
+
+
 def precision_trajectory(mpsw, synth, torch, args):
     """FP64, FP32 and BF16 contractions on the same shot from rest, stepped
     together as one group; rel-L2 of FP32 and BF16 against FP64 at the given
@@ -255,6 +322,9 @@ def main():
 
     if args.trajectory:
         precision_trajectory(mpsw, synth, torch, args)
+        return
+    if args.workload == "C4":
+        mixed_batch(mpsw, synth, torch, args)
         return
 
     t_setup = time.perf_counter()
