@@ -147,9 +147,19 @@ def cpu_baseline(synth, workload, fields, seconds):
         el = time.perf_counter() - t0
         if el >= seconds or steps >= 50:
             break
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": steps / el, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{steps} steps of the same workload (shot 0, same starting wavefield) with the "
-                      f"FP64 dense-detour oracle stepper on the host, {el:.1f} s"}
+                      f"FP64 dense-detour oracle stepper on the host, {el:.1f} s "
+                      f"({model}, {os.cpu_count()} logical CPUs visible)"}
 
 
 def copy_calibration(torch):

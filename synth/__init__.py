@@ -12,11 +12,11 @@ depth / position as described there).
 """
 from .velocity import layered_fault_velocity, constant_velocity
 from .wavelet import ricker, impulse
-from .fields import plane_wave_fields, random_fields, random_mps_cores, wavefront_fields
+from .fields import plane_wave_fields, sine_mode_fields, random_fields, random_mps_cores, wavefront_fields
 from .configs import CONFIGS, get_config, batch_shots
 
 __all__ = [
     "layered_fault_velocity", "constant_velocity", "ricker", "impulse",
-    "plane_wave_fields", "random_fields", "random_mps_cores", "wavefront_fields", "CONFIGS", "batch_shots",
+    "plane_wave_fields", "sine_mode_fields", "random_fields", "random_mps_cores", "wavefront_fields", "CONFIGS", "batch_shots",
     "get_config",
 ]

@@ -35,6 +35,28 @@ def plane_wave_fields(n, mx, mz, courant, phase=0.0):
     return np.cos(theta + wdt), np.cos(theta)
 
 
+def sine_mode_omega_dt(n, mx, mz, courant):
+    """omega*dt of a standing sine mode on the 2^n grid with zero-fill (open)
+    shifts: sin(pi mx (x+1)/(N+1)) sin(pi mz (z+1)/(N+1)) is an eigenvector of
+    the 5-point Laplacian with that boundary, eigenvalue
+    -4 (sin^2(pi mx / (2(N+1))) + sin^2(pi mz / (2(N+1)))), so
+    sin^2(omega dt / 2) = courant^2 (sin^2(pi mx / (2(N+1))) + sin^2(pi mz / (2(N+1))))."""
+    N = 1 << n
+    s = courant ** 2 * (np.sin(np.pi * mx / (2 * (N + 1))) ** 2 + np.sin(np.pi * mz / (2 * (N + 1))) ** 2)
+    return 2.0 * np.arcsin(np.sqrt(s))
+
+
+def sine_mode_fields(n, mx, mz, courant, phase=0.0):
+    """(u^{-1}, u^0) such that u^k = cos(phase - k omega dt) v for all k >= -1,
+    v the standing sine mode (mx, mz) of the open boundary."""
+    N = 1 << n
+    wdt = sine_mode_omega_dt(n, mx, mz, courant)
+    x = np.arange(N)[:, None]
+    z = np.arange(N)[None, :]
+    v = np.sin(np.pi * mx * (x + 1) / (N + 1)) * np.sin(np.pi * mz * (z + 1) / (N + 1))
+    return np.cos(phase + wdt) * v, np.cos(phase) * v
+
+
 def random_fields(n, seed=0, smooth=True):
     """Two seeded smooth random fields (u^{-1}, u^0)."""
     rng = np.random.default_rng(seed)

@@ -187,6 +187,27 @@ def test_plane_wave_production_size(mpsw):
     st.close()
 
 
+def test_open_boundary_sine_mode_production_size(mpsw):
+    """n = 10, zero-fill shifts (eq. 11 as printed): a standing sine mode stays
+    rank 2 and follows its closed form."""
+    n, mx, mz, courant = 10, 17, 5, 0.5
+    N = 1 << n
+    st = mpsw.State(mpsw.make_config(n, 8, 1e-10, courant, boundary=mpsw.MPSW_OPEN))
+    st.set_velocity_dense(np.ones((N, N)), 1e-12)
+    up, u = synth.sine_mode_fields(n, mx, mz, courant, phase=0.2)
+    st.set_fields(0, up, u)
+    wdt = synth.fields.sine_mode_omega_dt(n, mx, mz, courant)
+    steps = 20
+    st.step(steps)
+    _, v = synth.sine_mode_fields(n, mx, mz, courant)
+    exact = np.cos(0.2 - steps * wdt) * v
+    g = st.to_dense(0, 0)
+    _say("open sine mode n=10", np.max(np.abs(g - exact)), max(st.bonds(0, 0)))
+    assert np.max(np.abs(g - exact)) < 1e-10
+    assert max(st.bonds(0, 0)) == 2
+    st.close()
+
+
 def test_batch_equals_single(mpsw):
     n, eps, lam = 5, 1e-7, 0.5
     N = 1 << n

@@ -49,6 +49,25 @@ def test_plane_wave_dispersion(n, mx, mz):
     assert np.max(np.abs(u_end - exact)) < 1e-10
 
 
+@pytest.mark.parametrize("n,mx,mz", [(4, 1, 1), (6, 3, 5), (8, 7, 2), (10, 13, 29)])
+def test_sine_mode_dispersion_open_boundary(n, mx, mz):
+    """With zero-fill shifts (eq. 11 as printed), standing sine modes are exact
+    eigenvectors of the 5-point Laplacian, so cos(phi - k w dt) v is exact."""
+    courant = 0.5
+    N = 1 << n
+    c2 = np.full((N, N), 1.0)
+    up, u = synth.sine_mode_fields(n, mx, mz, courant, phase=0.3)
+    wdt = synth.fields.sine_mode_omega_dt(n, mx, mz, courant)
+    steps = 200
+    _, u_end, _ = F.fdtd_run(up, u, c2, courant, steps, boundary="open")
+    _, v = synth.sine_mode_fields(n, mx, mz, courant, phase=0.0)
+    exact = np.cos(0.3 - steps * wdt) * v
+    assert np.max(np.abs(u_end - exact)) < 1e-10
+    # and it is not a solution of the periodic scheme (the boundary matters)
+    _, u_per, _ = F.fdtd_run(up, u, c2, courant, steps, boundary="periodic")
+    assert np.max(np.abs(u_per - exact)) > 1e-3
+
+
 @pytest.mark.parametrize("boundary", ["periodic", "open"])
 def test_energy_conserved(boundary):
     n = 5

@@ -73,6 +73,28 @@ def test_plane_wave_stays_rank_two(n, mx, mz):
     assert max(ds.ranks[-1][2]) == 2
 
 
+@pytest.mark.parametrize("n,mx,mz", [(6, 2, 3), (8, 5, 1)])
+def test_open_boundary_sine_mode_stays_rank_two(n, mx, mz):
+    """Zero-fill shifts: a standing sine mode has quantics rank 2 (sin(a x + b)
+    over the bits of x) and stays one, following its closed form."""
+    courant = 0.5
+    N = 1 << n
+    c2 = np.ones((N, N))
+    up, u = synth.sine_mode_fields(n, mx, mz, courant, phase=0.3)
+    wdt = synth.fields.sine_mode_omega_dt(n, mx, mz, courant)
+    ds = S.DenseStepper(n, courant, 1e-10, 16, c2, boundary="open")
+    ms = S.MPSStepper(n, courant, 1e-10, 16, S.c2_mps(c2, n, 1e-12), boundary="open")
+    _, v = synth.sine_mode_fields(n, mx, mz, courant)
+    steps = 30
+    for stepper in (ds, ms):
+        stepper.set_fields(up, u)
+        for _ in range(steps):
+            stepper.step()
+        assert np.max(np.abs(stepper.dense() - np.cos(0.3 - steps * wdt) * v)) < 1e-10
+    assert max(ds.ranks[-1][2]) == 2
+    assert max(c.shape[2] for c in ms.psi) == 2
+
+
 def test_energy_conserved_untruncated_mps():
     n = 3
     N = 1 << n
