@@ -446,10 +446,16 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
       }
     }
     __syncthreads();
+    // a NaN norm sorts last (key -1): the ranks stay a permutation, so no
+    // column index is left unset whatever the data
+    auto key = [](double x) { return (x == x) ? x : -1.0; };
     for (int j = t; j < n; j += QNT) {
-      const double sj = cnorm[j];
+      const double sj = key(cnorm[j]);
       int rank = 0;
-      for (int i = 0; i < n; ++i) rank += (cnorm[i] > sj) || (cnorm[i] == sj && i < j);
+      for (int i = 0; i < n; ++i) {
+        const double si = key(cnorm[i]);
+        rank += (si > sj) || (si == sj && i < j);
+      }
       perm[rank] = j;
     }
     __syncthreads();
@@ -991,11 +997,14 @@ __global__ __launch_bounds__(256) void k_jacfin(const DevCtx* __restrict__ cp, O
     if (lane == 0) sig[j] = sqrt(s);
   }
   __syncthreads();
+  // a NaN sorts last (key -1): the order stays a permutation, and the
+  // non-finite value is reported below
+  auto key = [](double x) { return (x == x) ? x : -1.0; };
   for (int j = t; j < cc; j += blockDim.x) {
-    const double sj = sig[j];
+    const double sj = key(sig[j]);
     int r = 0;
     for (int i = 0; i < cc; ++i) {
-      const double si = sig[i];
+      const double si = key(sig[i]);
       r += (si > sj) || (si == sj && i < j);
     }
     order[r] = j;
