@@ -60,10 +60,10 @@ def source_hash(kclass):
     return h.hexdigest()[:16]
 
 
-def read_traffic(kclass, workload, batch):
+def read_traffic(kclass, workload, batch, precision):
     """HBM bytes per launch from a committed counter summary, or None when the
     summary is missing or was taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{KERNEL_NAMES[kclass]}_{workload}_b{batch}.txt")
+    path = os.path.join(ROOT, "profiles", f"traffic_{KERNEL_NAMES[kclass]}_{workload}_b{batch}_{precision}.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -389,7 +389,7 @@ def main():
     avg_ms = prof["total_ms"] / max(prof["launches"], 1)
     flops_per_launch = prof["alg_flops"] / max(prof["launches"], 1)
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    traffic = read_traffic(kclass, args.workload, args.batch)
+    traffic = read_traffic(kclass, args.workload, args.batch, args.precision)
     # contractions run on the matrix cores (dense peak of their operand type);
     # the factorisation kernels on the FP64 vector ALUs
     if KERNEL_NAMES[kclass] == "k_gemm":
