@@ -216,7 +216,7 @@ __device__ __forceinline__ short bf16_rne(float x) {   // round to nearest even 
 __device__ __forceinline__ float bf16_val(short h) { return __uint_as_float(((unsigned)(unsigned short)h) << 16); }
 
 template <int MODE, int TS, int KS>
-__global__ __launch_bounds__(256) void k_gemm(const DevCtx* __restrict__ cp, OpArgs a) {
+__global__ __launch_bounds__(256, (MODE == GEMM_FP64) ? 4 : 2) void k_gemm(const DevCtx* __restrict__ cp, OpArgs a) {
   static_assert(TS == 64 || (TS == 128 && MODE == GEMM_FP64), "128-wide tiles are FP64 only");
   static_assert(KS == 16 || (KS == 32 && MODE == GEMM_FP64), "FP32 sums cover 16-deep slices");
   constexpr int EU = TS * KS / 256;   // elements of each slice per thread
