@@ -22,6 +22,7 @@ namespace mpsw {
 #define MPSW_PERM_MAX 1024
 #define QNT 1024   // threads of the QR-family kernels
 #define MPSW_APPLY_LDS (16 * 256 + 256)   // doubles of LDS for apply_reflector
+#define APNT 512   // threads of k_applyq, k_applyv, k_formq (8 waves, no register spills)
 
 __device__ __forceinline__ int ld_acquire(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -82,7 +83,7 @@ __global__ void k_sync_reset(const DevCtx* __restrict__ cp) {
 // ---------------------------------------------------------------------------
 typedef double mpsw_d4 __attribute__((ext_vector_type(4)));
 
-template <int BW>
+template <int BW, int NWV = 16>
 __device__ void apply_reflector(const double* __restrict__ V, int64_t ldv, double* C, int64_t crs, int64_t ccs,
                                 int mj, int bw, int bwc, const double* __restrict__ T, bool trans, double* wsp) {
   static_assert(BW <= 16, "panel wider than one matrix-core tile");
@@ -97,11 +98,11 @@ __device__ void apply_reflector(const double* __restrict__ V, int64_t ldv, doubl
   constexpr int UN = 4;
   const int nsteps = (mj + 3) >> 2;
   mpsw_d4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int s0 = wv; s0 < nsteps; s0 += 16 * UN) {
+  for (int s0 = wv; s0 < nsteps; s0 += NWV * UN) {
     double av[UN], bv[UN];
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
-      const int r = 4 * (s0 + 16 * u) + lk;
+      const int r = 4 * (s0 + NWV * u) + lk;
       av[u] = vfull(r, li);
       bv[u] = (r < mj && li < bwc) ? C[(int64_t)r * crs + (int64_t)li * ccs] : 0.0;
     }
@@ -111,10 +112,10 @@ __device__ void apply_reflector(const double* __restrict__ V, int64_t ldv, doubl
 #pragma unroll
   for (int v = 0; v < 4; ++v) wsp[wv * 256 + (lk + 4 * v) * 16 + li] = acc[v];
   __syncthreads();
-  double* W2 = wsp + 16 * 256;
+  double* W2 = wsp + NWV * 256;
   if (t < 256) {
     double s = 0.0;
-    for (int w = 0; w < 16; ++w) s += wsp[w * 256 + t];
+    for (int w = 0; w < NWV; ++w) s += wsp[w * 256 + t];
     wsp[t] = s;   // W[p][q], p = t / 16, q = t % 16
   }
   __syncthreads();
@@ -136,11 +137,11 @@ __device__ void apply_reflector(const double* __restrict__ V, int64_t ldv, doubl
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) bk[kk] = W2[(4 * kk + lk) * 16 + li];
   const int ntile = (mj + 15) >> 4;
-  for (int tb = wv; tb < ntile; tb += 32) {
+  for (int tb = wv; tb < ntile; tb += 2 * NWV) {
     double av[2][4], cv[2][4];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int r0 = 16 * (tb + 16 * h);
+      const int r0 = 16 * (tb + NWV * h);
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) av[h][kk] = (4 * kk < bw) ? vfull(r0 + li, 4 * kk + lk) : 0.0;
 #pragma unroll
@@ -154,7 +155,7 @@ __device__ void apply_reflector(const double* __restrict__ V, int64_t ldv, doubl
       mpsw_d4 d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) d = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h][kk], bk[kk], d, 0, 0, 0);
-      const int r0 = 16 * (tb + 16 * h);
+      const int r0 = 16 * (tb + NWV * h);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = r0 + lk + 4 * v;
@@ -540,7 +541,7 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
 // per workgroup, reflectors applied last to first.
 // ---------------------------------------------------------------------------
 template <int BW>
-__global__ __launch_bounds__(1024) void k_applyq(const DevCtx* __restrict__ cp, OpArgs a) {
+__global__ __launch_bounds__(APNT) void k_applyq(const DevCtx* __restrict__ cp, OpArgs a) {
   const DevCtx& c = *cp;
   const int shot = blockIdx.z, w = blockIdx.x;
   const int k = a.site;
@@ -561,7 +562,7 @@ __global__ __launch_bounds__(1024) void k_applyq(const DevCtx* __restrict__ cp, 
   if (col0 >= r) return;
   const int cw = min(CW, r - col0);
   if (dm[DL::qid + k - 1]) {  // identity: rt_k = 2 rt_{k-1}, same memory shape
-    bulk_copy<8>(m * cw, t, QNT, [&](int e) { return US[(e / cw) * r + col0 + (int)(e % cw)]; },
+    bulk_copy<8>(m * cw, t, APNT, [&](int e) { return US[(e / cw) * r + col0 + (int)(e % cw)]; },
                  [&](int e, double v) { M[(e / cw) * r + col0 + (int)(e % cw)] = v; });
     return;
   }
@@ -575,13 +576,13 @@ __global__ __launch_bounds__(1024) void k_applyq(const DevCtx* __restrict__ cp, 
   extern __shared__ double wsp[];
   if (w == 0 && t == 0)   // n reflectors of length <= m applied to r columns
     count_flops(c, shot, MPSW_KC_APPLYQ, 4.0 * m * (double)n * r - 2.0 * (double)n * n * r);
-  bulk_copy<8>(m * cw, t, QNT,
+  bulk_copy<8>(m * cw, t, APNT,
                [&](int e) { return (e / cw < n) ? US[(e / cw) * r + col0 + (int)(e % cw)] : 0.0; },
                [&](int e, double v) { M[(e / cw) * r + col0 + (int)(e % cw)] = v; });
   __syncthreads();
   for (int j = nbk - 1; j >= 0; --j) {
     const int r0 = j * BW, c0 = j * BW, bw = min(BW, n - c0);
-    apply_reflector<BW>(S + r0 + (int64_t)m * c0, m, M + (int64_t)r0 * r + col0, r, 1, m - r0, bw, cw,
+    apply_reflector<BW, APNT / 64>(S + r0 + (int64_t)m * c0, m, M + (int64_t)r0 * r + col0, r, 1, m - r0, bw, cw,
                         T + (int64_t)j * BW * BW, false, wsp);
   }
 }
@@ -592,7 +593,7 @@ __global__ __launch_bounds__(1024) void k_applyq(const DevCtx* __restrict__ cp, 
 // Column chunks of BW per workgroup.
 // ---------------------------------------------------------------------------
 template <int BW>
-__global__ __launch_bounds__(1024) void k_applyv(const DevCtx* __restrict__ cp, OpArgs a) {
+__global__ __launch_bounds__(APNT) void k_applyv(const DevCtx* __restrict__ cp, OpArgs a) {
   const DevCtx& c = *cp;
   const int shot = blockIdx.z, w = blockIdx.x;
   const int k = a.site;
@@ -620,7 +621,7 @@ __global__ __launch_bounds__(1024) void k_applyv(const DevCtx* __restrict__ cp, 
   extern __shared__ double wsp[];
   if (w == 0 && t == 0)   // m reflectors of length <= n applied to r columns
     count_flops(c, shot, MPSW_KC_APPLYV, 4.0 * n * (double)m * r - 2.0 * (double)m * m * r);
-  bulk_copy<8>(n * cw, t, QNT,
+  bulk_copy<8>(n * cw, t, APNT,
                [&](int e) {
                  const int row = (int)(e / cw), qq = (int)(e % cw);
                  return (row < m) ? Vp[(int64_t)(col0 + qq) * m + row] : 0.0;
@@ -629,10 +630,10 @@ __global__ __launch_bounds__(1024) void k_applyv(const DevCtx* __restrict__ cp, 
   __syncthreads();
   for (int j = nbk - 1; j >= 0; --j) {
     const int r0 = j * BW, c0 = j * BW, bw = min(BW, m - c0);
-    apply_reflector<BW>(S + r0 + (int64_t)n * c0, n, Y + (int64_t)r0 * r + col0, r, 1, n - r0, bw, cw,
+    apply_reflector<BW, APNT / 64>(S + r0 + (int64_t)n * c0, n, Y + (int64_t)r0 * r + col0, r, 1, n - r0, bw, cw,
                         T + (int64_t)j * BW * BW, false, wsp);
   }
-  bulk_copy<8>(n * cw, t, QNT, [&](int e) { return Y[(e % n) * r + col0 + (int)(e / n)]; },
+  bulk_copy<8>(n * cw, t, APNT, [&](int e) { return Y[(e % n) * r + col0 + (int)(e / n)]; },
                [&](int e, double v) { core[(int64_t)(col0 + (int)(e / n)) * n + (e % n)] = v; });
 }
 
@@ -643,7 +644,7 @@ __global__ __launch_bounds__(1024) void k_applyv(const DevCtx* __restrict__ cp, 
 // workgroup.
 // ---------------------------------------------------------------------------
 template <int BW>
-__global__ __launch_bounds__(1024) void k_formq(const DevCtx* __restrict__ cp, OpArgs a) {
+__global__ __launch_bounds__(APNT) void k_formq(const DevCtx* __restrict__ cp, OpArgs a) {
   const DevCtx& c = *cp;
   const int shot = blockIdx.z, w = blockIdx.x;
   const int k = a.site;
@@ -666,12 +667,12 @@ __global__ __launch_bounds__(1024) void k_formq(const DevCtx* __restrict__ cp, O
     return;
   }
   extern __shared__ double wsp[];
-  bulk_copy<8>(m * cw, t, QNT, [&](int e) { return ((e / cw) == col0 + (e % cw)) ? 1.0 : 0.0; },
+  bulk_copy<8>(m * cw, t, APNT, [&](int e) { return ((e / cw) == col0 + (e % cw)) ? 1.0 : 0.0; },
                [&](int e, double v) { Q[(int64_t)(e / cw) * l + col0 + (e % cw)] = v; });
   __syncthreads();
   for (int j = nbk - 1; j >= 0; --j) {
     const int r0 = j * BW, c0 = j * BW, bw = min(BW, l - c0);
-    apply_reflector<BW>(S + r0 + (int64_t)m * c0, m, Q + (int64_t)r0 * l + col0, l, 1, m - r0, bw, cw,
+    apply_reflector<BW, APNT / 64>(S + r0 + (int64_t)m * c0, m, Q + (int64_t)r0 * l + col0, l, 1, m - r0, bw, cw,
                         T + (int64_t)j * BW * BW, false, wsp);
   }
 }
@@ -1088,31 +1089,31 @@ void launch_qrf(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, s
 void launch_applyq(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, hipStream_t s) {
   const size_t lds = (size_t)MPSW_APPLY_LDS * sizeof(double);
   if (bw == 16)
-    hipLaunchKernelGGL(k_applyq<16>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
+    hipLaunchKernelGGL(k_applyq<16>, dim3(nwg, 1, nshots), dim3(APNT), lds, s, d, a);
   else if (bw == 8)
-    hipLaunchKernelGGL(k_applyq<8>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
+    hipLaunchKernelGGL(k_applyq<8>, dim3(nwg, 1, nshots), dim3(APNT), lds, s, d, a);
   else
-    hipLaunchKernelGGL(k_applyq<4>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
+    hipLaunchKernelGGL(k_applyq<4>, dim3(nwg, 1, nshots), dim3(APNT), lds, s, d, a);
 }
 
 void launch_applyv(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, hipStream_t s) {
   const size_t lds = (size_t)MPSW_APPLY_LDS * sizeof(double);
   if (bw == 16)
-    hipLaunchKernelGGL(k_applyv<16>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
+    hipLaunchKernelGGL(k_applyv<16>, dim3(nwg, 1, nshots), dim3(APNT), lds, s, d, a);
   else if (bw == 8)
-    hipLaunchKernelGGL(k_applyv<8>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
+    hipLaunchKernelGGL(k_applyv<8>, dim3(nwg, 1, nshots), dim3(APNT), lds, s, d, a);
   else
-    hipLaunchKernelGGL(k_applyv<4>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
+    hipLaunchKernelGGL(k_applyv<4>, dim3(nwg, 1, nshots), dim3(APNT), lds, s, d, a);
 }
 
 void launch_formq(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, hipStream_t s) {
   const size_t lds = (size_t)MPSW_APPLY_LDS * sizeof(double);
   if (bw == 16)
-    hipLaunchKernelGGL(k_formq<16>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
+    hipLaunchKernelGGL(k_formq<16>, dim3(nwg, 1, nshots), dim3(APNT), lds, s, d, a);
   else if (bw == 8)
-    hipLaunchKernelGGL(k_formq<8>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
+    hipLaunchKernelGGL(k_formq<8>, dim3(nwg, 1, nshots), dim3(APNT), lds, s, d, a);
   else
-    hipLaunchKernelGGL(k_formq<4>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
+    hipLaunchKernelGGL(k_formq<4>, dim3(nwg, 1, nshots), dim3(APNT), lds, s, d, a);
 }
 
 // Rows a Jacobi column occupies in LDS for a column length of at most lcap.
