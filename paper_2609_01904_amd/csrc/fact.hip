@@ -734,20 +734,24 @@ __device__ __forceinline__ double rotate_reg(double (&x)[EPL], double* aq, int g
   double y[EPL];
 #pragma unroll
   for (int e = 0; e < EPL; ++e) y[e] = aq[gl + 16 * e];
-  // two accumulators per sum halve the dependent chains
-  double al0 = 0.0, be0 = 0.0, ga0 = 0.0, al1 = 0.0, be1 = 0.0, ga1 = 0.0;
+  // NA accumulators per sum shorten the dependent chains
+  constexpr int NA = (EPL < 4) ? EPL : 4;
+  double al_[NA], be_[NA], ga_[NA];
 #pragma unroll
-  for (int e = 0; e < EPL; e += 2) {
-    al0 = fma(x[e], x[e], al0);
-    be0 = fma(y[e], y[e], be0);
-    ga0 = fma(x[e], y[e], ga0);
-    if (e + 1 < EPL) {
-      al1 = fma(x[e + 1], x[e + 1], al1);
-      be1 = fma(y[e + 1], y[e + 1], be1);
-      ga1 = fma(x[e + 1], y[e + 1], ga1);
-    }
+  for (int i = 0; i < NA; ++i) al_[i] = be_[i] = ga_[i] = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    al_[e % NA] = fma(x[e], x[e], al_[e % NA]);
+    be_[e % NA] = fma(y[e], y[e], be_[e % NA]);
+    ga_[e % NA] = fma(x[e], y[e], ga_[e % NA]);
   }
-  const double al = row_sum16(al0 + al1), be = row_sum16(be0 + be1), ga = row_sum16(ga0 + ga1);
+#pragma unroll
+  for (int i = 1; i < NA; ++i) {
+    al_[0] += al_[i];
+    be_[0] += be_[i];
+    ga_[0] += ga_[i];
+  }
+  const double al = row_sum16(al_[0]), be = row_sum16(be_[0]), ga = row_sum16(ga_[0]);
   double rel2, cs, sn;
   if (!jacobi_angle(al, be, ga, tol2, floor2, rel2, cs, sn)) return rel2;
 #pragma unroll
