@@ -874,9 +874,21 @@ __global__ __launch_bounds__(JNT) void k_jac(const DevCtx* __restrict__ cp, OpAr
         const int ncol = np_ + nq_;
         if (t == 0) { nrot = 0; maxrel = 0u; }
         auto gcol = [&](int jj) { return (jj < np_) ? bp * b + jj : bq * b + (jj - np_); };
-        bulk_copy<32>(ncol * Lc, t, blockDim.x,
-                     [&](int e) { return A[(int64_t)gcol(e / Lc) * Lc + (e % Lc)]; },
-                     [&](int e, double v) { blk[(e / Lc) * ldl + (e % Lc)] = v; });
+        if constexpr (EPL > 0) {
+          // columns padded to LP = 16 EPL rows (a power of two): element e is
+          // (e / LP, e % LP) by shifts, and the padding rows receive zeros
+          constexpr int LP = 16 * EPL;
+          bulk_copy<32>(ncol * LP, t, JNT,
+                        [&](int e) {
+                          const int row = e & (LP - 1);
+                          return (row < Lc) ? A[(int64_t)gcol(e / LP) * Lc + row] : 0.0;
+                        },
+                        [&](int e, double v) { blk[(e / LP) * ldl + (e & (LP - 1))] = v; });
+        } else {
+          bulk_copy<32>(ncol * Lc, t, blockDim.x,
+                        [&](int e) { return A[(int64_t)gcol(e / Lc) * Lc + (e % Lc)]; },
+                        [&](int e, double v) { blk[(e / Lc) * ldl + (e % Lc)] = v; });
+        }
         __syncthreads();
         if (rnd == 0) {
           // internal pairs of both blocks at once: two round-robin
@@ -950,8 +962,17 @@ __global__ __launch_bounds__(JNT) void k_jac(const DevCtx* __restrict__ cp, OpAr
         myrot = 0;
         mymax = 0.0f;
         __syncthreads();
-        bulk_copy<32>(ncol * Lc, t, blockDim.x, [&](int e) { return blk[(e / Lc) * ldl + (e % Lc)]; },
-                     [&](int e, double v) { A[(int64_t)gcol(e / Lc) * Lc + (e % Lc)] = v; });
+        if constexpr (EPL > 0) {
+          constexpr int LP = 16 * EPL;
+          bulk_copy<32>(ncol * LP, t, JNT, [&](int e) { return blk[(e / LP) * ldl + (e & (LP - 1))]; },
+                        [&](int e, double v) {
+                          const int row = e & (LP - 1);
+                          if (row < Lc) A[(int64_t)gcol(e / LP) * Lc + row] = v;
+                        });
+        } else {
+          bulk_copy<32>(ncol * Lc, t, blockDim.x, [&](int e) { return blk[(e / Lc) * ldl + (e % Lc)]; },
+                        [&](int e, double v) { A[(int64_t)gcol(e / Lc) * Lc + (e % Lc)] = v; });
+        }
         if (t == 0) {
           if (nrot > 0) atomicAdd(sy + MPSW_SYNC_ROT + (sweep & 63), nrot);
           atomicMax((unsigned int*)sy + MPSW_SYNC_MAXREL + (sweep & 63), maxrel);
