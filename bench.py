@@ -173,19 +173,17 @@ def copy_calibration(torch):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}))
 
 
-def mixed_batch(mpsw, synth, torch, args):
-    """The batched-shots workload: 64 shots on grids n in {8, 9, 10} with chi
-    caps in {32, 64, 128} (seeded), one state per grid size holding its shots,
-    all states stepped by one group graph.  The shots start from rest; the
-    first `warmup` steps are untimed, then each state's launch shapes are
-    autotuned, then `steps` steps are timed."""
-    shots = synth.batch_shots(64, seed=1, steps=args.warmup + args.steps)
-    prec = {"fp64": mpsw.MPSW_FP64, "fp32": mpsw.MPSW_FP32, "bf16": mpsw.MPSW_BF16}[args.precision]
-    states, counts = [], {}
-    t0 = time.perf_counter()
+def make_mixed_states(mpsw, synth, precision, steps, nshots=64):
+    """States of the batched-shots workload: the seeded shot list (grids n in
+    {8, 9, 10}, chi caps in {32, 64, 128}, Ricker sources), one state per grid
+    holding its shots with the layered model of that grid.  Returns (states,
+    {n: shots of that state in order}, all shots)."""
+    shots = synth.batch_shots(nshots, seed=1, steps=steps)
+    prec = {"fp64": mpsw.MPSW_FP64, "fp32": mpsw.MPSW_FP32, "bf16": mpsw.MPSW_BF16}[precision]
+    states, groups = [], {}
     for n in sorted(set(sh["n"] for sh in shots)):
         mine = [sh for sh in shots if sh["n"] == n]
-        counts[n] = len(mine)
+        groups[n] = mine
         cfg = synth.get_config("C3", n=n)
         lam = mine[0]["dt"] / mine[0]["dh"]
         st = mpsw.State([mpsw.make_config(n, sh["chi"], sh["eps"], lam, precision=prec) for sh in mine])
@@ -193,6 +191,18 @@ def mixed_batch(mpsw, synth, torch, args):
         for i, sh in enumerate(mine):
             st.set_source(i, sh["ix"], sh["iz"], sh["wavelet_samples"])
         states.append(st)
+    return states, groups, shots
+
+
+def mixed_batch(mpsw, synth, torch, args):
+    """The batched-shots workload: 64 shots on grids n in {8, 9, 10} with chi
+    caps in {32, 64, 128} (seeded), one state per grid size holding its shots,
+    all states stepped by one group graph.  The shots start from rest; the
+    first `warmup` steps are untimed, then each state's launch shapes are
+    autotuned, then `steps` steps are timed."""
+    t0 = time.perf_counter()
+    states, groups, shots = make_mixed_states(mpsw, synth, args.precision, args.warmup + args.steps)
+    counts = {n: len(g) for n, g in groups.items()}
     grp = mpsw.Group(states)
     done = 0
     while done < args.warmup:
