@@ -256,15 +256,27 @@ __global__ __launch_bounds__(256, (MODE == GEMM_FP64) ? 4 : 2) void k_gemm(const
     if (b_n_fast) { nn = e % TS; kk = e / TS; } else { kk = e % KS; nn = e / KS; }
   };
   double ra[EU], rb[EU];
+  // per element: offset of its k = 0 entry (every operand spans fewer than
+  // 2^31 elements) or -1 outside the tile's rows/columns, and its k within a
+  // slice; a slice at k0 adds k0 times the k stride
+  int aoff[EU], boff[EU], akk[EU], bkk[EU];
+#pragma unroll
+  for (int u = 0; u < EU; ++u) {
+    int mm, kk, nn, kb;
+    a_idx(u, mm, kk);
+    b_idx(u, nn, kb);
+    const int gi = m0 + mm, gj = n0 + nn;
+    aoff[u] = (gi < d.M) ? (int)((int64_t)gi * d.ars + (int64_t)kk * d.acs) : -1;
+    boff[u] = (gj < d.N) ? (int)((int64_t)kb * d.brs + (int64_t)gj * d.bcs) : -1;
+    akk[u] = kk;
+    bkk[u] = kb;
+  }
+  const int acs = (int)d.acs, brs = (int)d.brs;
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < EU; ++u) {
-      int mm, kk, nn, kb;
-      a_idx(u, mm, kk);
-      b_idx(u, nn, kb);
-      const int gi = m0 + mm, gk = k0 + kk, gj = n0 + nn, gkb = k0 + kb;
-      ra[u] = (gi < d.M && gk < d.K) ? d.A[(int64_t)gi * d.ars + (int64_t)gk * d.acs] : 0.0;
-      rb[u] = (gj < d.N && gkb < d.K) ? d.B[(int64_t)gkb * d.brs + (int64_t)gj * d.bcs] : 0.0;
+      ra[u] = (aoff[u] >= 0 && k0 + akk[u] < d.K) ? d.A[aoff[u] + k0 * acs] : 0.0;
+      rb[u] = (boff[u] >= 0 && k0 + bkk[u] < d.K) ? d.B[boff[u] + k0 * brs] : 0.0;
     }
   };
   const int l = t & 63, w = t >> 6, li = l & 15, lq = l >> 4;
