@@ -108,14 +108,15 @@ int mpsw_set_velocity_dense(mpsw_state st, const double* c2, double eps_c);
 int mpsw_set_velocity_mpo(mpsw_state st, const int* bonds, const double* cores);
 
 /* Point source for shot `shot` at grid point (ix, iz): step j (counted from
- * creation) adds wavelet[j] * e_(ix,iz) to psi^{j+1}; steps j >= nt add
- * nothing.  The host array is copied.  Errors: EINVAL. */
+ * creation, or from the shot's last mpsw_set_fields) adds wavelet[j] *
+ * e_(ix,iz) to psi^{j+1}; steps j >= nt add nothing.  The host array is
+ * copied.  Errors: EINVAL. */
 int mpsw_set_source(mpsw_state st, int shot, int ix, int iz, int nt, const double* wavelet);
 
 /* Initial fields of shot `shot` from dense host arrays (NULL = zero); each is
  * stored as its right-to-left TT-SVD with the shot's (eps, chi_max).
- * Restarts the shot's step counter (its source clock) at 0.  Errors: EINVAL,
- * ENOMEM, EHIP. */
+ * Restarts the shot's step counter (its source clock) at 0 and clears its
+ * learned-rank sketch back-offs.  Errors: EINVAL, ENOMEM, EHIP. */
 int mpsw_set_fields(mpsw_state st, int shot, const double* u_prev, const double* u_cur);
 
 /* Enqueue k >= 0 steps of eq. 17 on the state's stream (asynchronous).
