@@ -417,7 +417,7 @@ def main():
         "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: n={cfg['n']} (1024x1024), chi_max={cfg['chi']}, "
+        "config": {"workload": f"{args.workload}: n={cfg['n']} ({1 << cfg['n']}x{1 << cfg['n']}), chi_max={cfg['chi']}, "
                                f"eps={cfg['eps']}, layered-fault c^2 (cutoff {cfg['eps_c']}), "
                                f"start from a developed wavefield at the chi cap",
                    "shots": args.batch, "precision": args.precision,
