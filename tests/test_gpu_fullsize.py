@@ -74,3 +74,28 @@ def test_c3_batched_step_matches_oracle_on_sampled_shots(mpsw):
         assert err < 1e-10, (s, err)
         assert st.bonds(s, 0) == ds.ranks[-1][2], s
     st.close()
+
+
+def test_c5_step_matches_oracle(mpsw):
+    """n = 11 (2048 x 2048), chi = 256: factors of up to 512 columns and QR
+    panels of 4096 rows; one shot, one step after a warm-up step, against the
+    oracle step from the same fields."""
+    import torch
+    import bench
+    st, cfg, fields = bench.make_state(mpsw, synth, "C5", 1, "fp64")
+    st.step(1)
+    torch.cuda.synchronize()
+    n = cfg["n"]
+    up, u, k = st.to_dense(0, 1), st.to_dense(0, 0), st.stats(0)["step"]
+    st.step(1)
+    torch.cuda.synchronize()
+    g = st.to_dense(0, 0)
+    ds = S.DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], st.to_dense(0, 2), src=(fields[0][2], cfg["iz"]),
+                        wavelet=cfg["wavelet_samples"])
+    ds.u_prev, ds.u, ds.k = up, u, k
+    ds.step()
+    err = rel(g, ds.dense())
+    _say(f"C5 step {k + 1}: rel-L2 vs oracle {err:.2e}; bonds {st.bonds(0, 0)}")
+    assert err < 1e-10, err
+    assert st.bonds(0, 0) == ds.ranks[-1][2]
+    st.close()
