@@ -465,8 +465,15 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
       for (int j = t; j < n; j += QNT) pout[j] = (double)perm[j];
     }
   }
+  // Column blocks of BW are owned in groups of GB = 16 / BW adjacent blocks,
+  // the groups cyclically over the P workgroups: a narrow panel's reflector
+  // then reaches a whole 16-column matrix-core tile of trailing columns per
+  // application.  The owner of block j factors panel j.
+  constexpr int GB = 16 / BW;
+  auto owner = [&](int blk) { return (blk / GB) % P; };
   // my column blocks into S (column-major m x n)
-  for (int blk = w; blk < nbk; blk += P) {
+  for (int blk = 0; blk < nbk; ++blk) {
+    if (owner(blk) != w) continue;
     const int c0 = blk * BW, bw = min(BW, n - c0);
     if (xc == 1 && !pivot) {
       bulk_copy<8>(m * bw, t, QNT,
@@ -487,37 +494,40 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
     __syncthreads();
     if (t == 0) __hip_atomic_store(flags + j, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   };
-  auto apply = [&](int j, int blk) {
+  // panel j's reflector on blocks b0..b1 (adjacent, at most 16 columns)
+  auto apply = [&](int j, int b0, int b1) {
     const int r0 = j * BW, c0 = j * BW, bw = min(BW, n - c0);
-    const int cb = blk * BW, bwc = min(BW, n - cb);
+    const int cb = b0 * BW, bwc = min((b1 - b0 + 1) * BW, n - cb);
     apply_reflector<BW>(S + r0 + (int64_t)m * c0, m, S + r0 + (int64_t)m * cb, 1, m, m - r0, bw, bwc,
                         T + (int64_t)j * BW * BW, true, lds);
   };
-  if (w == 0) {
+  if (owner(0) == w) {
     factor_panel<BW, QNT>(c, S, m, n, 0, T, lds, red);
     publish(0);
   }
+  const int ngroups = (nbk + GB - 1) / GB;
   for (int j = 0; j < nbk; ++j) {
-    if (j % P != w) {
+    if (owner(j) != w) {
       if (t == 0) wait_geq(c, flags + j, 1);
       __syncthreads();
     }
     const int j1 = j + 1;
-    const bool own1 = (j1 < nbk) && (j1 % P == w);
-    if (own1) {
-      apply(j, j1);
+    const bool own1 = (j1 < nbk) && (owner(j1) == w);
+    if (own1) {   // the next panel first (lookahead)
+      apply(j, j1, j1);
       factor_panel<BW, QNT>(c, S, m, n, j1, T, lds, red);
       publish(j1);
     }
-    int first = w;
-    while (first <= j) first += P;
-    for (int blk = first; blk < nbk; blk += P) {
-      if (own1 && blk == j1) continue;
-      apply(j, blk);
+    for (int g = w; g < ngroups; g += P) {   // my other trailing blocks, one group at a time
+      int lo = max(g * GB, j + 1);
+      const int hi = min(g * GB + GB - 1, nbk - 1);
+      if (own1 && lo <= j1 && j1 <= hi) lo = j1 + 1;
+      if (lo <= hi) apply(j, lo, hi);
     }
   }
   // R (n x n) from my columns: row-major R (sweep) or R^T column-major (SVD)
-  for (int blk = w; blk < nbk && Rout; blk += P) {
+  for (int blk = 0; blk < nbk && Rout; ++blk) {
+    if (owner(blk) != w) continue;
     const int c0 = blk * BW, bw = min(BW, n - c0);
     bulk_copy<8>(n * bw, t, QNT,
                  [&](int e) {
