@@ -7,6 +7,11 @@ index (most significant first) and sites n+1..2n the bits z_{n-1} .. z_0
 real array G_k of shape (r_{k-1}, 2, r_k) with r_0 = r_K = 1 (the fields are
 real, so the complex cores of eq. 8 are not needed).
 
+A second site order, "interleaved", pairs the bits of equal significance:
+sites x_{n-1}, z_{n-1}, x_{n-2}, z_{n-2}, ..., x_0, z_0.  It represents the same
+fields (the paper fixes the register order of eq. 3; the interleaved order is
+the usual alternative for quantics grids and changes only the ranks needed).
+
 An MPO core has shape (w_left, w_right, 2, 2) indexed [a_l, a_r, s_out, s_in].
 """
 import numpy as np
@@ -20,6 +25,35 @@ SIGMA_MINUS = np.array([[0.0, 1.0], [0.0, 0.0]])  # |0><1|
 # ---------------------------------------------------------------------------
 # dense <-> cores
 # ---------------------------------------------------------------------------
+
+ORDERINGS = ("sequential", "interleaved")
+
+
+def site_bits(n, ordering="sequential"):
+    """(register, bit) of each of the K = 2n sites; register 0 is x, 1 is z and
+    bit is the significance (n-1 = most significant)."""
+    if ordering == "sequential":
+        return [(0, n - 1 - m) for m in range(n)] + [(1, n - 1 - m) for m in range(n)]
+    if ordering == "interleaved":
+        return [(r, n - 1 - m) for m in range(n) for r in (0, 1)]
+    raise ValueError(ordering)
+
+
+def to_sites(u, ordering="sequential"):
+    """Flat tensor over the sites (C order over [2]*K) of the field u[x, z]."""
+    u = np.asarray(u)
+    n = int(u.shape[0]).bit_length() - 1
+    t = u.reshape([2] * (2 * n))          # axes x_{n-1}..x_0, z_{n-1}..z_0
+    axes = [r * n + (n - 1 - b) for r, b in site_bits(n, ordering)]
+    return np.transpose(t, axes).reshape(-1)
+
+
+def from_sites(v, n, ordering="sequential"):
+    """Inverse of to_sites: the field u[x, z] (2^n x 2^n) of a site-order tensor."""
+    axes = [r * n + (n - 1 - b) for r, b in site_bits(n, ordering)]
+    t = np.asarray(v).reshape([2] * (2 * n))
+    return np.transpose(t, np.argsort(axes)).reshape(1 << n, 1 << n)
+
 
 def to_dense(cores):
     """Contract the chain; returns the flat vector of length 2^K."""
@@ -117,11 +151,10 @@ def product_state(bits):
     return cores
 
 
-def point_state(n, ix, iz):
-    """e_(ix, iz): sites are the bits of ix (MSB first) then of iz (eq. 3)."""
-    bits = [(ix >> (n - 1 - m)) & 1 for m in range(n)] + \
-           [(iz >> (n - 1 - m)) & 1 for m in range(n)]
-    return product_state(bits)
+def point_state(n, ix, iz, ordering="sequential"):
+    """e_(ix, iz): sites are the bits of ix (MSB first) then of iz (eq. 3), or
+    the two interleaved."""
+    return product_state([((ix, iz)[r] >> b) & 1 for r, b in site_bits(n, ordering)])
 
 
 def scale(cores, alpha):
@@ -223,12 +256,33 @@ def identity_mpo(n):
     return [I2.reshape(1, 1, 2, 2).copy() for _ in range(n)]
 
 
-def shift_mpo_2d(n, axis, direction, boundary="periodic"):
-    """S_x^{+-} = S^{+-} (x) I (eq. 14) and S_z^{+-} = I (x) S^{+-} (eq. 15)."""
+def passthrough_mpo_core(r):
+    """Identity on a site of the other register while a carry of bond r passes."""
+    return np.einsum("ab,ts->abts", np.eye(r), I2)
+
+
+def shift_mpo_2d(n, axis, direction, boundary="periodic", ordering="sequential"):
+    """S_x^{+-} = S^{+-} (x) I (eq. 14) and S_z^{+-} = I (x) S^{+-} (eq. 15).
+
+    In the interleaved order the register's cores alternate with identity cores
+    of the other register; a site that lies between two cores of the shifted
+    register passes the carry bond through unchanged.
+    """
     s = shift_mpo_1d(n, direction, boundary)
-    if axis == 0:
-        return s + identity_mpo(n)
-    return identity_mpo(n) + s
+    if ordering == "sequential":
+        if axis == 0:
+            return s + identity_mpo(n)
+        return identity_mpo(n) + s
+    out = []
+    for m in range(n):
+        for r in (0, 1):
+            if r == axis:
+                out.append(s[m])
+            elif r > axis:      # z site after x core m: the carry into x core m
+                out.append(passthrough_mpo_core(s[m].shape[1]))
+            else:               # x site before z core m: the carry out of z core m
+                out.append(passthrough_mpo_core(s[m].shape[0]))
+    return out
 
 
 def mpo_to_dense(W):
@@ -242,13 +296,13 @@ def mpo_to_dense(W):
     return M[0]
 
 
-def laplacian_mps(cores, n, boundary="periodic"):
+def laplacian_mps(cores, n, boundary="periodic", ordering="sequential"):
     """L psi with L = S_x+ + S_x- + S_z+ + S_z- - 4 I (eqs. 6 and 16) as one MPS.
 
     Each shift MPO is applied separately and the five terms are added as a
     direct sum (bond 2chi+2chi+chi+chi+chi inside a register).
     """
-    terms = [apply_mpo(shift_mpo_2d(n, ax, d, boundary), cores)
+    terms = [apply_mpo(shift_mpo_2d(n, ax, d, boundary, ordering), cores)
              for ax in (0, 1) for d in (+1, -1)]
     terms.append(cores)
     return direct_sum(terms, [1.0, 1.0, 1.0, 1.0, -4.0])

@@ -2,7 +2,9 @@
 
 psi^{k+1} = 2 psi^k - psi^{k-1} + lambda^2 C^2 (S_x+ + S_x- + S_z+ + S_z- - 4 I) psi^k
 
-with a compression after each operator application (Sec. 4.3).  Reading used
+with a compression after each operator application (Sec. 4.3).  Both steppers
+take the site order (sequential registers of eq. 3, or interleaved bits) as a
+parameter; fields given to and returned by them are always u[x, z].  Reading used
 throughout (three roundings per step, "S1"):
 
     y        = round(L psi^k)
@@ -27,19 +29,20 @@ from . import mps as M
 from . import fdtd as F
 
 
-def c2_mps(c2_dense, n, eps_c):
+def c2_mps(c2_dense, n, eps_c, ordering="sequential"):
     """The c^2 diagonal operator as an MPS (its diagonal), TT-SVD with cutoff eps_c."""
-    return M.tt_svd(np.asarray(c2_dense, dtype=np.float64).reshape(-1), 2 * n, eps_c,
+    return M.tt_svd(M.to_sites(np.asarray(c2_dense, dtype=np.float64), ordering), 2 * n, eps_c,
                     chi_max=1 << 30)
 
 
 class MPSStepper:
     def __init__(self, n, lam, eps, chi_max, c2_cores, boundary="periodic",
-                 src=None, wavelet=None):
+                 src=None, wavelet=None, ordering="sequential"):
         self.n, self.K = n, 2 * n
         self.lam, self.eps, self.chi = lam, eps, chi_max
         self.c2 = c2_cores
         self.boundary = boundary
+        self.ordering = ordering
         self.src = src
         self.wavelet = wavelet
         self.k = 0
@@ -49,8 +52,8 @@ class MPSStepper:
 
     def set_fields(self, u_prev, u):
         """Initial fields given densely; stored as their rounded MPS."""
-        self.psi_prev = M.tt_svd(np.asarray(u_prev).reshape(-1), self.K, self.eps, self.chi)
-        self.psi = M.tt_svd(np.asarray(u).reshape(-1), self.K, self.eps, self.chi)
+        self.psi_prev = M.tt_svd(M.to_sites(u_prev, self.ordering), self.K, self.eps, self.chi)
+        self.psi = M.tt_svd(M.to_sites(u, self.ordering), self.K, self.eps, self.chi)
 
     def _round(self, cores, which):
         log = []
@@ -63,32 +66,33 @@ class MPSStepper:
         s_k = 0.0
         if self.wavelet is not None and self.k < len(self.wavelet):
             s_k = float(self.wavelet[self.k])
-        y = self._round(M.laplacian_mps(self.psi, self.n, self.boundary), 0)
+        y = self._round(M.laplacian_mps(self.psi, self.n, self.boundary, self.ordering), 0)
         w = self._round(M.hadamard(self.c2, y), 1)
         terms = [self.psi, self.psi_prev, w]
         coeffs = [2.0, -1.0, self.lam * self.lam]
         if self.src is not None:
-            terms.append(M.point_state(self.n, self.src[0], self.src[1]))
+            terms.append(M.point_state(self.n, self.src[0], self.src[1], self.ordering))
             coeffs.append(s_k)
         nxt = self._round(M.direct_sum(terms, coeffs), 2)
         self.psi_prev, self.psi = self.psi, nxt
         self.k += 1
 
     def dense(self, which=0):
-        N = 1 << self.n
-        return M.to_dense(self.psi if which == 0 else self.psi_prev).reshape(N, N)
+        return M.from_sites(M.to_dense(self.psi if which == 0 else self.psi_prev), self.n,
+                            self.ordering)
 
 
 class DenseStepper:
     """Same rounded trajectory as MPSStepper, through dense TT-SVDs."""
 
     def __init__(self, n, lam, eps, chi_max, c2_dense, boundary="periodic",
-                 src=None, wavelet=None):
+                 src=None, wavelet=None, ordering="sequential"):
         self.n, self.K = n, 2 * n
         self.N = 1 << n
         self.lam, self.eps, self.chi = lam, eps, chi_max
         self.c2 = np.asarray(c2_dense, dtype=np.float64)
         self.boundary = boundary
+        self.ordering = ordering
         self.src = src
         self.wavelet = wavelet
         self.k = 0
@@ -99,10 +103,10 @@ class DenseStepper:
 
     def _round(self, t, which):
         log = []
-        cores = M.tt_svd(t.reshape(-1), self.K, self.eps, self.chi, log)
+        cores = M.tt_svd(M.to_sites(t, self.ordering), self.K, self.eps, self.chi, log)
         for site, s, r in log:
             self.log.append((self.k, which, site, s, r))
-        return M.to_dense(cores).reshape(self.N, self.N), M.bonds_of(cores)
+        return M.from_sites(M.to_dense(cores), self.n, self.ordering), M.bonds_of(cores)
 
     def set_fields(self, u_prev, u):
         self.u_prev, _ = self._round(np.asarray(u_prev, dtype=np.float64), -1)
