@@ -97,13 +97,15 @@ def train_rank_model(mpsw, synth, steps=80):
     return w, len(y)
 
 
-def make_state(mpsw, synth, workload, batch, precision, rank="exact", model=None):
+def make_state(mpsw, synth, workload, batch, precision, rank="exact", model=None, ordering="sequential"):
     cfg = synth.get_config(workload)
     n = cfg["n"]
     N = 1 << n
     prec = {"fp64": mpsw.MPSW_FP64, "fp32": mpsw.MPSW_FP32, "bf16": mpsw.MPSW_BF16}[precision]
     rmode = mpsw.MPSW_RANK_LEARNED if rank == "learned" else mpsw.MPSW_RANK_EXACT
-    cfgs = [mpsw.make_config(n, cfg["chi"], cfg["eps"], cfg["lam"], precision=prec, rank_mode=rmode, seed=11)
+    order = mpsw.MPSW_INTERLEAVED if ordering == "interleaved" else mpsw.MPSW_SEQUENTIAL
+    cfgs = [mpsw.make_config(n, cfg["chi"], cfg["eps"], cfg["lam"], precision=prec, rank_mode=rmode, seed=11,
+                             ordering=order)
             for _ in range(batch)]
     st = mpsw.State(cfgs if batch > 1 else cfgs[0])
     st.set_velocity_dense(cfg["c2"], cfg["eps_c"])
@@ -123,7 +125,7 @@ def make_state(mpsw, synth, workload, batch, precision, rank="exact", model=None
     return st, cfg, fields
 
 
-def cpu_baseline(synth, workload, fields, seconds):
+def cpu_baseline(synth, workload, fields, seconds, ordering="sequential"):
     """Steps/s of the FP64 CPU oracle (dense-detour stepper) from shot 0's state."""
     from oracle import mps as OM
     from oracle.stepper import DenseStepper
@@ -135,10 +137,11 @@ def cpu_baseline(synth, workload, fields, seconds):
     cfg = synth.get_config(workload)
     n = cfg["n"]
     N = 1 << n
-    c2 = OM.to_dense(OM.tt_svd(cfg["c2"].reshape(-1), 2 * n, cfg["eps_c"], chi_max=1 << 30)).reshape(N, N)
+    c2 = OM.from_sites(OM.to_dense(OM.tt_svd(OM.to_sites(cfg["c2"], ordering), 2 * n, cfg["eps_c"],
+                                              chi_max=1 << 30)), n, ordering)
     up, u, ix = fields[0]
     ds = DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], c2, src=(ix, cfg["iz"]),
-                      wavelet=cfg["wavelet_samples"])
+                      wavelet=cfg["wavelet_samples"], ordering=ordering)
     ds.set_fields(up, u)
     steps, t0 = 0, time.perf_counter()
     while True:
@@ -312,6 +315,8 @@ def main():
     ap.add_argument("--kernel-class", type=int, default=-1,
                     help="kernel class for the roofline (-1: the one with most time)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--ordering", default="sequential", choices=["sequential", "interleaved"],
+                    help="site order of the quantics MPS: x bits then z bits, or the two interleaved")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trajectory", default=None, metavar="STEPS",
                     help="precision run instead of the throughput measurement: one shot of the "
@@ -352,10 +357,11 @@ def main():
     if args.rank == "learned":
         model, nrows = train_rank_model(mpsw, synth)
         log(f"rank network trained on {nrows} logged bonds in {time.perf_counter() - t_setup:.1f} s")
-    st, cfg, fields = make_state(mpsw, synth, args.workload, args.batch, args.precision, args.rank, model)
+    st, cfg, fields = make_state(mpsw, synth, args.workload, args.batch, args.precision, args.rank, model,
+                                 args.ordering)
     torch.cuda.synchronize()
     free, total = torch.cuda.mem_get_info()
-    log(f"setup {time.perf_counter() - t_setup:.1f} s; bonds {st.bonds(0, 0)}; "
+    log(f"setup {time.perf_counter() - t_setup:.1f} s; bonds {st.bonds(0, 0)}; c^2 bonds {st.bonds(0, 2)}; "
         f"device memory in use {(total - free) / 2**30:.1f} of {total / 2**30:.0f} GiB")
 
     tuned = None
@@ -399,7 +405,8 @@ def main():
     avg_ms = prof["total_ms"] / max(prof["launches"], 1)
     flops_per_launch = prof["alg_flops"] / max(prof["launches"], 1)
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    traffic = read_traffic(kclass, args.workload, args.batch, args.precision)
+    # counters were taken on the sequential site order only
+    traffic = read_traffic(kclass, args.workload, args.batch, args.precision) if args.ordering == "sequential" else None
     # contractions run on the matrix cores (dense peak of their operand type);
     # the factorisation kernels on the FP64 vector ALUs
     if KERNEL_NAMES[kclass] == "k_gemm":
@@ -420,7 +427,7 @@ def main():
         "config": {"workload": f"{args.workload}: n={cfg['n']} ({1 << cfg['n']}x{1 << cfg['n']}), chi_max={cfg['chi']}, "
                                f"eps={cfg['eps']}, layered-fault c^2 (cutoff {cfg['eps_c']}), "
                                f"start from a developed wavefield at the chi cap",
-                   "shots": args.batch, "precision": args.precision,
+                   "shots": args.batch, "precision": args.precision, "site_order": args.ordering,
                    "rank": "exact SVD" if args.rank == "exact" else "learned rank + range finder, exact fallback",
                    "graph": bool(args.graph),
                    "tuned": None if tuned is None else {"qr_workgroups_per_shot": tuned[0],
@@ -432,7 +439,7 @@ def main():
         # the same number of steps; its last `steps` steps are timed
         total = int(stats[0]["step"])
         u_form = st.to_dense(0, 0)
-        pl, _, _ = make_state(mpsw, synth, args.workload, 1, "fp64")
+        pl, _, _ = make_state(mpsw, synth, args.workload, 1, "fp64", ordering=args.ordering)
         up, u, ix = fields[0]
         pl.set_fields(0, up, u)
         pl.set_source(0, ix, cfg["iz"], cfg["wavelet_samples"])
@@ -453,7 +460,7 @@ def main():
                                  "what": "shot 0 of this run vs the plain single-shot FP64 run after the same steps"}
         log(f"plain FP64 single shot: {args.steps / pel:.2f} steps/s; rel-L2 of shot 0 vs it {err:.2e}")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(synth, args.workload, fields, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(synth, args.workload, fields, args.cpu_seconds, args.ordering)
     st.close()
     print(json.dumps(out), flush=True)
 

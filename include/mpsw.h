@@ -6,6 +6,9 @@
  * (Sec. 2) is held as a matrix product state over K = 2n binary sites
  * (Sec. 4.1, eq. 8); sites 1..n are the bits x_{n-1}..x_0 of the horizontal
  * index (most significant first), sites n+1..2n the bits z_{n-1}..z_0 (eq. 3).
+ * A state may instead use the interleaved order x_{n-1} z_{n-1} ... x_0 z_0
+ * (bits of equal significance side by side); it holds the same fields and
+ * changes only the ranks the roundings keep.
  * One call of mpsw_step advances eq. 17,
  *
  *   psi^{k+1} = 2 psi^k - psi^{k-1} + lambda^2 C^2 (S_x+ + S_x- + S_z+ + S_z- - 4 I) psi^k,
@@ -56,6 +59,7 @@ enum {
    accumulated in FP64. */
 enum { MPSW_FP64 = 0, MPSW_FP32 = 1, MPSW_BF16 = 2 };
 enum { MPSW_PERIODIC = 0, MPSW_OPEN = 1 };                     /* shift boundary */
+enum { MPSW_SEQUENTIAL = 0, MPSW_INTERLEAVED = 1 };            /* site order */
 enum { MPSW_RANK_EXACT = 0, MPSW_RANK_LEARNED = 1 };           /* truncation rank mode */
 
 typedef struct mpsw_config {
@@ -67,6 +71,10 @@ typedef struct mpsw_config {
   int boundary;       /* MPSW_PERIODIC (cyclic shifts) | MPSW_OPEN (eq. 11 as printed) */
   int rank_mode;      /* MPSW_RANK_EXACT | MPSW_RANK_LEARNED */
   uint64_t seed;      /* seed of the library's own random sketches */
+  int ordering;       /* MPSW_SEQUENTIAL (x bits, then z bits; eq. 3) | MPSW_INTERLEAVED
+                         (x_{n-1} z_{n-1} ... x_0 z_0).  Dense fields passed in and out
+                         are u[x, z] in either order; MPS cores given to
+                         mpsw_set_velocity_mpo are in the state's site order */
 } mpsw_config;
 
 typedef struct mpsw_state_s* mpsw_state;
@@ -90,20 +98,21 @@ typedef struct mpsw_stats {
 int mpsw_create_state(const mpsw_config* cfg, void* hip_stream, mpsw_state* out);
 
 /* Batch of nshots shots with the same n sharing one c^2 model; shot i uses
- * cfgs[i] (chi_max and eps may differ per shot; n, lambda, precision, boundary
- * must agree).  Steps of a batch advance all shots together.  Errors as above. */
+ * cfgs[i] (chi_max and eps may differ per shot; n, lambda, precision, boundary,
+ * rank mode and site order must agree).  Steps of a batch advance all shots together.  Errors as above. */
 int mpsw_create_batch(const mpsw_config* cfgs, int nshots, void* hip_stream, mpsw_state* out);
 
 /* Set c^2 from its dense field (host, 4^n float64, all > 0).  The diagonal
  * c^2 operator is built on the device as the right-to-left truncated TT-SVD of
- * c^2 with relative cutoff eps_c and no bond cap (Sec. 4.3: the velocity
- * field encoded as a diagonal MPO).  Errors: EINVAL (non-positive or
+ * c^2 (taken in the state's site order) with relative cutoff eps_c and no
+ * bond cap (Sec. 4.3: the velocity field encoded as a diagonal MPO).  Errors: EINVAL (non-positive or
  * non-finite c^2), ECFL, ENOMEM, EHIP. */
 int mpsw_set_velocity_dense(mpsw_state st, const double* c2, double eps_c);
 
 /* Set c^2 directly as the cores of its diagonal (host, float64):
  * bonds[0..K] with bonds[0] = bonds[K] = 1, cores packed site after site,
- * core k row-major of shape (bonds[k], 2, bonds[k+1]).  CFL is checked on the
+ * core k row-major of shape (bonds[k], 2, bonds[k+1]), site k of the state's
+ * site order.  CFL is checked on the
  * reconstructed field.  Errors: EINVAL, ECFL, ENOMEM, EHIP. */
 int mpsw_set_velocity_mpo(mpsw_state st, const int* bonds, const double* cores);
 
@@ -235,11 +244,12 @@ int mpsw_mlp_forward(const float* X, int m, const float* w, float* out);
 
 /* Host-only helper (no device work), used by the CPU tests: the fused
  * Laplacian MPO S_x+ + S_x- + S_z+ + S_z- - 4I (eqs. 6 and 16) the library
- * applies, for an n-bit register pair and a boundary.  Writes K+1 bonds into
+ * applies, for an n-bit register pair, a boundary and a site order
+ * (MPSW_SEQUENTIAL or MPSW_INTERLEAVED).  Writes K+1 bonds into
  * `bonds` and, if `cores` is not NULL, the cores packed site after site, core k
  * of shape [w_k][w_{k+1}][s_out][s_in] row-major (at most `cap` doubles).
  * Returns the total number of core entries (>= 0) or a negative error code. */
-int mpsw_debug_laplacian_mpo(int n, int boundary, int* bonds, double* cores, int64_t cap);
+int mpsw_debug_laplacian_mpo(int n, int boundary, int ordering, int* bonds, double* cores, int64_t cap);
 
 /* Test helper (device work on the current device, default stream): runs the
  * factorisation kernels of a rounding on one host matrix A (m x n row-major).

@@ -486,7 +486,9 @@ __global__ void k_pack_sum(const DevCtx* __restrict__ cp, OpArgs a) {
   const int stp = dm[DL::step];
   if (stp >= 0 && stp < nt && stp < c.nt_max) ssrc = c.wavelet[(int64_t)shot * c.nt_max + stp];
   const int ix = dm[DL::src_ix], iz = dm[DL::src_iz];
-  const int bit = (k < n) ? ((ix >> (n - 1 - k)) & 1) : ((iz >> (K - 1 - k)) & 1);
+  int bit;
+  if (c.ordering == MPSW_INTERLEAVED) bit = (((k & 1) ? iz : ix) >> (n - 1 - (k >> 1))) & 1;
+  else bit = (k < n) ? ((ix >> (n - 1 - k)) & 1) : ((iz >> (K - 1 - k)) & 1);
   const double coef[3] = {2.0, -1.0, c.lam2};
   double* out = shot_eng(c, shot) + c.L.off_in[k];
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {

@@ -118,6 +118,7 @@ struct EngineLayout {
 struct DevCtx {
   int K, n, B;
   int boundary;
+  int ordering;                                  // MPSW_SEQUENTIAL or MPSW_INTERLEAVED
   double lam2;
   int64_t mps_stride;                            // doubles per shot of the MPS arena
   double* mps;                                   // MPS arena base

@@ -50,105 +50,147 @@ int set_last_error(int code, const char* msg) { return fail(code, msg); }
 namespace {
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// Dense fields cross the boundary as u[x, z] (flat x 2^n + z).  In the
+// interleaved site order the flat site index holds x_m at bit 2m+1 and z_m at
+// bit 2m; these two copies move a field between the two layouts.
+std::vector<int64_t> spread_bits(int n) {
+  std::vector<int64_t> sp((size_t)1 << n, 0);
+  for (int64_t v = 0; v < ((int64_t)1 << n); ++v)
+    for (int m = 0; m < n; ++m) sp[v] |= ((v >> m) & 1) << (2 * m);
+  return sp;
+}
+void field_to_sites(const double* u, int n, double* t) {
+  const auto sp = spread_bits(n);
+  const int64_t N = (int64_t)1 << n;
+  for (int64_t x = 0; x < N; ++x)
+    for (int64_t z = 0; z < N; ++z) t[(sp[x] << 1) | sp[z]] = u[x * N + z];
+}
+void sites_to_field(const double* t, int n, double* u) {
+  const auto sp = spread_bits(n);
+  const int64_t N = (int64_t)1 << n;
+  for (int64_t x = 0; x < N; ++x)
+    for (int64_t z = 0; z < N; ++z) u[x * N + z] = t[(sp[x] << 1) | sp[z]];
+}
+
 // ---------------------------------------------------------------------------
 // The fused Laplacian MPO S_x+ + S_x- + S_z+ + S_z- - 4I (eqs. 6, 16) in site
-// order (x bits MSB first, then z bits).  It is a finite automaton read from
-// the last site to the first; the bond carries what the sites to the right
-// did: P (no shift yet: the x register will shift), C (carry of an S+ still
-// pending), B (borrow of an S- still pending), D (shift finished, or the -4I
-// term).  A pending carry at a register's top bit wraps (periodic) or is
-// dropped (open, the terminal core of eq. 11 as printed).  Unused states of a
-// bond are pruned, giving bonds 3 inside the x register, 2 at the x|z cut and
-// 4 inside the z register.
+// order: x bits MSB first then z bits (eq. 3), or the two interleaved.  It is
+// a finite automaton read from the last site to the first; the bond carries
+// what the sites to the right did: P (no shift yet: the x register will
+// shift), CX / BX (carry of an S+ / borrow of an S- of the x register still
+// pending), CZ / BZ (the same for z), D (shift finished, or the -4I term).
+// The z shift starts at the last site (its least significant bit); the x shift
+// starts where P meets the first x site, its least significant bit.  A site
+// of one register passes the other register's pending carry on unchanged.  A
+// pending carry at a register's top bit wraps (periodic) or is dropped (open,
+// the terminal core of eq. 11 as printed).  States that no path from both
+// ends reaches are pruned: bonds 3 inside the x register, 2 at the x|z cut
+// and 4 inside the z register in the sequential order; at most 5 in the
+// interleaved one.
 // ---------------------------------------------------------------------------
 struct LapMPO {
   std::vector<int> bonds;                  // K+1
   std::vector<std::vector<double>> cores;  // [wl][wr][2][2]
 };
 
-LapMPO build_laplacian_mpo(int n, int boundary) {
+LapMPO build_laplacian_mpo(int n, int boundary, int ordering) {
   const int K = 2 * n;
-  enum { P = 0, C = 1, Bs = 2, D = 3 };
+  enum { P = 0, CX = 1, BX = 2, CZ = 3, BZ = 4, D = 5, NS = 6 };
   const double I2[2][2] = {{1, 0}, {0, 1}};
   const double SP[2][2] = {{0, 0}, {1, 0}};  // |1><0|
   const double SM[2][2] = {{0, 1}, {0, 0}};  // |0><1|
   const bool periodic = boundary == MPSW_PERIODIC;
+  const bool il = ordering == MPSW_INTERLEAVED;
+  auto zsite = [&](int k) { return il ? (k & 1) == 1 : k >= n; };
+  const int zmsb = il ? 1 : n;   // site of the most significant z bit
   // T[k][out][in][s'][s]
-  std::vector<std::vector<double>> T(K, std::vector<double>(4 * 4 * 4, 0.0));
-  auto add = [&](int k, int out, int in, const double (*op)[2], double w) {
+  std::vector<std::vector<double>> T(K, std::vector<double>(NS * NS * 4, 0.0));
+  auto add = [&](int k, int out, int in, const double (*op)[2]) {
     for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) T[k][((out * 4 + in) * 2 + a) * 2 + b] += w * op[a][b];
+      for (int b = 0; b < 2; ++b) T[k][((out * NS + in) * 2 + a) * 2 + b] += op[a][b];
   };
   for (int k = 0; k < K; ++k) {
-    const bool zreg = k >= n;
-    add(k, D, D, I2, 1.0);
-    add(k, C, C, SM, 1.0);  // bit 1 -> 0, carry moves on
-    add(k, D, C, SP, 1.0);  // bit 0 -> 1, carry absorbed
-    add(k, Bs, Bs, SP, 1.0);  // bit 0 -> 1, borrow moves on
-    add(k, D, Bs, SM, 1.0);   // bit 1 -> 0, borrow absorbed
-    if (zreg) {
-      add(k, P, P, I2, 1.0);
+    const bool z = zsite(k);
+    const int C = z ? CZ : CX, Bs = z ? BZ : BX;    // this site's register
+    const int Co = z ? CX : CZ, Bo = z ? BX : BZ;   // the other register
+    add(k, D, D, I2);
+    add(k, C, C, SM);    // bit 1 -> 0, carry moves on
+    add(k, D, C, SP);    // bit 0 -> 1, carry absorbed
+    add(k, Bs, Bs, SP);  // bit 0 -> 1, borrow moves on
+    add(k, D, Bs, SM);   // bit 1 -> 0, borrow absorbed
+    add(k, Co, Co, I2);  // the other register's carry and borrow pass
+    add(k, Bo, Bo, I2);
+    if (z) {
+      add(k, P, P, I2);
     } else {
-      // the x register starts its shift where P arrives (its least significant bit)
-      add(k, D, P, SP, 1.0);
-      add(k, D, P, SM, 1.0);
-      add(k, C, P, SM, 1.0);
-      add(k, Bs, P, SP, 1.0);
+      add(k, D, P, SP);
+      add(k, D, P, SM);
+      add(k, CX, P, SM);
+      add(k, BX, P, SP);
     }
-    if (k == n) {  // most significant z bit: a pending carry/borrow wraps or is dropped
-      for (int in = 0; in < 4; ++in)
+    if (k == zmsb) {  // most significant z bit: a pending carry/borrow wraps or is dropped
+      for (int in = 0; in < NS; ++in)
         for (int e = 0; e < 4; ++e) {
-          double& c = T[k][((C * 4 + in) * 2) * 2 + e];
-          double& b = T[k][((Bs * 4 + in) * 2) * 2 + e];
-          if (periodic) {
-            T[k][((D * 4 + in) * 2) * 2 + e] += c + b;
-          }
+          double& c = T[k][(CZ * NS + in) * 4 + e];
+          double& b = T[k][(BZ * NS + in) * 4 + e];
+          if (periodic) T[k][(D * NS + in) * 4 + e] += c + b;
           c = 0.0;
           b = 0.0;
         }
     }
   }
-  const double left[4] = {0.0, periodic ? 1.0 : 0.0, periodic ? 1.0 : 0.0, 1.0};
-  const double right[4] = {1.0, 1.0, 1.0, -4.0};
-  // dense cores with bonds 1, 4, ..., 4, 1
+  // the x register's top bit is site 0: its pending carry leaves through the
+  // left end (kept when periodic); the z shift enters at the right end
+  double left[NS] = {0.0, 0.0, 0.0, 0.0, 0.0, 1.0};
+  left[CX] = left[BX] = periodic ? 1.0 : 0.0;
+  double right[NS] = {1.0, 0.0, 0.0, 1.0, 1.0, -4.0};
+  // dense cores with bonds 1, NS, ..., NS, 1
   std::vector<int> wl(K), wr(K);
   std::vector<std::vector<double>> W(K);
   for (int k = 0; k < K; ++k) {
-    wl[k] = (k == 0) ? 1 : 4;
-    wr[k] = (k == K - 1) ? 1 : 4;
+    wl[k] = (k == 0) ? 1 : NS;
+    wr[k] = (k == K - 1) ? 1 : NS;
     W[k].assign((size_t)wl[k] * wr[k] * 4, 0.0);
     for (int o = 0; o < wl[k]; ++o)
       for (int i = 0; i < wr[k]; ++i)
         for (int e = 0; e < 4; ++e) {
           double v = 0.0;
-          for (int oo = 0; oo < 4; ++oo) {
+          for (int oo = 0; oo < NS; ++oo) {
             if (k != 0 && oo != o) continue;
             const double lw = (k == 0) ? left[oo] : 1.0;
-            for (int ii = 0; ii < 4; ++ii) {
+            for (int ii = 0; ii < NS; ++ii) {
               if (k != K - 1 && ii != i) continue;
               const double rw = (k == K - 1) ? right[ii] : 1.0;
-              v += lw * rw * T[k][(oo * 4 + ii) * 4 + e];
+              v += lw * rw * T[k][(oo * NS + ii) * 4 + e];
             }
           }
           W[k][((size_t)o * wr[k] + i) * 4 + e] = v;
         }
   }
-  // prune states of each internal bond that carry nothing on either side
+  // keep the states of each bond that a chain of nonzero transitions reaches
+  // from the left end and from the right end
+  auto nz = [&](int k, int o, int i) {
+    for (int e = 0; e < 4; ++e)
+      if (W[k][((size_t)o * wr[k] + i) * 4 + e] != 0.0) return true;
+    return false;
+  };
+  std::vector<std::vector<char>> fromL(K + 1, std::vector<char>(NS, 0)), fromR(K + 1, std::vector<char>(NS, 0));
+  fromL[0][0] = 1;
+  for (int b = 1; b <= K; ++b)
+    for (int s = 0; s < wr[b - 1]; ++s)
+      for (int o = 0; o < wl[b - 1]; ++o)
+        if (fromL[b - 1][o] && nz(b - 1, o, s)) { fromL[b][s] = 1; break; }
+  fromR[K][0] = 1;
+  for (int b = K - 1; b >= 0; --b)
+    for (int s = 0; s < wl[b]; ++s)
+      for (int i = 0; i < wr[b]; ++i)
+        if (fromR[b + 1][i] && nz(b, s, i)) { fromR[b][s] = 1; break; }
   std::vector<std::vector<int>> keep(K + 1);
   keep[0] = {0};
   keep[K] = {0};
-  for (int b = 1; b < K; ++b) {
-    for (int s = 0; s < 4; ++s) {
-      bool lnz = false, rnz = false;
-      for (int o = 0; o < wl[b - 1] && !lnz; ++o)
-        for (int e = 0; e < 4; ++e)
-          if (W[b - 1][((size_t)o * wr[b - 1] + s) * 4 + e] != 0.0) { lnz = true; break; }
-      for (int i = 0; i < wr[b] && !rnz; ++i)
-        for (int e = 0; e < 4; ++e)
-          if (W[b][((size_t)s * wr[b] + i) * 4 + e] != 0.0) { rnz = true; break; }
-      if (lnz && rnz) keep[b].push_back(s);
-    }
-  }
+  for (int b = 1; b < K; ++b)
+    for (int s = 0; s < NS; ++s)
+      if (fromL[b][s] && fromR[b][s]) keep[b].push_back(s);
   LapMPO out;
   out.bonds.resize(K + 1);
   for (int b = 0; b <= K; ++b) out.bonds[b] = (int)keep[b].size();
@@ -408,6 +450,7 @@ void fill_ctx(mpsw_state st, DevCtx& h, double* eng, const EngineLayout& L) {
   h.n = st->n;
   h.B = st->B;
   h.boundary = st->cfg[0].boundary;
+  h.ordering = st->cfg[0].ordering;
   h.lam2 = st->cfg[0].lambda * st->cfg[0].lambda;
   h.mps_stride = st->mps_stride;
   h.mps = st->mps;
@@ -765,6 +808,12 @@ int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t ch
   std::vector<double> hr(RL::size, 0.0);
   hr[RL::eps] = eps;
   hipStream_t s0 = st->stream;
+  std::vector<double> sites;   // the field in site order (interleaved states)
+  if (st->cfg[0].ordering == MPSW_INTERLEAVED) {
+    sites.resize(N);
+    field_to_sites(host_field, st->n, sites.data());
+    host_field = sites.data();
+  }
   if (hipMemcpyAsync(dims, hd.data(), DL::size * sizeof(int), hipMemcpyHostToDevice, s0) != hipSuccess ||
       hipMemcpyAsync(reals, hr.data(), RL::size * sizeof(double), hipMemcpyHostToDevice, s0) != hipSuccess ||
       hipMemcpyAsync(dense, host_field, N * sizeof(double), hipMemcpyHostToDevice, s0) != hipSuccess) {
@@ -877,9 +926,10 @@ int create_group(const mpsw_config* cfgs, int nshots, void* stream, mpsw_state* 
       return fail(MPSW_EINVAL, "unknown precision");
     if (c.boundary != MPSW_PERIODIC && c.boundary != MPSW_OPEN) return fail(MPSW_EINVAL, "unknown boundary");
     if (c.rank_mode != MPSW_RANK_EXACT && c.rank_mode != MPSW_RANK_LEARNED) return fail(MPSW_EINVAL, "unknown rank mode");
+    if (c.ordering != MPSW_SEQUENTIAL && c.ordering != MPSW_INTERLEAVED) return fail(MPSW_EINVAL, "unknown site order");
     if (c.n != c0.n || c.lambda != c0.lambda || c.precision != c0.precision || c.boundary != c0.boundary ||
-        c.rank_mode != c0.rank_mode)
-      return fail(MPSW_EINVAL, "shots of one batch must share n, lambda, precision, boundary and rank mode");
+        c.rank_mode != c0.rank_mode || c.ordering != c0.ordering)
+      return fail(MPSW_EINVAL, "shots of one batch must share n, lambda, precision, boundary, rank mode and site order");
   }
   mpsw_state st = new mpsw_state_s();
   st->B = nshots;
@@ -892,7 +942,7 @@ int create_group(const mpsw_config* cfgs, int nshots, void* stream, mpsw_state* 
   st->chi_cap = 1;
   for (int i = 0; i < nshots; ++i) st->chi_cap = std::max(st->chi_cap, cfgs[i].chi_max);
   const int K = st->K;
-  st->lap = build_laplacian_mpo(st->n, c0.boundary);
+  st->lap = build_laplacian_mpo(st->n, c0.boundary, c0.ordering);
   st->Rmax = state_rmax(K, st->chi_cap);
   // MPS slots
   int64_t off = 0;
@@ -1331,6 +1381,11 @@ int mpsw_to_dense(mpsw_state st, int shot, int which, double* out, int out_is_de
   std::vector<double> host;
   int rc = contract_dense(st, shot, slot, host);
   if (rc != MPSW_OK) return rc;
+  if (st->cfg[0].ordering == MPSW_INTERLEAVED) {
+    std::vector<double> u(host.size());
+    sites_to_field(host.data(), st->n, u.data());
+    host.swap(u);
+  }
   for (double v : host)
     if (!std::isfinite(v)) return fail(MPSW_ENONFINITE, "non-finite value in the field");
   if (out_is_device) {
@@ -1668,9 +1723,10 @@ int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, doubl
 
 // Host-side helper exported for tests: the fused Laplacian MPO cores
 // ([wl][wr][s'][s] per site, packed) and bonds (K+1) for a register of n bits.
-int mpsw_debug_laplacian_mpo(int n, int boundary, int* bonds, double* cores, int64_t cap) {
+int mpsw_debug_laplacian_mpo(int n, int boundary, int ordering, int* bonds, double* cores, int64_t cap) {
   if (n < 1 || n > 12 || !bonds) return fail(MPSW_EINVAL, "bad argument");
-  LapMPO m = build_laplacian_mpo(n, boundary);
+  if (ordering != MPSW_SEQUENTIAL && ordering != MPSW_INTERLEAVED) return fail(MPSW_EINVAL, "unknown site order");
+  LapMPO m = build_laplacian_mpo(n, boundary, ordering);
   std::copy(m.bonds.begin(), m.bonds.end(), bonds);
   int64_t o = 0;
   for (auto& c : m.cores) {

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libmpsw.so")
 MPSW_FP64, MPSW_FP32, MPSW_BF16 = 0, 1, 2
 MPSW_PERIODIC, MPSW_OPEN = 0, 1
 MPSW_RANK_EXACT, MPSW_RANK_LEARNED = 0, 1
+MPSW_SEQUENTIAL, MPSW_INTERLEAVED = 0, 1
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ECFL", -6: "ENONFINITE"}
 
 EXPORTS = [
@@ -41,7 +42,7 @@ class MpswError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("chi_max", ctypes.c_int), ("eps", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("precision", ctypes.c_int), ("boundary", ctypes.c_int),
-                ("rank_mode", ctypes.c_int), ("seed", ctypes.c_uint64)]
+                ("rank_mode", ctypes.c_int), ("seed", ctypes.c_uint64), ("ordering", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -80,7 +81,7 @@ def load():
         "mpsw_get_stats": [P, I, ctypes.POINTER(Stats)],
         "mpsw_get_shape": [P, ctypes.POINTER(I), ctypes.POINTER(I)],
         "mpsw_destroy": [P],
-        "mpsw_debug_laplacian_mpo": [I, I, P, P, ctypes.c_int64],
+        "mpsw_debug_laplacian_mpo": [I, I, I, P, P, ctypes.c_int64],
         "mpsw_debug_factor": [I, I, I, P, P, P],
         "mpsw_profile": [P, I],
         "mpsw_set_graph_mode": [P, I],
@@ -116,8 +117,8 @@ def _f64(a):
 
 
 def make_config(n, chi_max, eps, lam, precision=MPSW_FP64, boundary=MPSW_PERIODIC,
-                rank_mode=MPSW_RANK_EXACT, seed=0):
-    return Config(n, chi_max, eps, lam, precision, boundary, rank_mode, seed)
+                rank_mode=MPSW_RANK_EXACT, seed=0, ordering=MPSW_SEQUENTIAL):
+    return Config(n, chi_max, eps, lam, precision, boundary, rank_mode, seed, ordering)
 
 
 def _stream_handle(stream):
@@ -298,14 +299,15 @@ def mlp_forward(X, w):
     return out
 
 
-def debug_laplacian_mpo(n, boundary=MPSW_PERIODIC):
+def debug_laplacian_mpo(n, boundary=MPSW_PERIODIC, ordering=MPSW_SEQUENTIAL):
     """Host-built fused Laplacian MPO cores (list of [wl, wr, 2, 2] arrays)."""
     lib = load()
     K = 2 * n
     bonds = np.zeros(K + 1, dtype=np.int32)
-    total = _check(lib.mpsw_debug_laplacian_mpo(n, boundary, bonds.ctypes.data_as(ctypes.c_void_p), None, 0))
+    total = _check(lib.mpsw_debug_laplacian_mpo(n, boundary, ordering, bonds.ctypes.data_as(ctypes.c_void_p),
+                                                None, 0))
     buf = np.zeros(max(total, 1))
-    _check(lib.mpsw_debug_laplacian_mpo(n, boundary, bonds.ctypes.data_as(ctypes.c_void_p),
+    _check(lib.mpsw_debug_laplacian_mpo(n, boundary, ordering, bonds.ctypes.data_as(ctypes.c_void_p),
                                         buf.ctypes.data_as(ctypes.c_void_p), buf.size))
     cores, o = [], 0
     for k in range(K):

@@ -44,6 +44,38 @@ def test_fused_laplacian_mpo_is_five_point_stencil(lib, n, boundary):
         assert bonds[1:n] == [3] * (n - 1) and bonds[n] == 2 and bonds[n + 1:2 * n] == [4] * (n - 1)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+@pytest.mark.parametrize("boundary", ["periodic", "open"])
+def test_fused_laplacian_mpo_interleaved(lib, n, boundary):
+    """The interleaved-order MPO is the five-point stencil with rows and
+    columns in site order (checked on every basis field of the grid)."""
+    bc = mpsw.MPSW_PERIODIC if boundary == "periodic" else mpsw.MPSW_OPEN
+    bonds, W = mpsw.debug_laplacian_mpo(n, bc, mpsw.MPSW_INTERLEAVED)
+    Wd = M.mpo_to_dense(W)
+    N = 1 << n
+    for x in range(N):
+        for z in range(N):
+            e = np.zeros((N, N))
+            e[x, z] = 1.0
+            got = M.from_sites(Wd @ M.to_sites(e, "interleaved"), n, "interleaved")
+            np.testing.assert_array_equal(got, F.laplacian(e, boundary))
+    assert max(bonds) <= 5
+    if n >= 2:   # x carry, x borrow, z carry, z borrow and D cross the inner bonds
+        assert bonds[2:2 * n - 1] == [5] * (2 * n - 3)
+
+
+def test_interleaved_order_is_validated(lib):
+    a = mpsw.make_config(4, 8, 1e-8, 0.1, ordering=7)
+    with pytest.raises(mpsw.MpswError) as ei:
+        mpsw.State(a)
+    assert ei.value.name == "EINVAL"
+    b = mpsw.make_config(4, 8, 1e-8, 0.1, ordering=mpsw.MPSW_INTERLEAVED)
+    c = mpsw.make_config(4, 8, 1e-8, 0.1)
+    with pytest.raises(mpsw.MpswError) as ei:
+        mpsw.State([b, c])
+    assert ei.value.name == "EINVAL"
+
+
 @pytest.mark.parametrize("kw,field", [
     (dict(n=0), "n"), (dict(n=13), "n"), (dict(chi_max=0), "chi"), (dict(eps=-1.0), "eps"),
     (dict(lam=0.0), "lambda"), (dict(precision=7), "precision"), (dict(boundary=5), "boundary"),
