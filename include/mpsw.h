@@ -63,7 +63,8 @@ enum { MPSW_SEQUENTIAL = 0, MPSW_INTERLEAVED = 1 };            /* site order */
 enum { MPSW_RANK_EXACT = 0, MPSW_RANK_LEARNED = 1 };           /* truncation rank mode */
 
 typedef struct mpsw_config {
-  int n;              /* grid 2^n x 2^n, 1 <= n <= 12; K = 2n sites */
+  int n;              /* grid 2^n x 2^n, 1 <= n <= 11; K = 2n sites (the tallest QR of a
+                         rounding has 2^(n+1) rows, and a panel of it must fit in LDS) */
   int chi_max;        /* bond cap of every rounding, >= 1 */
   double eps;         /* relative singular-value cutoff, >= 0 */
   double lambda;      /* mesh ratio dt/dh of eq. 2, > 0 */

@@ -918,7 +918,7 @@ int create_group(const mpsw_config* cfgs, int nshots, void* stream, mpsw_state* 
   const mpsw_config& c0 = cfgs[0];
   for (int i = 0; i < nshots; ++i) {
     const mpsw_config& c = cfgs[i];
-    if (c.n < 1 || c.n > 12) return fail(MPSW_EINVAL, "n must be in [1, 12]");
+    if (c.n < 1 || c.n > 11) return fail(MPSW_EINVAL, "n must be in [1, 11]");
     if (c.chi_max < 1) return fail(MPSW_EINVAL, "chi_max must be >= 1");
     if (!(c.eps >= 0.0) || !std::isfinite(c.eps)) return fail(MPSW_EINVAL, "eps must be finite and >= 0");
     if (!(c.lambda > 0.0) || !std::isfinite(c.lambda)) return fail(MPSW_EINVAL, "lambda must be > 0");
@@ -1724,7 +1724,7 @@ int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, doubl
 // Host-side helper exported for tests: the fused Laplacian MPO cores
 // ([wl][wr][s'][s] per site, packed) and bonds (K+1) for a register of n bits.
 int mpsw_debug_laplacian_mpo(int n, int boundary, int ordering, int* bonds, double* cores, int64_t cap) {
-  if (n < 1 || n > 12 || !bonds) return fail(MPSW_EINVAL, "bad argument");
+  if (n < 1 || n > 11 || !bonds) return fail(MPSW_EINVAL, "bad argument");
   if (ordering != MPSW_SEQUENTIAL && ordering != MPSW_INTERLEAVED) return fail(MPSW_EINVAL, "unknown site order");
   LapMPO m = build_laplacian_mpo(n, boundary, ordering);
   std::copy(m.bonds.begin(), m.bonds.end(), bonds);

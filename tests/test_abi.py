@@ -77,7 +77,7 @@ def test_interleaved_order_is_validated(lib):
 
 
 @pytest.mark.parametrize("kw,field", [
-    (dict(n=0), "n"), (dict(n=13), "n"), (dict(chi_max=0), "chi"), (dict(eps=-1.0), "eps"),
+    (dict(n=0), "n"), (dict(n=12), "n"), (dict(chi_max=0), "chi"), (dict(eps=-1.0), "eps"),
     (dict(lam=0.0), "lambda"), (dict(precision=7), "precision"), (dict(boundary=5), "boundary"),
 ])
 def test_config_validation_before_device_work(lib, kw, field):
