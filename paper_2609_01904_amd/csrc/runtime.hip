@@ -508,11 +508,12 @@ size_t lds_limit() {
 }
 
 // Householder panel width for a QR whose row count is at most mcap: the panel
-// (mcap x bw doubles) lives in LDS.
+// ((mcap + 1) x bw doubles: one spare row for an odd leading dimension) lives
+// in LDS.
 int qr_panel(int64_t mcap) {
   const size_t lim = lds_limit() - 24576;   // static LDS of the kernel
   for (int bw = 16; bw >= 4; bw >>= 1)
-    if ((size_t)mcap * bw * 8 <= lim) return bw;
+    if ((size_t)(mcap + 1) * bw * 8 <= lim) return bw;
   return 0;
 }
 
