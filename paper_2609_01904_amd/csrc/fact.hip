@@ -181,29 +181,44 @@ template <int BW>
 __device__ void apply_wave(const double* Vl, int ldv, int mj, int bw, double* C, int64_t ldc, int bwc,
                            const double* __restrict__ T) {
   const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  // branch-free: every lane loads an in-range element, then selects
   auto vfull = [&](int rr, int p) -> double {
-    if (rr >= mj || p >= bw) return 0.0;
-    return (rr > p) ? Vl[rr + ldv * p] : ((rr == p) ? 1.0 : 0.0);
+    const double x = Vl[min(rr, mj - 1) + ldv * min(p, bw - 1)];
+    const bool in = rr < mj && p < bw;
+    const double y = (in && rr > p) ? x : 0.0;
+    return (in && rr == p) ? 1.0 : y;
   };
   const bool colok = li < bwc;
-  double* Cc = C + (int64_t)(colok ? li : 0) * ldc;
-  const int nchunk = (mj + 15) >> 4;
+  // global address space: its loads are counted apart from the LDS reads, so
+  // waiting for V does not wait for C
+  typedef __attribute__((address_space(1))) double gdouble;
+  gdouble* Cc = (gdouble*)(C + (int64_t)(colok ? li : 0) * ldc);   // column 0 stands in for idle lanes
+  const int nchunk = (mj + 15) >> 4, nfull = mj >> 4;
+  constexpr int UN = 2;   // chunks whose loads are in flight together
   // W = V^T C; acc[v] = W[lk + 4 v][li]
   mpsw_d4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int tt = 0; tt < nchunk; ++tt) {
-    const int rb = 16 * tt + 4 * lk;
-    double av[4], cv[4];
+  int tt = 0;
+  for (; tt + UN <= nfull; tt += UN) {
+    double cv[UN][4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) av[e] = vfull(rb + e, li);
-    if (colok && rb + 3 < mj) {   // four contiguous rows of this lane's column
+    for (int u = 0; u < UN; ++u)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) cv[e] = Cc[rb + e];
-    } else {
+      for (int e = 0; e < 4; ++e) cv[u][e] = Cc[16 * (tt + u) + 4 * lk + e];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) cv[e] = (colok && rb + e < mj) ? Cc[rb + e] : 0.0;
+    for (int u = 0; u < UN; ++u) {
+      const int rb = 16 * (tt + u) + 4 * lk;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(vfull(rb + e, li), colok ? cv[u][e] : 0.0, acc, 0, 0, 0);
     }
+  }
+  for (; tt < nchunk; ++tt) {
+    const int rb = 16 * tt + 4 * lk;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[e], cv[e], acc, 0, 0, 0);
+    for (int e = 0; e < 4; ++e) {
+      const double cv = (colok && rb + e < mj) ? Cc[rb + e] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(vfull(rb + e, li), cv, acc, 0, 0, 0);
+    }
   }
   // W2 = T^T W: the accumulator of W is the b operand of k-step v
   mpsw_d4 w2 = {0.0, 0.0, 0.0, 0.0};
@@ -213,23 +228,42 @@ __device__ void apply_wave(const double* Vl, int ldv, int mj, int bw, double* C,
     const double a = (sidx < BW && li < BW && sidx <= li && li < bw) ? T[sidx * BW + li] : 0.0;
     w2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, acc[kk], w2, 0, 0, 0);
   }
-  // C -= V W2 in 16-row tiles; A's row i is tile row 4 (i % 4) + i / 4
-  for (int tt = 0; tt < nchunk; ++tt) {
-    const int rb0 = 16 * tt;
+  // C -= V W2 in 16-row tiles; A's row i is tile row 4 (i % 4) + i / 4, so
+  // lane (li, lk) owns rows 4 lk .. 4 lk + 3 of the tile in column li
+  auto tile = [&](int rb0, const double (&cv)[4], bool full) {
     const int ra = rb0 + 4 * (li & 3) + (li >> 2);
     mpsw_d4 d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk)
       if (4 * kk < bw) d = __builtin_amdgcn_mfma_f64_16x16x4f64(vfull(ra, 4 * kk + lk), w2[kk], d, 0, 0, 0);
     const int rw = rb0 + 4 * lk;
-    if (colok && rw + 3 < mj) {
+    if (full) {
+      if (colok) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Cc[rw + v] -= d[v];
+        for (int v = 0; v < 4; ++v) Cc[rw + v] = cv[v] - d[v];
+      }
     } else {
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        if (colok && rw + v < mj) Cc[rw + v] -= d[v];
+        if (colok && rw + v < mj) Cc[rw + v] = cv[v] - d[v];
     }
+  };
+  tt = 0;
+  for (; tt + UN <= nfull; tt += UN) {
+    double cv[UN][4];
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) cv[u][e] = Cc[16 * (tt + u) + 4 * lk + e];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) tile(16 * (tt + u), cv[u], true);
+  }
+  for (; tt < nchunk; ++tt) {
+    const int rw = 16 * tt + 4 * lk;
+    double cv[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) cv[e] = (colok && rw + e < mj) ? Cc[rw + e] : 0.0;
+    tile(16 * tt, cv, false);
   }
 }
 
