@@ -4,7 +4,10 @@ u^{k+1}_{i,j} = 2 u^k_{i,j} - u^{k-1}_{i,j}
                + lambda^2 c^2_{i,j} (u^k_{i+1,j} + u^k_{i-1,j} + u^k_{i,j+1} + u^k_{i,j-1} - 4 u^k_{i,j})
 
 with lambda = dt/dh.  Arrays are u[x, z] (x = i horizontal, z = j depth).  The
-boundary is not stated in the paper; two readings are offered:
+same update in three dimensions, u[x, y, z] with the seven-point sum
+(- 6 u), is the 3D form the paper anticipates for its MPS solver; every
+function here takes fields of either rank.  The boundary is not stated in the
+paper; two readings are offered:
 
 * "periodic": indices wrap mod 2^n (the cyclic shifts of Sec. 3.1 / Sec. 4.2);
 * "open":     values outside the grid are zero (the terminal shift core of
@@ -15,15 +18,18 @@ A point source adds s_k at (ix, iz) of u^{k+1}.
 import numpy as np
 
 
+def _along(axis, ndim, sl):
+    idx = [slice(None)] * ndim
+    idx[axis] = sl
+    return tuple(idx)
+
+
 def shift_plus(u, axis, boundary):
     """(S^+ u)[x] = u[x-1]: the amplitude of |x> moves to |x+1> (eq. 5)."""
     if boundary == "periodic":
         return np.roll(u, 1, axis=axis)
     out = np.zeros_like(u)
-    if axis == 0:
-        out[1:, :] = u[:-1, :]
-    else:
-        out[:, 1:] = u[:, :-1]
+    out[_along(axis, u.ndim, slice(1, None))] = u[_along(axis, u.ndim, slice(None, -1))]
     return out
 
 
@@ -32,24 +38,24 @@ def shift_minus(u, axis, boundary):
     if boundary == "periodic":
         return np.roll(u, -1, axis=axis)
     out = np.zeros_like(u)
-    if axis == 0:
-        out[:-1, :] = u[1:, :]
-    else:
-        out[:, :-1] = u[:, 1:]
+    out[_along(axis, u.ndim, slice(None, -1))] = u[_along(axis, u.ndim, slice(1, None))]
     return out
 
 
 def laplacian(u, boundary="periodic"):
-    """Five-point sum of eq. 2 (second row), in grid units (no 1/dh^2)."""
-    return (shift_plus(u, 0, boundary) + shift_minus(u, 0, boundary)
-            + shift_plus(u, 1, boundary) + shift_minus(u, 1, boundary) - 4.0 * u)
+    """Five-point sum of eq. 2 (second row), in grid units (no 1/dh^2); the
+    seven-point sum for a three-dimensional field."""
+    out = shift_plus(u, 0, boundary) + shift_minus(u, 0, boundary)
+    for ax in range(1, u.ndim):
+        out = out + shift_plus(u, ax, boundary) + shift_minus(u, ax, boundary)
+    return out - 2.0 * u.ndim * u
 
 
 def fdtd_step(u, u_prev, c2, lam, s=0.0, src=None, boundary="periodic"):
     """One leapfrog step of eq. 2; returns u^{k+1}."""
     u_next = 2.0 * u - u_prev + (lam * lam) * c2 * laplacian(u, boundary)
     if src is not None and s != 0.0:
-        u_next[src[0], src[1]] += s
+        u_next[tuple(src)] += s
     return u_next
 
 

@@ -12,6 +12,10 @@ sites x_{n-1}, z_{n-1}, x_{n-2}, z_{n-2}, ..., x_0, z_0.  It represents the same
 fields (the paper fixes the register order of eq. 3; the interleaved order is
 the usual alternative for quantics grids and changes only the ranks needed).
 
+Three-dimensional fields u[x, y, z] use K = 3n sites in the same way (three
+registers, sequential or interleaved); the functions taking ``ndim`` default
+to the paper's two dimensions.
+
 An MPO core has shape (w_left, w_right, 2, 2) indexed [a_l, a_r, s_out, s_in].
 """
 import numpy as np
@@ -29,30 +33,32 @@ SIGMA_MINUS = np.array([[0.0, 1.0], [0.0, 0.0]])  # |0><1|
 ORDERINGS = ("sequential", "interleaved")
 
 
-def site_bits(n, ordering="sequential"):
-    """(register, bit) of each of the K = 2n sites; register 0 is x, 1 is z and
-    bit is the significance (n-1 = most significant)."""
+def site_bits(n, ordering="sequential", ndim=2):
+    """(register, bit) of each of the K = ndim n sites; registers 0.. are the
+    axes (x, z in two dimensions; x, y, z in three) and bit is the significance
+    (n-1 = most significant)."""
     if ordering == "sequential":
-        return [(0, n - 1 - m) for m in range(n)] + [(1, n - 1 - m) for m in range(n)]
+        return [(r, n - 1 - m) for r in range(ndim) for m in range(n)]
     if ordering == "interleaved":
-        return [(r, n - 1 - m) for m in range(n) for r in (0, 1)]
+        return [(r, n - 1 - m) for m in range(n) for r in range(ndim)]
     raise ValueError(ordering)
 
 
 def to_sites(u, ordering="sequential"):
-    """Flat tensor over the sites (C order over [2]*K) of the field u[x, z]."""
+    """Flat tensor over the sites (C order over [2]*K) of the field u[x, z]
+    (or u[x, y, z])."""
     u = np.asarray(u)
     n = int(u.shape[0]).bit_length() - 1
-    t = u.reshape([2] * (2 * n))          # axes x_{n-1}..x_0, z_{n-1}..z_0
-    axes = [r * n + (n - 1 - b) for r, b in site_bits(n, ordering)]
+    t = u.reshape([2] * (u.ndim * n))     # axes x_{n-1}..x_0, then the next register
+    axes = [r * n + (n - 1 - b) for r, b in site_bits(n, ordering, u.ndim)]
     return np.transpose(t, axes).reshape(-1)
 
 
-def from_sites(v, n, ordering="sequential"):
-    """Inverse of to_sites: the field u[x, z] (2^n x 2^n) of a site-order tensor."""
-    axes = [r * n + (n - 1 - b) for r, b in site_bits(n, ordering)]
-    t = np.asarray(v).reshape([2] * (2 * n))
-    return np.transpose(t, np.argsort(axes)).reshape(1 << n, 1 << n)
+def from_sites(v, n, ordering="sequential", ndim=2):
+    """Inverse of to_sites: the field (2^n per axis) of a site-order tensor."""
+    axes = [r * n + (n - 1 - b) for r, b in site_bits(n, ordering, ndim)]
+    t = np.asarray(v).reshape([2] * (ndim * n))
+    return np.transpose(t, np.argsort(axes)).reshape((1 << n,) * ndim)
 
 
 def to_dense(cores):
@@ -154,7 +160,12 @@ def product_state(bits):
 def point_state(n, ix, iz, ordering="sequential"):
     """e_(ix, iz): sites are the bits of ix (MSB first) then of iz (eq. 3), or
     the two interleaved."""
-    return product_state([((ix, iz)[r] >> b) & 1 for r, b in site_bits(n, ordering)])
+    return point_state_nd(n, (ix, iz), ordering)
+
+
+def point_state_nd(n, coords, ordering="sequential"):
+    """The basis field at grid point coords (one index per axis)."""
+    return product_state([(coords[r] >> b) & 1 for r, b in site_bits(n, ordering, len(coords))])
 
 
 def scale(cores, alpha):
@@ -262,25 +273,29 @@ def passthrough_mpo_core(r):
 
 
 def shift_mpo_2d(n, axis, direction, boundary="periodic", ordering="sequential"):
-    """S_x^{+-} = S^{+-} (x) I (eq. 14) and S_z^{+-} = I (x) S^{+-} (eq. 15).
+    """S_x^{+-} = S^{+-} (x) I (eq. 14) and S_z^{+-} = I (x) S^{+-} (eq. 15)."""
+    return shift_mpo_nd(n, axis, direction, boundary, ordering, 2)
+
+
+def shift_mpo_nd(n, axis, direction, boundary="periodic", ordering="sequential", ndim=2):
+    """The shift along one axis as an MPO over all K = ndim n sites: the
+    register's shift cores, identities elsewhere.
 
     In the interleaved order the register's cores alternate with identity cores
-    of the other register; a site that lies between two cores of the shifted
+    of the other registers; a site that lies between two cores of the shifted
     register passes the carry bond through unchanged.
     """
     s = shift_mpo_1d(n, direction, boundary)
     if ordering == "sequential":
-        if axis == 0:
-            return s + identity_mpo(n)
-        return identity_mpo(n) + s
+        return identity_mpo(n * axis) + s + identity_mpo(n * (ndim - 1 - axis))
     out = []
     for m in range(n):
-        for r in (0, 1):
+        for r in range(ndim):
             if r == axis:
                 out.append(s[m])
-            elif r > axis:      # z site after x core m: the carry into x core m
+            elif r > axis:      # a site after core m: the carry into core m
                 out.append(passthrough_mpo_core(s[m].shape[1]))
-            else:               # x site before z core m: the carry out of z core m
+            else:               # a site before core m: the carry out of core m
                 out.append(passthrough_mpo_core(s[m].shape[0]))
     return out
 
@@ -296,13 +311,14 @@ def mpo_to_dense(W):
     return M[0]
 
 
-def laplacian_mps(cores, n, boundary="periodic", ordering="sequential"):
+def laplacian_mps(cores, n, boundary="periodic", ordering="sequential", ndim=2):
     """L psi with L = S_x+ + S_x- + S_z+ + S_z- - 4 I (eqs. 6 and 16) as one MPS.
 
     Each shift MPO is applied separately and the five terms are added as a
-    direct sum (bond 2chi+2chi+chi+chi+chi inside a register).
+    direct sum (bond 2chi+2chi+chi+chi+chi inside a register).  With ndim = 3
+    the six shifts and -6 I give the seven-point operator.
     """
-    terms = [apply_mpo(shift_mpo_2d(n, ax, d, boundary, ordering), cores)
-             for ax in (0, 1) for d in (+1, -1)]
+    terms = [apply_mpo(shift_mpo_nd(n, ax, d, boundary, ordering, ndim), cores)
+             for ax in range(ndim) for d in (+1, -1)]
     terms.append(cores)
-    return direct_sum(terms, [1.0, 1.0, 1.0, 1.0, -4.0])
+    return direct_sum(terms, [1.0] * (2 * ndim) + [-2.0 * ndim])

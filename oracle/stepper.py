@@ -4,7 +4,9 @@ psi^{k+1} = 2 psi^k - psi^{k-1} + lambda^2 C^2 (S_x+ + S_x- + S_z+ + S_z- - 4 I)
 
 with a compression after each operator application (Sec. 4.3).  Both steppers
 take the site order (sequential registers of eq. 3, or interleaved bits) as a
-parameter; fields given to and returned by them are always u[x, z].  Reading used
+parameter; fields given to and returned by them are always u[x, z], or
+u[x, y, z] for the three-dimensional form (MPSStepper's ndim = 3; the dense
+stepper takes the rank of its c^2 array).  Reading used
 throughout (three roundings per step, "S1"):
 
     y        = round(L psi^k)
@@ -31,14 +33,14 @@ from . import fdtd as F
 
 def c2_mps(c2_dense, n, eps_c, ordering="sequential"):
     """The c^2 diagonal operator as an MPS (its diagonal), TT-SVD with cutoff eps_c."""
-    return M.tt_svd(M.to_sites(np.asarray(c2_dense, dtype=np.float64), ordering), 2 * n, eps_c,
-                    chi_max=1 << 30)
+    c2_dense = np.asarray(c2_dense, dtype=np.float64)
+    return M.tt_svd(M.to_sites(c2_dense, ordering), c2_dense.ndim * n, eps_c, chi_max=1 << 30)
 
 
 class MPSStepper:
     def __init__(self, n, lam, eps, chi_max, c2_cores, boundary="periodic",
-                 src=None, wavelet=None, ordering="sequential"):
-        self.n, self.K = n, 2 * n
+                 src=None, wavelet=None, ordering="sequential", ndim=2):
+        self.n, self.K, self.ndim = n, ndim * n, ndim
         self.lam, self.eps, self.chi = lam, eps, chi_max
         self.c2 = c2_cores
         self.boundary = boundary
@@ -66,12 +68,12 @@ class MPSStepper:
         s_k = 0.0
         if self.wavelet is not None and self.k < len(self.wavelet):
             s_k = float(self.wavelet[self.k])
-        y = self._round(M.laplacian_mps(self.psi, self.n, self.boundary, self.ordering), 0)
+        y = self._round(M.laplacian_mps(self.psi, self.n, self.boundary, self.ordering, self.ndim), 0)
         w = self._round(M.hadamard(self.c2, y), 1)
         terms = [self.psi, self.psi_prev, w]
         coeffs = [2.0, -1.0, self.lam * self.lam]
         if self.src is not None:
-            terms.append(M.point_state(self.n, self.src[0], self.src[1], self.ordering))
+            terms.append(M.point_state_nd(self.n, tuple(self.src), self.ordering))
             coeffs.append(s_k)
         nxt = self._round(M.direct_sum(terms, coeffs), 2)
         self.psi_prev, self.psi = self.psi, nxt
@@ -79,7 +81,7 @@ class MPSStepper:
 
     def dense(self, which=0):
         return M.from_sites(M.to_dense(self.psi if which == 0 else self.psi_prev), self.n,
-                            self.ordering)
+                            self.ordering, self.ndim)
 
 
 class DenseStepper:
@@ -87,7 +89,9 @@ class DenseStepper:
 
     def __init__(self, n, lam, eps, chi_max, c2_dense, boundary="periodic",
                  src=None, wavelet=None, ordering="sequential"):
-        self.n, self.K = n, 2 * n
+        c2_dense = np.asarray(c2_dense, dtype=np.float64)
+        self.ndim = c2_dense.ndim
+        self.n, self.K = n, self.ndim * n
         self.N = 1 << n
         self.lam, self.eps, self.chi = lam, eps, chi_max
         self.c2 = np.asarray(c2_dense, dtype=np.float64)
@@ -96,8 +100,8 @@ class DenseStepper:
         self.src = src
         self.wavelet = wavelet
         self.k = 0
-        self.u = np.zeros((self.N, self.N))
-        self.u_prev = np.zeros((self.N, self.N))
+        self.u = np.zeros((self.N,) * self.ndim)
+        self.u_prev = np.zeros((self.N,) * self.ndim)
         self.log = []
         self.ranks = []          # per step: (bonds of y, bonds of w, bonds of psi)
 
@@ -106,7 +110,7 @@ class DenseStepper:
         cores = M.tt_svd(M.to_sites(t, self.ordering), self.K, self.eps, self.chi, log)
         for site, s, r in log:
             self.log.append((self.k, which, site, s, r))
-        return M.from_sites(M.to_dense(cores), self.n, self.ordering), M.bonds_of(cores)
+        return M.from_sites(M.to_dense(cores), self.n, self.ordering, self.ndim), M.bonds_of(cores)
 
     def set_fields(self, u_prev, u):
         self.u_prev, _ = self._round(np.asarray(u_prev, dtype=np.float64), -1)
@@ -120,7 +124,7 @@ class DenseStepper:
         w, bw = self._round(self.c2 * y, 1)
         t = 2.0 * self.u - self.u_prev + (self.lam * self.lam) * w
         if self.src is not None:
-            t[self.src[0], self.src[1]] += s_k
+            t[tuple(self.src)] += s_k
         nxt, bp = self._round(t, 2)
         self.ranks.append((by, bw, bp))
         self.u_prev, self.u = self.u, nxt
