@@ -24,7 +24,8 @@
  *   - return 0 (MPSW_OK) on success, a negative MPSW_E* code on failure; the
  *     message of the last failure on the calling thread is mpsw_last_error();
  *   - host arrays passed in are borrowed for the duration of the call only;
- *   - dense fields are float64, 4^n entries, flat index x * 2^n + z;
+ *   - dense fields are float64, 4^n entries, flat index x * 2^n + z (three-
+ *     dimensional states: 8^n entries, flat index (x * 2^n + y) * 2^n + z);
  *   - all device work of a state is ordered on the HIP stream given at
  *     creation (NULL = the default stream); entry points that return data to
  *     the host synchronise that stream;
@@ -47,7 +48,7 @@ enum {
   MPSW_ENOMEM = -2,     /* device allocation failed or a size exceeds the workspace */
   MPSW_EHIP = -3,       /* a HIP runtime call failed */
   MPSW_ESTATE = -4,     /* call out of order (e.g. step before set_velocity) */
-  MPSW_ECFL = -5,       /* lambda^2 * max(c^2) * 2 > 1: the scheme is unstable */
+  MPSW_ECFL = -5,       /* lambda^2 * max(c^2) * ndim > 1: the scheme is unstable */
   MPSW_ENONFINITE = -6  /* a non-finite value was produced (detected at a sync) */
 };
 
@@ -64,7 +65,7 @@ enum { MPSW_RANK_EXACT = 0, MPSW_RANK_LEARNED = 1 };           /* truncation ran
 
 typedef struct mpsw_config {
   int n;              /* grid 2^n x 2^n, 1 <= n <= 11; K = 2n sites (the tallest QR of a
-                         rounding has 2^(n+1) rows, and a panel of it must fit in LDS) */
+                         rounding has 2^(K/2+1) rows, and a panel of it must fit in LDS) */
   int chi_max;        /* bond cap of every rounding, >= 1 */
   double eps;         /* relative singular-value cutoff, >= 0 */
   double lambda;      /* mesh ratio dt/dh of eq. 2, > 0 */
@@ -76,6 +77,9 @@ typedef struct mpsw_config {
                          (x_{n-1} z_{n-1} ... x_0 z_0).  Dense fields passed in and out
                          are u[x, z] in either order; MPS cores given to
                          mpsw_set_velocity_mpo are in the state's site order */
+  int ndim;           /* 2 (0 means 2): the paper's u[x, z], K = 2n sites; or 3: u[x, y, z]
+                         on a 2^n cube, K = 3n sites (registers x, y, z), the seven-point
+                         Laplacian with -6I, n <= 7 */
 } mpsw_config;
 
 typedef struct mpsw_state_s* mpsw_state;
@@ -103,7 +107,7 @@ int mpsw_create_state(const mpsw_config* cfg, void* hip_stream, mpsw_state* out)
  * rank mode and site order must agree).  Steps of a batch advance all shots together.  Errors as above. */
 int mpsw_create_batch(const mpsw_config* cfgs, int nshots, void* hip_stream, mpsw_state* out);
 
-/* Set c^2 from its dense field (host, 4^n float64, all > 0).  The diagonal
+/* Set c^2 from its dense field (host, 4^n or 8^n float64, all > 0).  The diagonal
  * c^2 operator is built on the device as the right-to-left truncated TT-SVD of
  * c^2 (taken in the state's site order) with relative cutoff eps_c and no
  * bond cap (Sec. 4.3: the velocity field encoded as a diagonal MPO).  Errors: EINVAL (non-positive or
@@ -120,8 +124,11 @@ int mpsw_set_velocity_mpo(mpsw_state st, const int* bonds, const double* cores);
 /* Point source for shot `shot` at grid point (ix, iz): step j (counted from
  * creation, or from the shot's last mpsw_set_fields) adds wavelet[j] *
  * e_(ix,iz) to psi^{j+1}; steps j >= nt add nothing.  The host array is
- * copied.  Errors: EINVAL. */
+ * copied.  Errors: EINVAL (also for a three-dimensional state). */
 int mpsw_set_source(mpsw_state st, int shot, int ix, int iz, int nt, const double* wavelet);
+/* The same at grid point (ix, iy, iz) of a three-dimensional state.
+ * Errors: EINVAL (also for a two-dimensional state). */
+int mpsw_set_source_3d(mpsw_state st, int shot, int ix, int iy, int iz, int nt, const double* wavelet);
 
 /* Initial fields of shot `shot` from dense host arrays (NULL = zero); each is
  * stored as its right-to-left TT-SVD with the shot's (eps, chi_max).
@@ -152,7 +159,7 @@ int mpsw_group_step(mpsw_group g, int k);
 int mpsw_group_destroy(mpsw_group g);
 
 /* Write the dense field of shot `shot` (which = 0: u^k, 1: u^{k-1}) into the
- * caller's buffer of 4^n float64 (host memory, or device memory if
+ * caller's buffer of 4^n (8^n) float64 (host memory, or device memory if
  * out_is_device != 0).  Synchronises the stream; reports ENONFINITE if any
  * entry is not finite.  Errors: EINVAL, EHIP, ENONFINITE. */
 int mpsw_to_dense(mpsw_state st, int shot, int which, double* out, int out_is_device);
@@ -245,12 +252,13 @@ int mpsw_mlp_forward(const float* X, int m, const float* w, float* out);
 
 /* Host-only helper (no device work), used by the CPU tests: the fused
  * Laplacian MPO S_x+ + S_x- + S_z+ + S_z- - 4I (eqs. 6 and 16) the library
- * applies, for an n-bit register pair, a boundary and a site order
- * (MPSW_SEQUENTIAL or MPSW_INTERLEAVED).  Writes K+1 bonds into
+ * applies, for n-bit registers, a boundary, a site order (MPSW_SEQUENTIAL or
+ * MPSW_INTERLEAVED) and ndim = 2 or 3 registers (three: the six shifts and
+ * -6I).  Writes K+1 bonds into
  * `bonds` and, if `cores` is not NULL, the cores packed site after site, core k
  * of shape [w_k][w_{k+1}][s_out][s_in] row-major (at most `cap` doubles).
  * Returns the total number of core entries (>= 0) or a negative error code. */
-int mpsw_debug_laplacian_mpo(int n, int boundary, int ordering, int* bonds, double* cores, int64_t cap);
+int mpsw_debug_laplacian_mpo(int n, int boundary, int ordering, int ndim, int* bonds, double* cores, int64_t cap);
 
 /* Test helper (device work on the current device, default stream): runs the
  * factorisation kernels of a rounding on one host matrix A (m x n row-major).

@@ -387,7 +387,7 @@ __global__ void k_prepare(const DevCtx* __restrict__ cp, OpArgs a) {
   const int shot = blockIdx.x * blockDim.x + threadIdx.x;
   if (shot >= c.B) return;
   int* dm = shot_dims(c, shot);
-  const int K = c.K, n = c.n;
+  const int K = c.K, n = c.half;   // the Kronecker rounding's sweeps meet at site n
   const int* bonds = dm + DL::bonds;
   auto B = [&](int slot, int k) { return bonds[slot * (MPSW_MAXK + 1) + k]; };
   for (int k = 0; k <= K; ++k) {
@@ -485,10 +485,13 @@ __global__ void k_pack_sum(const DevCtx* __restrict__ cp, OpArgs a) {
   // the step index lives on the device, so a captured step replays correctly
   const int stp = dm[DL::step];
   if (stp >= 0 && stp < nt && stp < c.nt_max) ssrc = c.wavelet[(int64_t)shot * c.nt_max + stp];
-  const int ix = dm[DL::src_ix], iz = dm[DL::src_iz];
-  int bit;
-  if (c.ordering == MPSW_INTERLEAVED) bit = (((k & 1) ? iz : ix) >> (n - 1 - (k >> 1))) & 1;
-  else bit = (k < n) ? ((ix >> (n - 1 - k)) & 1) : ((iz >> (K - 1 - k)) & 1);
+  // site k holds bit b of axis r: registers in order (sequential) or bits of
+  // equal significance side by side (interleaved); the last axis is z
+  const int nd = c.ndim;
+  const int r = (c.ordering == MPSW_INTERLEAVED) ? k % nd : k / n;
+  const int b = (c.ordering == MPSW_INTERLEAVED) ? n - 1 - k / nd : n - 1 - k % n;
+  const int coord = (r == 0) ? dm[DL::src_ix] : (r == nd - 1) ? dm[DL::src_iz] : dm[DL::src_iy];
+  const int bit = (coord >> b) & 1;
   const double coef[3] = {2.0, -1.0, c.lam2};
   double* out = shot_eng(c, shot) + c.L.off_in[k];
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {

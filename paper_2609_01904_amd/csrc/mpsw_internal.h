@@ -13,7 +13,7 @@
 
 #include "../../include/mpsw.h"
 
-#define MPSW_MAXK 24          // n <= 12
+#define MPSW_MAXK 24          // K = ndim n <= 22 is what the LDS allows
 #define MPSW_NSLOT 5          // MPS buffers: 0..2 psi rotation, 3 = y, 4 = w
 #define MPSW_SLOT_Y 3
 #define MPSW_SLOT_W 4
@@ -67,7 +67,8 @@ struct ShotDimsLayout {
   // with every further rejection; an accepted sketch resets it
   static constexpr int rrf_skip = fallbacks + 1;            // [3][MAXK]
   static constexpr int rrf_back = rrf_skip + 3 * MPSW_MAXK; // [3][MAXK]
-  static constexpr int size = rrf_back + 3 * MPSW_MAXK;
+  static constexpr int src_iy = rrf_back + 3 * MPSW_MAXK;   // source y (three-dimensional states)
+  static constexpr int size = src_iy + 1;
 };
 
 // Per-shot double block layout (offsets in doubles, separate small array).
@@ -116,7 +117,9 @@ struct EngineLayout {
 };
 
 struct DevCtx {
-  int K, n, B;
+  int K, n, B;                                   // sites, bits per axis, shots
+  int ndim;                                      // axes (2 or 3): K = ndim n
+  int half;                                      // meeting site of the Kronecker rounding (K / 2)
   int boundary;
   int ordering;                                  // MPSW_SEQUENTIAL or MPSW_INTERLEAVED
   double lam2;

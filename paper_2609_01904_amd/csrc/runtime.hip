@@ -50,100 +50,113 @@ int set_last_error(int code, const char* msg) { return fail(code, msg); }
 namespace {
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
-// Dense fields cross the boundary as u[x, z] (flat x 2^n + z).  In the
-// interleaved site order the flat site index holds x_m at bit 2m+1 and z_m at
-// bit 2m; these two copies move a field between the two layouts.
-std::vector<int64_t> spread_bits(int n) {
+// Dense fields cross the boundary as u[x, z] (flat x 2^n + z), or u[x, y, z].
+// In the sequential site order that flat index is the site index; in the
+// interleaved order bit m of axis r sits at bit ndim m + (ndim - 1 - r) of the
+// site index.  These two copies move a field between the two layouts.
+std::vector<int64_t> spread_bits(int n, int ndim) {
   std::vector<int64_t> sp((size_t)1 << n, 0);
   for (int64_t v = 0; v < ((int64_t)1 << n); ++v)
-    for (int m = 0; m < n; ++m) sp[v] |= ((v >> m) & 1) << (2 * m);
+    for (int m = 0; m < n; ++m) sp[v] |= ((v >> m) & 1) << (ndim * m);
   return sp;
 }
-void field_to_sites(const double* u, int n, double* t) {
-  const auto sp = spread_bits(n);
-  const int64_t N = (int64_t)1 << n;
-  for (int64_t x = 0; x < N; ++x)
-    for (int64_t z = 0; z < N; ++z) t[(sp[x] << 1) | sp[z]] = u[x * N + z];
+int64_t site_index(const std::vector<int64_t>& sp, int n, int ndim, int64_t flat) {
+  const int64_t mask = ((int64_t)1 << n) - 1;
+  int64_t idx = 0;
+  for (int r = 0; r < ndim; ++r) idx |= sp[(flat >> (n * (ndim - 1 - r))) & mask] << (ndim - 1 - r);
+  return idx;
 }
-void sites_to_field(const double* t, int n, double* u) {
-  const auto sp = spread_bits(n);
-  const int64_t N = (int64_t)1 << n;
-  for (int64_t x = 0; x < N; ++x)
-    for (int64_t z = 0; z < N; ++z) u[x * N + z] = t[(sp[x] << 1) | sp[z]];
+void field_to_sites(const double* u, int n, int ndim, double* t) {
+  const auto sp = spread_bits(n, ndim);
+  const int64_t total = (int64_t)1 << (n * ndim);
+  for (int64_t f = 0; f < total; ++f) t[site_index(sp, n, ndim, f)] = u[f];
+}
+void sites_to_field(const double* t, int n, int ndim, double* u) {
+  const auto sp = spread_bits(n, ndim);
+  const int64_t total = (int64_t)1 << (n * ndim);
+  for (int64_t f = 0; f < total; ++f) u[f] = t[site_index(sp, n, ndim, f)];
 }
 
 // ---------------------------------------------------------------------------
-// The fused Laplacian MPO S_x+ + S_x- + S_z+ + S_z- - 4I (eqs. 6, 16) in site
-// order: x bits MSB first then z bits (eq. 3), or the two interleaved.  It is
-// a finite automaton read from the last site to the first; the bond carries
-// what the sites to the right did: P (no shift yet: the x register will
-// shift), CX / BX (carry of an S+ / borrow of an S- of the x register still
-// pending), CZ / BZ (the same for z), D (shift finished, or the -4I term).
-// The z shift starts at the last site (its least significant bit); the x shift
-// starts where P meets the first x site, its least significant bit.  A site
-// of one register passes the other register's pending carry on unchanged.  A
-// pending carry at a register's top bit wraps (periodic) or is dropped (open,
-// the terminal core of eq. 11 as printed).  States that no path from both
-// ends reaches are pruned: bonds 3 inside the x register, 2 at the x|z cut
-// and 4 inside the z register in the sequential order; at most 5 in the
-// interleaved one.
+// The fused Laplacian MPO (eqs. 6, 16: the four shifts and -4I; in three
+// dimensions the six shifts and -6I) in site order: the registers x, z (or
+// x, y, z) one after the other, MSB first (eq. 3), or their bits interleaved.
+// It is a finite automaton read from the last site to the first; the bond
+// carries what the sites to the right did: P (no shift yet), the carry of an
+// S+ or the borrow of an S- still pending in register r (C_r, B_r), D (shift
+// finished, or the -2 ndim I term).  The last register's shift enters at the
+// right end (the last site is its least significant bit); P passes every site
+// and may start the shift of another register at that register's least
+// significant bit.  A site passes the other registers' pending carries on
+// unchanged.  A pending carry at a register's top bit wraps (periodic) or is
+// dropped (open, the terminal core of eq. 11 as printed).  States that no
+// path from both ends reaches are pruned: in two dimensions bonds 3 inside
+// the x register, 2 at the x|z cut and 4 inside the z register (sequential),
+// at most 5 interleaved.
 // ---------------------------------------------------------------------------
 struct LapMPO {
   std::vector<int> bonds;                  // K+1
   std::vector<std::vector<double>> cores;  // [wl][wr][2][2]
 };
 
-LapMPO build_laplacian_mpo(int n, int boundary, int ordering) {
-  const int K = 2 * n;
-  enum { P = 0, CX = 1, BX = 2, CZ = 3, BZ = 4, D = 5, NS = 6 };
+LapMPO build_laplacian_mpo(int n, int boundary, int ordering, int ndim) {
+  const int K = ndim * n;
+  // states: P = 0, C_r = 1 + 2r, B_r = 2 + 2r, D = NS - 1
+  const int NS = 2 + 2 * ndim, P = 0, D = NS - 1;
   const double I2[2][2] = {{1, 0}, {0, 1}};
   const double SP[2][2] = {{0, 0}, {1, 0}};  // |1><0|
   const double SM[2][2] = {{0, 1}, {0, 0}};  // |0><1|
   const bool periodic = boundary == MPSW_PERIODIC;
   const bool il = ordering == MPSW_INTERLEAVED;
-  auto zsite = [&](int k) { return il ? (k & 1) == 1 : k >= n; };
-  const int zmsb = il ? 1 : n;   // site of the most significant z bit
+  auto reg = [&](int k) { return il ? k % ndim : k / n; };
+  auto bit = [&](int k) { return il ? n - 1 - k / ndim : n - 1 - k % n; };
   // T[k][out][in][s'][s]
-  std::vector<std::vector<double>> T(K, std::vector<double>(NS * NS * 4, 0.0));
+  std::vector<std::vector<double>> T(K, std::vector<double>((size_t)NS * NS * 4, 0.0));
   auto add = [&](int k, int out, int in, const double (*op)[2]) {
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) T[k][((out * NS + in) * 2 + a) * 2 + b] += op[a][b];
   };
   for (int k = 0; k < K; ++k) {
-    const bool z = zsite(k);
-    const int C = z ? CZ : CX, Bs = z ? BZ : BX;    // this site's register
-    const int Co = z ? CX : CZ, Bo = z ? BX : BZ;   // the other register
+    const int r = reg(k);
     add(k, D, D, I2);
-    add(k, C, C, SM);    // bit 1 -> 0, carry moves on
-    add(k, D, C, SP);    // bit 0 -> 1, carry absorbed
-    add(k, Bs, Bs, SP);  // bit 0 -> 1, borrow moves on
-    add(k, D, Bs, SM);   // bit 1 -> 0, borrow absorbed
-    add(k, Co, Co, I2);  // the other register's carry and borrow pass
-    add(k, Bo, Bo, I2);
-    if (z) {
-      add(k, P, P, I2);
-    } else {
+    add(k, P, P, I2);
+    for (int q = 0; q < ndim; ++q) {
+      const int C = 1 + 2 * q, Bs = 2 + 2 * q;
+      if (q == r) {
+        add(k, C, C, SM);    // bit 1 -> 0, carry moves on
+        add(k, D, C, SP);    // bit 0 -> 1, carry absorbed
+        add(k, Bs, Bs, SP);  // bit 0 -> 1, borrow moves on
+        add(k, D, Bs, SM);   // bit 1 -> 0, borrow absorbed
+      } else {               // another register's carry and borrow pass
+        add(k, C, C, I2);
+        add(k, Bs, Bs, I2);
+      }
+    }
+    if (bit(k) == 0 && r < ndim - 1) {   // P starts this register's shift here
       add(k, D, P, SP);
       add(k, D, P, SM);
-      add(k, CX, P, SM);
-      add(k, BX, P, SP);
+      add(k, 1 + 2 * r, P, SM);
+      add(k, 2 + 2 * r, P, SP);
     }
-    if (k == zmsb) {  // most significant z bit: a pending carry/borrow wraps or is dropped
+    if (bit(k) == n - 1) {   // top bit: a pending carry/borrow wraps or is dropped
+      const int C = 1 + 2 * r, Bs = 2 + 2 * r;
       for (int in = 0; in < NS; ++in)
         for (int e = 0; e < 4; ++e) {
-          double& c = T[k][(CZ * NS + in) * 4 + e];
-          double& b = T[k][(BZ * NS + in) * 4 + e];
-          if (periodic) T[k][(D * NS + in) * 4 + e] += c + b;
-          c = 0.0;
-          b = 0.0;
+          double& cv = T[k][((size_t)C * NS + in) * 4 + e];
+          double& bv = T[k][((size_t)Bs * NS + in) * 4 + e];
+          if (periodic) T[k][((size_t)D * NS + in) * 4 + e] += cv + bv;
+          cv = 0.0;
+          bv = 0.0;
         }
     }
   }
-  // the x register's top bit is site 0: its pending carry leaves through the
-  // left end (kept when periodic); the z shift enters at the right end
-  double left[NS] = {0.0, 0.0, 0.0, 0.0, 0.0, 1.0};
-  left[CX] = left[BX] = periodic ? 1.0 : 0.0;
-  double right[NS] = {1.0, 0.0, 0.0, 1.0, 1.0, -4.0};
+  // the left end keeps the finished terms; the last register's shift and the
+  // -2 ndim I term enter at the right end
+  std::vector<double> left(NS, 0.0), right(NS, 0.0);
+  left[D] = 1.0;
+  right[P] = 1.0;
+  right[1 + 2 * (ndim - 1)] = right[2 + 2 * (ndim - 1)] = 1.0;
+  right[D] = -2.0 * ndim;
   // dense cores with bonds 1, NS, ..., NS, 1
   std::vector<int> wl(K), wr(K);
   std::vector<std::vector<double>> W(K);
@@ -226,7 +239,7 @@ SweepCaps sweep_caps(const std::vector<int64_t>& rin, int K, int64_t chi) {
 }
 
 struct Plan {
-  int K, n;
+  int K, half;   // sites; where the two sweeps of the Kronecker rounding meet
   std::vector<SweepCaps> sw;   // roundings handled by this engine
   std::vector<int64_t> Rmax;   // state bond caps (y feeding the Kronecker rounding)
   std::vector<int> D;          // c^2 bonds (empty when no Kronecker rounding)
@@ -241,7 +254,7 @@ void add64(int64_t& off, int64_t& field_off, int64_t cap) {
 
 // Fills the engine layout for the roundings in p and returns the per-shot stride.
 void layout_engine(const Plan& p, EngineLayout& L) {
-  const int K = p.K, n = p.n;
+  const int K = p.K, n = p.half;
   std::memset(&L, 0, sizeof(L));
   int64_t capX = 1, capX2 = 1, capR = 1, capT1 = 1, capB = 1, capM = 2, capUS = 1, capSA = 2, capSJ = 1,
           capQRS = 1, capQRT = 1, capSA2 = 1, capQRS2 = 1, capQRT2 = 1, capVp = 1, capYv = 1;
@@ -354,7 +367,9 @@ struct Engine {
 }  // namespace
 
 struct mpsw_state_s {
-  int B = 1, n = 0, K = 0;
+  // n bits per axis, ndim axes, K = ndim n sites; the two sweeps of the
+  // Kronecker rounding meet at site half = K / 2
+  int B = 1, n = 0, K = 0, ndim = 2, half = 0;
   std::vector<mpsw_config> cfg;
   hipStream_t stream = nullptr;
   int chi_cap = 1;
@@ -448,6 +463,8 @@ void fill_ctx(mpsw_state st, DevCtx& h, double* eng, const EngineLayout& L) {
   std::memset(&h, 0, sizeof(h));
   h.K = st->K;
   h.n = st->n;
+  h.ndim = st->ndim;
+  h.half = st->half;
   h.B = st->B;
   h.boundary = st->cfg[0].boundary;
   h.ordering = st->cfg[0].ordering;
@@ -554,7 +571,7 @@ int check_fits(const SweepCaps& s, int K) {
 // L->R sweep then R->L sweep for one rounding; output into MPS slot out_slot.
 void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int out_slot, int log_idx,
                   int slot_a, int slot_b, int step, int nshots, hipStream_t strm) {
-  const int K = st->K, n = st->n;
+  const int K = st->K, n = st->half;
   const DevCtx* d = e.d;
   // contractions of a time step run in the state's precision; set-up (dense
   // fields to MPS) always in FP64
@@ -757,7 +774,7 @@ int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t ch
   SweepCaps s = sweep_caps(rin, K, chi);
   Plan p;
   p.K = K;
-  p.n = st->n;
+  p.half = st->half;
   p.sw = {s};
   EngineLayout L;
   layout_engine(p, L);
@@ -791,6 +808,8 @@ int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t ch
   std::memset(&h, 0, sizeof(h));
   h.K = K;
   h.n = st->n;
+  h.ndim = st->ndim;
+  h.half = st->half;
   h.B = 1;
   h.mps = mps;
   h.mps_stride = mps_stride;
@@ -812,7 +831,7 @@ int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t ch
   std::vector<double> sites;   // the field in site order (interleaved states)
   if (st->cfg[0].ordering == MPSW_INTERLEAVED) {
     sites.resize(N);
-    field_to_sites(host_field, st->n, sites.data());
+    field_to_sites(host_field, st->n, st->ndim, sites.data());
     host_field = sites.data();
   }
   if (hipMemcpyAsync(dims, hd.data(), DL::size * sizeof(int), hipMemcpyHostToDevice, s0) != hipSuccess ||
@@ -874,7 +893,7 @@ int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t ch
 int build_step_engine(mpsw_state st) {
   drop_graphs(st);
   ++st->engine_gen;
-  const int K = st->K, n = st->n;
+  const int K = st->K, n = st->half;
   Engine& e = st->eng;
   if (e.eng) { hipFree(e.eng); e.eng = nullptr; }
   const auto& R = st->Rmax;
@@ -892,7 +911,7 @@ int build_step_engine(mpsw_state st) {
     if (rc != MPSW_OK) return rc;
   }
   e.plan.K = K;
-  e.plan.n = n;
+  e.plan.half = n;
   e.plan.sw = e.sw;
   e.plan.Rmax = R;
   e.plan.D = st->c2b;
@@ -919,7 +938,9 @@ int create_group(const mpsw_config* cfgs, int nshots, void* stream, mpsw_state* 
   const mpsw_config& c0 = cfgs[0];
   for (int i = 0; i < nshots; ++i) {
     const mpsw_config& c = cfgs[i];
-    if (c.n < 1 || c.n > 11) return fail(MPSW_EINVAL, "n must be in [1, 11]");
+    const int nd = c.ndim ? c.ndim : 2;
+    if (nd != 2 && nd != 3) return fail(MPSW_EINVAL, "ndim must be 2 or 3");
+    if (c.n < 1 || c.n * nd > 22) return fail(MPSW_EINVAL, "n must be in [1, 11] (two dimensions) or [1, 7] (three)");
     if (c.chi_max < 1) return fail(MPSW_EINVAL, "chi_max must be >= 1");
     if (!(c.eps >= 0.0) || !std::isfinite(c.eps)) return fail(MPSW_EINVAL, "eps must be finite and >= 0");
     if (!(c.lambda > 0.0) || !std::isfinite(c.lambda)) return fail(MPSW_EINVAL, "lambda must be > 0");
@@ -929,21 +950,23 @@ int create_group(const mpsw_config* cfgs, int nshots, void* stream, mpsw_state* 
     if (c.rank_mode != MPSW_RANK_EXACT && c.rank_mode != MPSW_RANK_LEARNED) return fail(MPSW_EINVAL, "unknown rank mode");
     if (c.ordering != MPSW_SEQUENTIAL && c.ordering != MPSW_INTERLEAVED) return fail(MPSW_EINVAL, "unknown site order");
     if (c.n != c0.n || c.lambda != c0.lambda || c.precision != c0.precision || c.boundary != c0.boundary ||
-        c.rank_mode != c0.rank_mode || c.ordering != c0.ordering)
-      return fail(MPSW_EINVAL, "shots of one batch must share n, lambda, precision, boundary, rank mode and site order");
+        c.rank_mode != c0.rank_mode || c.ordering != c0.ordering || nd != (c0.ndim ? c0.ndim : 2))
+      return fail(MPSW_EINVAL, "shots of one batch must share n, ndim, lambda, precision, boundary, rank mode and site order");
   }
   mpsw_state st = new mpsw_state_s();
   st->B = nshots;
   st->gemm_mode = (c0.precision == MPSW_FP32) ? GEMM_FP32 : (c0.precision == MPSW_BF16) ? GEMM_BF16X6 : GEMM_FP64;
   st->learned = (c0.rank_mode == MPSW_RANK_LEARNED);
   st->n = c0.n;
-  st->K = 2 * c0.n;
+  st->ndim = c0.ndim ? c0.ndim : 2;
+  st->K = st->ndim * c0.n;
+  st->half = st->K / 2;
   st->cfg.assign(cfgs, cfgs + nshots);
   st->stream = (hipStream_t)stream;
   st->chi_cap = 1;
   for (int i = 0; i < nshots; ++i) st->chi_cap = std::max(st->chi_cap, cfgs[i].chi_max);
   const int K = st->K;
-  st->lap = build_laplacian_mpo(st->n, c0.boundary, c0.ordering);
+  st->lap = build_laplacian_mpo(st->n, c0.boundary, c0.ordering, st->ndim);
   st->Rmax = state_rmax(K, st->chi_cap);
   // MPS slots
   int64_t off = 0;
@@ -1094,7 +1117,7 @@ int mpsw_set_velocity_dense(mpsw_state st, const double* c2, double eps_c) {
     mx = std::max(mx, c2[i]);
   }
   const double lam = st->cfg[0].lambda;
-  if (lam * lam * mx * 2.0 > 1.0) return fail(MPSW_ECFL, "CFL violated: lambda^2 max(c^2) 2 > 1");
+  if (lam * lam * mx * st->ndim > 1.0) return fail(MPSW_ECFL, "CFL violated: lambda^2 max(c^2) ndim > 1");
   int rc = dense_to_mps(st, c2, eps_c, p2(st->K), 0, 0, true);
   if (rc != MPSW_OK) return rc;
   if ((rc = build_step_engine(st)) != MPSW_OK) return rc;
@@ -1125,22 +1148,36 @@ int mpsw_set_velocity_mpo(mpsw_state st, const int* bonds, const double* cores) 
     mx = std::max(mx, v);
   }
   const double lam = st->cfg[0].lambda;
-  if (lam * lam * mx * 2.0 > 1.0) return fail(MPSW_ECFL, "CFL violated: lambda^2 max(c^2) 2 > 1");
+  if (lam * lam * mx * st->ndim > 1.0) return fail(MPSW_ECFL, "CFL violated: lambda^2 max(c^2) ndim > 1");
   if ((rc = build_step_engine(st)) != MPSW_OK) return rc;
   st->have_velocity = true;
   return MPSW_OK;
 }
 
-int mpsw_set_source(mpsw_state st, int shot, int ix, int iz, int nt, const double* wavelet) {
-  if (!st) return fail(MPSW_EINVAL, "null state");
+namespace {
+int set_source_at(mpsw_state st, int shot, int ix, int iy, int iz, int nt, const double* wavelet) {
   const int N = 1 << st->n;
   if (shot < 0 || shot >= st->B) return fail(MPSW_EINVAL, "shot out of range");
-  if (ix < 0 || ix >= N || iz < 0 || iz >= N) return fail(MPSW_EINVAL, "source outside the grid");
+  if (ix < 0 || ix >= N || iy < 0 || iy >= N || iz < 0 || iz >= N) return fail(MPSW_EINVAL, "source outside the grid");
   if (nt < 0 || (nt > 0 && !wavelet)) return fail(MPSW_EINVAL, "bad wavelet");
   st->wavelets[shot].assign(wavelet, wavelet + nt);
   int vals[3] = {ix, iz, nt};
   HIP_TRY(hipMemcpy(st->dims + (int64_t)shot * DL::size + DL::src_ix, vals, sizeof(vals), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(st->dims + (int64_t)shot * DL::size + DL::src_iy, &iy, sizeof(int), hipMemcpyHostToDevice));
   return upload_wavelets(st);
+}
+}  // namespace
+
+int mpsw_set_source(mpsw_state st, int shot, int ix, int iz, int nt, const double* wavelet) {
+  if (!st) return fail(MPSW_EINVAL, "null state");
+  if (st->ndim != 2) return fail(MPSW_EINVAL, "a three-dimensional state takes mpsw_set_source_3d");
+  return set_source_at(st, shot, ix, 0, iz, nt, wavelet);
+}
+
+int mpsw_set_source_3d(mpsw_state st, int shot, int ix, int iy, int iz, int nt, const double* wavelet) {
+  if (!st) return fail(MPSW_EINVAL, "null state");
+  if (st->ndim != 3) return fail(MPSW_EINVAL, "a two-dimensional state takes mpsw_set_source");
+  return set_source_at(st, shot, ix, iy, iz, nt, wavelet);
 }
 
 int mpsw_set_fields(mpsw_state st, int shot, const double* u_prev, const double* u_cur) {
@@ -1384,7 +1421,7 @@ int mpsw_to_dense(mpsw_state st, int shot, int which, double* out, int out_is_de
   if (rc != MPSW_OK) return rc;
   if (st->cfg[0].ordering == MPSW_INTERLEAVED) {
     std::vector<double> u(host.size());
-    sites_to_field(host.data(), st->n, u.data());
+    sites_to_field(host.data(), st->n, st->ndim, u.data());
     host.swap(u);
   }
   for (double v : host)
@@ -1600,7 +1637,7 @@ int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, doubl
   }
   Plan p;
   p.K = K;
-  p.n = 2;
+  p.half = 2;
   p.sw = {s};
   EngineLayout L;
   layout_engine(p, L);
@@ -1640,7 +1677,7 @@ int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, doubl
   Engine e;
   DevCtx& h = e.h;
   std::memset(&h, 0, sizeof(h));
-  h.K = K; h.n = 2; h.B = 1;
+  h.K = K; h.n = 2; h.half = 2; h.ndim = 2; h.B = 1;
   h.mps = mps; h.mps_stride = core_cap;
   for (int k = 0; k < K; ++k) { h.off_mps[0][k] = 0; h.cap_mps[0][k] = core_cap; }
   h.dims = dims; h.reals = reals; h.eng = eng; h.L = L; h.err = err; h.sync = sync;
@@ -1724,10 +1761,10 @@ int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, doubl
 
 // Host-side helper exported for tests: the fused Laplacian MPO cores
 // ([wl][wr][s'][s] per site, packed) and bonds (K+1) for a register of n bits.
-int mpsw_debug_laplacian_mpo(int n, int boundary, int ordering, int* bonds, double* cores, int64_t cap) {
-  if (n < 1 || n > 11 || !bonds) return fail(MPSW_EINVAL, "bad argument");
+int mpsw_debug_laplacian_mpo(int n, int boundary, int ordering, int ndim, int* bonds, double* cores, int64_t cap) {
+  if ((ndim != 2 && ndim != 3) || n < 1 || n * ndim > 22 || !bonds) return fail(MPSW_EINVAL, "bad argument");
   if (ordering != MPSW_SEQUENTIAL && ordering != MPSW_INTERLEAVED) return fail(MPSW_EINVAL, "unknown site order");
-  LapMPO m = build_laplacian_mpo(n, boundary, ordering);
+  LapMPO m = build_laplacian_mpo(n, boundary, ordering, ndim);
   std::copy(m.bonds.begin(), m.bonds.end(), bonds);
   int64_t o = 0;
   for (auto& c : m.cores) {

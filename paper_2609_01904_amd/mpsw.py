@@ -24,7 +24,7 @@ EXPORTS = [
     "mpsw_get_stats", "mpsw_get_shape", "mpsw_destroy", "mpsw_last_error", "mpsw_debug_laplacian_mpo",
     "mpsw_debug_factor", "mpsw_profile", "mpsw_profile_read", "mpsw_set_graph_mode",
     "mpsw_group_create", "mpsw_group_step", "mpsw_group_destroy", "mpsw_mlp_grad", "mpsw_mlp_train",
-    "mpsw_mlp_forward", "mpsw_rank_model_set", "mpsw_get_sigma_log", "mpsw_autotune",
+    "mpsw_mlp_forward", "mpsw_rank_model_set", "mpsw_get_sigma_log", "mpsw_autotune", "mpsw_set_source_3d",
 ]
 MLP_NPARAM = 21121
 
@@ -42,7 +42,8 @@ class MpswError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("chi_max", ctypes.c_int), ("eps", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("precision", ctypes.c_int), ("boundary", ctypes.c_int),
-                ("rank_mode", ctypes.c_int), ("seed", ctypes.c_uint64), ("ordering", ctypes.c_int)]
+                ("rank_mode", ctypes.c_int), ("seed", ctypes.c_uint64), ("ordering", ctypes.c_int),
+                ("ndim", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -81,7 +82,8 @@ def load():
         "mpsw_get_stats": [P, I, ctypes.POINTER(Stats)],
         "mpsw_get_shape": [P, ctypes.POINTER(I), ctypes.POINTER(I)],
         "mpsw_destroy": [P],
-        "mpsw_debug_laplacian_mpo": [I, I, I, P, P, ctypes.c_int64],
+        "mpsw_debug_laplacian_mpo": [I, I, I, I, P, P, ctypes.c_int64],
+        "mpsw_set_source_3d": [P, I, I, I, I, I, P],
         "mpsw_debug_factor": [I, I, I, P, P, P],
         "mpsw_profile": [P, I],
         "mpsw_set_graph_mode": [P, I],
@@ -117,8 +119,8 @@ def _f64(a):
 
 
 def make_config(n, chi_max, eps, lam, precision=MPSW_FP64, boundary=MPSW_PERIODIC,
-                rank_mode=MPSW_RANK_EXACT, seed=0, ordering=MPSW_SEQUENTIAL):
-    return Config(n, chi_max, eps, lam, precision, boundary, rank_mode, seed, ordering)
+                rank_mode=MPSW_RANK_EXACT, seed=0, ordering=MPSW_SEQUENTIAL, ndim=2):
+    return Config(n, chi_max, eps, lam, precision, boundary, rank_mode, seed, ordering, ndim)
 
 
 def _stream_handle(stream):
@@ -138,10 +140,10 @@ class State:
         if isinstance(cfg, (list, tuple)):
             arr = (Config * len(cfg))(*cfg)
             _check(lib.mpsw_create_batch(arr, len(cfg), _stream_handle(stream), ctypes.byref(self._h)))
-            self.n = cfg[0].n
+            self.n, self.ndim = cfg[0].n, cfg[0].ndim or 2
         else:
             _check(lib.mpsw_create_state(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(self._h)))
-            self.n = cfg.n
+            self.n, self.ndim = cfg.n, cfg.ndim or 2
         nshots, nsites = ctypes.c_int(), ctypes.c_int()
         _check(lib.mpsw_get_shape(self._h, ctypes.byref(nshots), ctypes.byref(nsites)))
         self.nshots, self.K = nshots.value, nsites.value
@@ -170,6 +172,10 @@ class State:
         w, p = _f64(wavelet)
         _check(load().mpsw_set_source(self._h, shot, ix, iz, w.size, p))
 
+    def set_source_3d(self, shot, ix, iy, iz, wavelet):
+        w, p = _f64(wavelet)
+        _check(load().mpsw_set_source_3d(self._h, shot, ix, iy, iz, w.size, p))
+
     def set_fields(self, shot, u_prev, u_cur):
         args = []
         keep = []
@@ -186,12 +192,12 @@ class State:
         _check(load().mpsw_step(self._h, int(k)))
 
     def to_dense(self, shot=0, which=0, out=None):
-        """Dense field as a (2^n, 2^n) float64 array; `out` may be a CUDA torch tensor."""
+        """Dense field as a (2^n,)*ndim float64 array; `out` may be a CUDA torch tensor."""
         N = 1 << self.n
         if out is not None and hasattr(out, "data_ptr"):
             _check(load().mpsw_to_dense(self._h, shot, which, ctypes.c_void_p(out.data_ptr()), 1))
             return out
-        a = np.empty((N, N), dtype=np.float64)
+        a = np.empty((N,) * self.ndim, dtype=np.float64)
         _check(load().mpsw_to_dense(self._h, shot, which, a.ctypes.data_as(ctypes.c_void_p), 0))
         return a
 
@@ -299,15 +305,15 @@ def mlp_forward(X, w):
     return out
 
 
-def debug_laplacian_mpo(n, boundary=MPSW_PERIODIC, ordering=MPSW_SEQUENTIAL):
+def debug_laplacian_mpo(n, boundary=MPSW_PERIODIC, ordering=MPSW_SEQUENTIAL, ndim=2):
     """Host-built fused Laplacian MPO cores (list of [wl, wr, 2, 2] arrays)."""
     lib = load()
-    K = 2 * n
+    K = ndim * n
     bonds = np.zeros(K + 1, dtype=np.int32)
-    total = _check(lib.mpsw_debug_laplacian_mpo(n, boundary, ordering, bonds.ctypes.data_as(ctypes.c_void_p),
+    total = _check(lib.mpsw_debug_laplacian_mpo(n, boundary, ordering, ndim, bonds.ctypes.data_as(ctypes.c_void_p),
                                                 None, 0))
     buf = np.zeros(max(total, 1))
-    _check(lib.mpsw_debug_laplacian_mpo(n, boundary, ordering, bonds.ctypes.data_as(ctypes.c_void_p),
+    _check(lib.mpsw_debug_laplacian_mpo(n, boundary, ordering, ndim, bonds.ctypes.data_as(ctypes.c_void_p),
                                         buf.ctypes.data_as(ctypes.c_void_p), buf.size))
     cores, o = [], 0
     for k in range(K):

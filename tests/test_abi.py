@@ -23,7 +23,7 @@ def lib():
 def _header_functions(repo_root):
     text = open(os.path.join(repo_root, "include", "mpsw.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mpsw_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(mpsw_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_exports_every_declared_symbol(lib, repo_root):
@@ -62,6 +62,34 @@ def test_fused_laplacian_mpo_interleaved(lib, n, boundary):
     assert max(bonds) <= 5
     if n >= 2:   # x carry, x borrow, z carry, z borrow and D cross the inner bonds
         assert bonds[2:2 * n - 1] == [5] * (2 * n - 3)
+
+
+@pytest.mark.parametrize("n", [1, 2])
+@pytest.mark.parametrize("boundary", ["periodic", "open"])
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_fused_laplacian_mpo_3d(lib, n, boundary, ordering):
+    """Three registers: the MPO is the seven-point stencil (with -6I) in site
+    order, checked on every basis field of the 2^n cube."""
+    bc = mpsw.MPSW_PERIODIC if boundary == "periodic" else mpsw.MPSW_OPEN
+    oname = "interleaved" if ordering else "sequential"
+    bonds, W = mpsw.debug_laplacian_mpo(n, bc, ordering, 3)
+    Wd = M.mpo_to_dense(W)
+    N = 1 << n
+    for idx in np.ndindex(N, N, N):
+        e = np.zeros((N, N, N))
+        e[idx] = 1.0
+        got = M.from_sites(Wd @ M.to_sites(e, oname), n, oname, 3)
+        np.testing.assert_array_equal(got, F.laplacian(e, boundary))
+    assert len(bonds) == 3 * n + 1 and max(bonds) <= 8
+
+
+def test_dimension_is_validated(lib):
+    for kw in (dict(ndim=4), dict(ndim=1), dict(n=8, ndim=3)):
+        args = dict(n=4, chi_max=8, eps=1e-8, lam=0.1)
+        args.update(kw)
+        with pytest.raises(mpsw.MpswError) as ei:
+            mpsw.State(mpsw.make_config(**args))
+        assert ei.value.name == "EINVAL"
 
 
 def test_interleaved_order_is_validated(lib):

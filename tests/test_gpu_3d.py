@@ -1,0 +1,179 @@
+"""Parity of the three-dimensional HIP path (K = 3n sites, registers x, y, z;
+seven-point Laplacian) with the FP64 oracle, through the C ABI: the velocity
+operator and the field layout, eq. 2 in 3D without truncation for both
+boundaries and site orders, each rounding of one step, a truncated
+trajectory against the dense-detour stepper, and a plane wave on a 64^3 grid
+against its closed-form dispersion relation.  Tolerances as in the
+two-dimensional parity tests (1e-10 truncated, 1e-12 untruncated)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fdtd as F
+from oracle import mps as M
+from oracle import stepper as S
+import synth
+
+pytestmark = pytest.mark.gpu
+ORD = {0: "sequential", 1: "interleaved"}
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mpsw():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2609_01904_amd import mpsw as m
+    m.load()
+    return m
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def make_state(mpsw, n, chi, eps, lam, boundary=0, ordering=0):
+    return mpsw.State(mpsw.make_config(n, chi, eps, lam, boundary=boundary, ordering=ordering, ndim=3))
+
+
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_velocity_and_fields_3d(mpsw, ordering):
+    for n in (3, 4):
+        _say("3d velocity", n, ordering)
+        N = 1 << n
+        rng = np.random.default_rng(n)
+        c2 = 1.0 + 0.5 * np.cos(np.arange(N)[:, None, None] / 3.0) * np.cos(np.arange(N)[None, :, None] / 5.0) \
+            + 0.1 * rng.random((N, N, N))
+        st = make_state(mpsw, n, 64, 0.0, 0.1, ordering=ordering)
+        st.set_velocity_dense(c2, 1e-6)
+        ref = S.c2_mps(c2, n, 1e-6, ORD[ordering])
+        assert st.bonds(0, 2) == M.bonds_of(ref)
+        assert rel(st.to_dense(0, 2), M.from_sites(M.to_dense(ref), n, ORD[ordering], 3)) < 1e-12
+        up, u = rng.standard_normal((N, N, N)), rng.standard_normal((N, N, N))
+        st2 = make_state(mpsw, n, 1 << 20, 0.0, 0.1, ordering=ordering)
+        st2.set_velocity_dense(c2, 1e-6)
+        st2.set_fields(0, up, u)
+        # full-rank random fields through 3n-site TT-SVDs: rounding level only
+        assert rel(st2.to_dense(0, 0), u) < 1e-12
+        assert rel(st2.to_dense(0, 1), up) < 1e-12
+        st.close()
+        st2.close()
+
+
+@pytest.mark.parametrize("n", [2, 3])
+@pytest.mark.parametrize("boundary", [0, 1])
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_untruncated_3d_step_equals_fdtd(mpsw, n, boundary, ordering):
+    _say("3d untruncated", n, boundary, ordering)
+    N = 1 << n
+    rng = np.random.default_rng(40 + n)
+    c2 = 0.5 + rng.random((N, N, N))
+    lam = 0.3
+    wav = rng.standard_normal(8)
+    src = (N // 2, 1, N - 1)
+    st = make_state(mpsw, n, 1 << 20, 0.0, lam, boundary, ordering)
+    st.set_velocity_dense(c2, 0.0)
+    c2r = st.to_dense(0, 2)
+    up, u = rng.standard_normal((N, N, N)), rng.standard_normal((N, N, N))
+    st.set_fields(0, up, u)
+    st.set_source_3d(0, src[0], src[1], src[2], wav)
+    a, b = up, u
+    bname = "periodic" if boundary == 0 else "open"
+    for k in range(8):
+        st.step(1)
+        a, b = b, F.fdtd_step(b, a, c2r, lam, wav[k], src, bname)
+        assert rel(st.to_dense(0, 0), b) < 1e-12, k
+    st.close()
+
+
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_each_rounding_matches_oracle_3d(mpsw, ordering):
+    n, chi, eps = 3, 10, 1e-6
+    N = 1 << n
+    o = ORD[ordering]
+    rng = np.random.default_rng(3)
+    c2 = 0.6 + 0.3 * rng.random((N, N, N))
+    lam = 0.3
+    c2m = S.c2_mps(c2, n, 1e-8, o)
+    st = make_state(mpsw, n, chi, eps, lam, ordering=ordering)
+    st.set_velocity_dense(c2, 1e-8)
+    up, u = rng.standard_normal((N, N, N)), rng.standard_normal((N, N, N))
+    st.set_fields(0, up, u)
+    psi = M.tt_svd(M.to_sites(u, o), 3 * n, eps, chi)
+    psip = M.tt_svd(M.to_sites(up, o), 3 * n, eps, chi)
+    st.step(1)
+    y = M.round_mps(M.laplacian_mps(psi, n, "periodic", o, 3), eps, chi)
+    w = M.round_mps(M.hadamard(c2m, y), eps, chi)
+    nxt = M.round_mps(M.direct_sum([psi, psip, w], [2.0, -1.0, lam * lam]), eps, chi)
+    for which, ref in ((3, y), (4, w), (0, nxt)):
+        assert st.bonds(0, which) == M.bonds_of(ref), which
+        assert rel(st.to_dense(0, which), M.from_sites(M.to_dense(ref), n, o, 3)) < 1e-11, which
+    st.close()
+
+
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_truncated_3d_trajectory_matches_oracle(mpsw, ordering):
+    n, chi, eps, steps = 4, 16, 1e-6, 20
+    N = 1 << n
+    o = ORD[ordering]
+    rng = np.random.default_rng(9)
+    c2 = 0.6 + 0.2 * rng.random((N, N, N))
+    lam = 0.3
+    wav = synth.ricker(steps, 0.02, 4.0)
+    src = (N // 2, N // 3, 1)
+    st = make_state(mpsw, n, chi, eps, lam, ordering=ordering)
+    st.set_velocity_dense(c2, 1e-6)
+    st.set_source_3d(0, src[0], src[1], src[2], wav)
+    ds = S.DenseStepper(n, lam, eps, chi, st.to_dense(0, 2), src=src, wavelet=wav, ordering=o)
+    for _ in range(steps):
+        ds.step()
+    st.step(steps)
+    g = st.to_dense(0, 0)
+    _say("3d trajectory", o, rel(g, ds.dense()), st.bonds(0, 0))
+    assert rel(g, ds.dense()) < 1e-10
+    assert st.bonds(0, 0) == ds.ranks[-1][2]
+    st.close()
+
+
+def test_plane_wave_3d_64_cube(mpsw):
+    """n = 6 (64^3, K = 18): a plane wave stays rank 2 and follows the closed
+    form sin^2(omega dt / 2) = C^2 (sum over axes of sin^2(pi m / N))."""
+    n, ms, courant = 6, (5, 11, 2), 0.45
+    N = 1 << n
+    wdt = 2.0 * np.arcsin(courant * np.sqrt(sum(np.sin(np.pi * m / N) ** 2 for m in ms)))
+    grid = np.meshgrid(*[np.arange(N)] * 3, indexing="ij")
+    theta = 2.0 * np.pi * sum(m * g for m, g in zip(ms, grid)) / N + 0.2
+    st = make_state(mpsw, n, 8, 1e-10, courant)
+    st.set_velocity_dense(np.ones((N, N, N)), 1e-12)
+    st.set_fields(0, np.cos(theta + wdt), np.cos(theta))
+    steps = 15
+    st.step(steps)
+    g = st.to_dense(0, 0)
+    _say("3d plane wave", np.max(np.abs(g - np.cos(theta - steps * wdt))), max(st.bonds(0, 0)))
+    assert np.max(np.abs(g - np.cos(theta - steps * wdt))) < 1e-10
+    assert max(st.bonds(0, 0)) == 2
+    st.close()
+
+
+def test_source_entry_points_check_the_dimension(mpsw):
+    st = make_state(mpsw, 2, 4, 1e-8, 0.1)
+    with pytest.raises(mpsw.MpswError) as ei:
+        st.set_source(0, 1, 1, np.ones(3))
+    assert ei.value.name == "EINVAL"
+    st.set_velocity_dense(np.full((4, 4, 4), 30.0), 1e-8)      # lambda^2 c^2 3 = 0.9 <= 1
+    with pytest.raises(mpsw.MpswError) as ei:
+        st.set_velocity_dense(np.full((4, 4, 4), 40.0), 1e-8)  # lambda^2 c^2 3 = 1.2 > 1
+    assert ei.value.name == "ECFL"
+    st.close()
+    st2 = mpsw.State(mpsw.make_config(2, 4, 1e-8, 0.1))
+    with pytest.raises(mpsw.MpswError) as ei:
+        st2.set_source_3d(0, 1, 1, 1, np.ones(3))
+    assert ei.value.name == "EINVAL"
+    st2.close()
