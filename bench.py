@@ -104,14 +104,28 @@ def make_state(mpsw, synth, workload, batch, precision, rank="exact", model=None
     prec = {"fp64": mpsw.MPSW_FP64, "fp32": mpsw.MPSW_FP32, "bf16": mpsw.MPSW_BF16}[precision]
     rmode = mpsw.MPSW_RANK_LEARNED if rank == "learned" else mpsw.MPSW_RANK_EXACT
     order = mpsw.MPSW_INTERLEAVED if ordering == "interleaved" else mpsw.MPSW_SEQUENTIAL
+    nd = cfg["ndim"]
     cfgs = [mpsw.make_config(n, cfg["chi"], cfg["eps"], cfg["lam"], precision=prec, rank_mode=rmode, seed=11,
-                             ordering=order)
+                             ordering=order, ndim=nd)
             for _ in range(batch)]
     st = mpsw.State(cfgs if batch > 1 else cfgs[0])
     st.set_velocity_dense(cfg["c2"], cfg["eps_c"])
     if model is not None:
         st.set_rank_model(model)
     fields = []
+    if nd == 3:   # the cube: 8 variants of one developed wavefield (x, y swapped and flipped)
+        up0, u0 = synth.wavefront_fields_3d(n, seed=0)
+        for b in range(batch):
+            def sym(f):
+                g = f.transpose(1, 0, 2) if b % 2 else f
+                g = g[::-1] if (b // 2) % 2 else g
+                return np.ascontiguousarray(g[:, ::-1] if (b // 4) % 2 else g)
+            up, u = sym(up0), sym(u0)
+            st.set_fields(b, up, u)
+            ix = (cfg["ix"] + b * (N // max(batch, 1))) % N
+            st.set_source_3d(b, ix, cfg["iy"], cfg["iz"], cfg["wavelet_samples"])
+            fields.append((up, u, (ix, cfg["iy"], cfg["iz"])))
+        return st, cfg, fields
     up0, u0 = synth.wavefront_fields(n, seed=0)
     for b in range(batch):
         # shot b starts from one of the 8 symmetries of the square of the same wavefield
@@ -121,7 +135,7 @@ def make_state(mpsw, synth, workload, batch, precision, rank="exact", model=None
         # distinct source positions along the surface row
         ix = (cfg["ix"] + b * (N // max(batch, 1))) % N
         st.set_source(b, ix, cfg["iz"], cfg["wavelet_samples"])
-        fields.append((up, u, ix))
+        fields.append((up, u, (ix, cfg["iz"])))
     return st, cfg, fields
 
 
@@ -137,10 +151,11 @@ def cpu_baseline(synth, workload, fields, seconds, ordering="sequential"):
     cfg = synth.get_config(workload)
     n = cfg["n"]
     N = 1 << n
-    c2 = OM.from_sites(OM.to_dense(OM.tt_svd(OM.to_sites(cfg["c2"], ordering), 2 * n, cfg["eps_c"],
-                                              chi_max=1 << 30)), n, ordering)
-    up, u, ix = fields[0]
-    ds = DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], c2, src=(ix, cfg["iz"]),
+    nd = cfg["ndim"]
+    c2 = OM.from_sites(OM.to_dense(OM.tt_svd(OM.to_sites(cfg["c2"], ordering), nd * n, cfg["eps_c"],
+                                              chi_max=1 << 30)), n, ordering, nd)
+    up, u, src = fields[0]
+    ds = DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], c2, src=src,
                       wavelet=cfg["wavelet_samples"], ordering=ordering)
     ds.set_fields(up, u)
     steps, t0 = 0, time.perf_counter()
@@ -424,7 +439,7 @@ def main():
         "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: n={cfg['n']} ({1 << cfg['n']}x{1 << cfg['n']}), chi_max={cfg['chi']}, "
+        "config": {"workload": f"{args.workload}: n={cfg['n']} ({'x'.join([str(1 << cfg['n'])] * cfg['ndim'])}), chi_max={cfg['chi']}, "
                                f"eps={cfg['eps']}, layered-fault c^2 (cutoff {cfg['eps_c']}), "
                                f"start from a developed wavefield at the chi cap",
                    "shots": args.batch, "precision": args.precision, "site_order": args.ordering,
@@ -440,9 +455,12 @@ def main():
         total = int(stats[0]["step"])
         u_form = st.to_dense(0, 0)
         pl, _, _ = make_state(mpsw, synth, args.workload, 1, "fp64", ordering=args.ordering)
-        up, u, ix = fields[0]
+        up, u, src = fields[0]
         pl.set_fields(0, up, u)
-        pl.set_source(0, ix, cfg["iz"], cfg["wavelet_samples"])
+        if len(src) == 3:
+            pl.set_source_3d(0, *src, cfg["wavelet_samples"])
+        else:
+            pl.set_source(0, *src, cfg["wavelet_samples"])
         if not args.no_tune:
             pl.autotune(2)
         pl.step(total - args.steps)

@@ -14,10 +14,13 @@ workload list this library is measured on:
 * C4  64 shots, n in {8, 9, 10}, chi in {32, 64, 128}, Ricker f0 ~ U[8, 25] Hz at
       random x, depth 10 m, 1000 steps, eps = 1e-6.
 * C5  n=11, chi = 256, eps = 1e-6, 3000 steps.
+* C3D three-dimensional form: 128^3 cube (n=7, K = 21 sites), layered-fault
+      model with undulations along y, Ricker 15 Hz at the top centre, chi = 64,
+      eps = 1e-6, dt = 1 ms (c dt/dh <= 0.45 < 1/sqrt(3)).
 """
 import numpy as np
 
-from .velocity import layered_fault_velocity, constant_velocity
+from .velocity import layered_fault_velocity, layered_fault_velocity_3d, constant_velocity
 from .wavelet import ricker, impulse
 
 DH = 10.0
@@ -34,6 +37,8 @@ CONFIGS = {
                wavelet="ricker", f0=15.0, steps=2000, eps=1e-6, chi=128, eps_c=1e-6),
     "C5": dict(n=11, dh=DH, dt=DT, model="layered_fault", seed=0, src=("depth", 1),
                wavelet="ricker", f0=15.0, steps=3000, eps=1e-6, chi=256, eps_c=1e-6),
+    "C3D": dict(n=7, ndim=3, dh=DH, dt=DT, model="layered_fault_3d", seed=0, src=("depth", 1),
+                wavelet="ricker", f0=15.0, steps=1000, eps=1e-6, chi=64, eps_c=1e-6),
 }
 
 
@@ -45,6 +50,8 @@ def get_config(name, **overrides):
     N = 1 << n
     if cfg["model"] == "constant":
         c2 = constant_velocity(n, cfg["c"])
+    elif cfg["model"] == "layered_fault_3d":
+        c2 = layered_fault_velocity_3d(n, cfg["dh"], cfg.get("seed", 0))
     else:
         c2 = layered_fault_velocity(n, cfg["dh"], cfg.get("seed", 0))
     kind = cfg["src"]
@@ -59,6 +66,9 @@ def get_config(name, **overrides):
         w = ricker(nt, cfg["dt"], cfg["f0"])
     else:
         w = impulse(nt)
+    cfg.setdefault("ndim", 2)
+    if cfg["ndim"] == 3:
+        cfg["iy"] = N // 2
     cfg.update(c2=c2, ix=ix, iz=iz, wavelet_samples=w, lam=cfg["dt"] / cfg["dh"])
     return cfg
 

@@ -83,6 +83,31 @@ def random_mps_cores(K, bonds, seed=0):
             for k in range(K)]
 
 
+def wavefront_fields_3d(n, seed=0, nfronts=48, dh=10.0, dt=1e-3, f0=15.0, vmin=1500.0, vmax=4500.0):
+    """(u^{-1}, u^0) on a cube: the same recipe as wavefront_fields with
+    spherical fronts (centres uniform over the cube, amplitude a_j / (R_j / dh)
+    for spherical spreading)."""
+    rng = np.random.default_rng(seed)
+    N = 1 << n
+    X = N * dh
+    cen = rng.uniform(0.0, X, (nfronts, 3))
+    R = rng.uniform(0.05 * X, 0.8 * X, nfronts)
+    c = rng.uniform(vmin, vmax, nfronts)
+    amp = rng.uniform(0.5, 1.0, nfronts) * rng.choice([-1.0, 1.0], nfronts)
+    g = np.arange(N) * dh
+    x, y, z = g[:, None, None], g[None, :, None], g[None, None, :]
+    out = []
+    for t in (-dt, 0.0):
+        u = np.zeros((N, N, N))
+        for j in range(nfronts):
+            dist = np.sqrt((x - cen[j, 0]) ** 2 + (y - cen[j, 1]) ** 2 + (z - cen[j, 2]) ** 2)
+            tau = (dist - R[j] - c[j] * t) / c[j]
+            a = (np.pi * f0 * tau) ** 2
+            u += amp[j] / (R[j] / dh) * (1.0 - 2.0 * a) * np.exp(-a)
+        out.append(u)
+    return out[0], out[1]
+
+
 def wavefront_fields(n, seed=0, nfronts=48, dh=10.0, dt=1e-3, f0=15.0, vmin=1500.0, vmax=4500.0):
     """(u^{-1}, u^0) of a developed wavefield: a seeded superposition of
     expanding circular Ricker wavefronts.

@@ -65,7 +65,7 @@ def test_c3_batched_step_matches_oracle_on_sampled_shots(mpsw):
         up, u, k = before[s]
         g = st.to_dense(s, 0)
         assert np.all(np.isfinite(g))
-        ds = S.DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], c2r, src=(fields[s][2], cfg["iz"]),
+        ds = S.DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], c2r, src=fields[s][2],
                             wavelet=cfg["wavelet_samples"])
         ds.u_prev, ds.u, ds.k = up, u, k
         ds.step()
@@ -90,7 +90,7 @@ def test_c5_step_matches_oracle(mpsw):
     st.step(1)
     torch.cuda.synchronize()
     g = st.to_dense(0, 0)
-    ds = S.DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], st.to_dense(0, 2), src=(fields[0][2], cfg["iz"]),
+    ds = S.DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], st.to_dense(0, 2), src=fields[0][2],
                         wavelet=cfg["wavelet_samples"])
     ds.u_prev, ds.u, ds.k = up, u, k
     ds.step()

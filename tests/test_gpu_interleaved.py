@@ -171,7 +171,7 @@ def test_c3_step_matches_oracle_interleaved(mpsw):
     c2r = st.to_dense(0, 2)
     for s in sample:
         up, u, k = before[s]
-        ds = S.DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], c2r, src=(fields[s][2], cfg["iz"]),
+        ds = S.DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], c2r, src=fields[s][2],
                             wavelet=cfg["wavelet_samples"], ordering=IL)
         ds.u_prev, ds.u, ds.k = up, u, k
         ds.step()
