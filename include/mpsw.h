@@ -210,6 +210,15 @@ int mpsw_profile_read(mpsw_state st, int kclass, mpsw_kprof* out);
  * NULL.  Synchronises.  Errors: EINVAL, ESTATE, ENOMEM, EHIP. */
 int mpsw_autotune(mpsw_state st, int steps, int* qr_nwg, int* jac_block);
 
+/* Set the launch shapes mpsw_autotune chooses, without timing: the cap on the
+ * workgroups per shot of a QR factorisation (1..32) and the Jacobi block
+ * width (0 = rule from the column count, or 8, 16, 32).  For reusing a shape
+ * tuned earlier on another state of the same bucket; the shapes change the
+ * order of the factorisations' sums, so results agree with another shape to
+ * rounding, and with the same shape bit for bit.  Captured step graphs are
+ * dropped.  Errors: EINVAL. */
+int mpsw_set_launch_shapes(mpsw_state st, int qr_nwg, int jac_block);
+
 /* Learned-rank rounding (rank_mode MPSW_RANK_LEARNED): for every bond of the
  * SVD sweep the rank network (parameters w, MPSW_MLP_NPARAM floats, host
  * memory copied) proposes r from the bond's leading singular values at the

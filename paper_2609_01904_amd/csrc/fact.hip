@@ -167,107 +167,6 @@ __device__ void apply_reflector(const double* __restrict__ V, int64_t ldv, doubl
 }
 
 // ---------------------------------------------------------------------------
-// One wave applies a staged panel's block reflector to one group of at most
-// 16 columns: C -= V T^T (V^T C), all on the matrix cores, no workgroup
-// synchronisation.  V (mj x bw, unit lower trapezoid; its strict lower part
-// in Vl, column-major with leading dimension mj) sits in LDS; C (mj x bwc,
-// column-major, leading dimension ldc) and T (BW x BW row-major, upper
-// triangular) in global memory.  The row sum of V^T C runs in any order, so
-// lane (li, lk) takes rows 16 t + 4 lk + e of column li for both operands
-// (4 contiguous doubles per lane); the update's rows are permuted the same
-// way, so each lane writes 4 contiguous rows of its column.
-// ---------------------------------------------------------------------------
-template <int BW>
-__device__ void apply_wave(const double* Vl, int ldv, int mj, int bw, double* C, int64_t ldc, int bwc,
-                           const double* __restrict__ T) {
-  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
-  // branch-free: every lane loads an in-range element, then selects
-  auto vfull = [&](int rr, int p) -> double {
-    const double x = Vl[min(rr, mj - 1) + ldv * min(p, bw - 1)];
-    const bool in = rr < mj && p < bw;
-    const double y = (in && rr > p) ? x : 0.0;
-    return (in && rr == p) ? 1.0 : y;
-  };
-  const bool colok = li < bwc;
-  // global address space: its loads are counted apart from the LDS reads, so
-  // waiting for V does not wait for C
-  typedef __attribute__((address_space(1))) double gdouble;
-  gdouble* Cc = (gdouble*)(C + (int64_t)(colok ? li : 0) * ldc);   // column 0 stands in for idle lanes
-  const int nchunk = (mj + 15) >> 4, nfull = mj >> 4;
-  constexpr int UN = 2;   // chunks whose loads are in flight together
-  // W = V^T C; acc[v] = W[lk + 4 v][li]
-  mpsw_d4 acc = {0.0, 0.0, 0.0, 0.0};
-  int tt = 0;
-  for (; tt + UN <= nfull; tt += UN) {
-    double cv[UN][4];
-#pragma unroll
-    for (int u = 0; u < UN; ++u)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) cv[u][e] = Cc[16 * (tt + u) + 4 * lk + e];
-#pragma unroll
-    for (int u = 0; u < UN; ++u) {
-      const int rb = 16 * (tt + u) + 4 * lk;
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(vfull(rb + e, li), colok ? cv[u][e] : 0.0, acc, 0, 0, 0);
-    }
-  }
-  for (; tt < nchunk; ++tt) {
-    const int rb = 16 * tt + 4 * lk;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const double cv = (colok && rb + e < mj) ? Cc[rb + e] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(vfull(rb + e, li), cv, acc, 0, 0, 0);
-    }
-  }
-  // W2 = T^T W: the accumulator of W is the b operand of k-step v
-  mpsw_d4 w2 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
-    const int sidx = 4 * kk + lk;   // A2[li][sidx] = T[sidx][li], zero below the diagonal
-    const double a = (sidx < BW && li < BW && sidx <= li && li < bw) ? T[sidx * BW + li] : 0.0;
-    w2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, acc[kk], w2, 0, 0, 0);
-  }
-  // C -= V W2 in 16-row tiles; A's row i is tile row 4 (i % 4) + i / 4, so
-  // lane (li, lk) owns rows 4 lk .. 4 lk + 3 of the tile in column li
-  auto tile = [&](int rb0, const double (&cv)[4], bool full) {
-    const int ra = rb0 + 4 * (li & 3) + (li >> 2);
-    mpsw_d4 d = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
-      if (4 * kk < bw) d = __builtin_amdgcn_mfma_f64_16x16x4f64(vfull(ra, 4 * kk + lk), w2[kk], d, 0, 0, 0);
-    const int rw = rb0 + 4 * lk;
-    if (full) {
-      if (colok) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Cc[rw + v] = cv[v] - d[v];
-      }
-    } else {
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        if (colok && rw + v < mj) Cc[rw + v] = cv[v] - d[v];
-    }
-  };
-  tt = 0;
-  for (; tt + UN <= nfull; tt += UN) {
-    double cv[UN][4];
-#pragma unroll
-    for (int u = 0; u < UN; ++u)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) cv[u][e] = Cc[16 * (tt + u) + 4 * lk + e];
-#pragma unroll
-    for (int u = 0; u < UN; ++u) tile(16 * (tt + u), cv[u], true);
-  }
-  for (; tt < nchunk; ++tt) {
-    const int rw = 16 * tt + 4 * lk;
-    double cv[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) cv[e] = (colok && rw + e < mj) ? Cc[rw + e] : 0.0;
-    tile(16 * tt, cv, false);
-  }
-}
-
-// ---------------------------------------------------------------------------
 // QR factorisation.  a.op = 0: QR sweep at site a.site (X or X2 -> Q slot,
 // R buffer, rt/qid).  For the SVD of the bond matrix M (rt_k x 2 rho_{k+1}):
 // a.op = 1 factors M = Q R when M is tall or square (R^T -> Jacobi buffer),
@@ -619,25 +518,12 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
       factor_panel<BW, QNT>(c, S, m, n, j1, T, lds, red);
       publish(j1);
     }
-    // my other trailing blocks: panel j's reflectors staged in LDS, then one
-    // wave per group of up to 16 columns
-    const int r0 = j * BW, mj = m - r0, bwj = min(BW, n - j * BW);
-    const int ldv = mj | 1;   // odd: the 16 columns a load touches sit in distinct LDS banks
-    __syncthreads();   // the LDS held the lookahead panel or the previous stage
-    bulk_copy<8>(mj * bwj, t, QNT, [&](int e) { return S[r0 + (int)(e % mj) + (int64_t)m * (r0 + (int)(e / mj))]; },
-                 [&](int e, double v) { lds[(e % mj) + ldv * (e / mj)] = v; });
-    __syncthreads();
-    int q = 0;
-    for (int g = w; g < ngroups; g += P) {
+    for (int g = w; g < ngroups; g += P) {   // my other trailing blocks, one group at a time
       int lo = max(g * GB, j + 1);
       const int hi = min(g * GB + GB - 1, nbk - 1);
       if (own1 && lo <= j1 && j1 <= hi) lo = j1 + 1;
-      if (lo > hi) continue;
-      if (q++ % (QNT / 64) != (t >> 6)) continue;
-      const int cb = lo * BW, bwc = min((hi - lo + 1) * BW, n - cb);
-      apply_wave<BW>(lds, ldv, mj, bwj, S + r0 + (int64_t)m * cb, m, bwc, T + (int64_t)j * BW * BW);
+      if (lo <= hi) apply(j, lo, hi);
     }
-    __syncthreads();
   }
   // R (n x n) from my columns: row-major R (sweep) or R^T column-major (SVD)
   for (int blk = 0; blk < nbk && Rout; ++blk) {
@@ -1229,8 +1115,7 @@ void launch_sync_reset(const DevCtx* d, int nshots, hipStream_t s) {
 }
 
 void launch_qrf(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, size_t lds, hipStream_t s) {
-  // the panel with one spare row (an odd leading dimension), or the reflector workspace
-  lds = std::max(lds + (size_t)bw * sizeof(double), (size_t)MPSW_APPLY_LDS * sizeof(double));
+  lds = std::max(lds, (size_t)MPSW_APPLY_LDS * sizeof(double));   // the panel, or the reflector workspace
   if (bw == 16)
     hipLaunchKernelGGL(k_qrf<16>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
   else if (bw == 8)

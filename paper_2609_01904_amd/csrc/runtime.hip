@@ -1560,6 +1560,17 @@ int mpsw_autotune(mpsw_state st, int steps, int* qr_nwg, int* jac_block_out) {
   return MPSW_OK;
 }
 
+int mpsw_set_launch_shapes(mpsw_state st, int qr_nwg, int jac_block) {
+  if (!st) return fail(MPSW_EINVAL, "null state");
+  if (qr_nwg < 1 || qr_nwg > 32) return fail(MPSW_EINVAL, "qr_nwg must be in 1..32");
+  if (jac_block != 0 && jac_block != 8 && jac_block != 16 && jac_block != 32)
+    return fail(MPSW_EINVAL, "jac_block must be 0, 8, 16 or 32");
+  st->tune_qr_nwg = qr_nwg;
+  st->tune_jac_b = jac_block;
+  drop_graphs(st);   // captured steps hold the old grids
+  return MPSW_OK;
+}
+
 int mpsw_rank_model_set(mpsw_state st, const float* w, int nw) {
   if (!st || !w || nw != MLP_NPARAM) return fail(MPSW_EINVAL, "null argument or wrong parameter count");
   if (!st->mlp_w) HIP_TRY(hipMalloc(&st->mlp_w, MLP_NPARAM * sizeof(float)));

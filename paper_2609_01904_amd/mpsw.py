@@ -24,7 +24,7 @@ EXPORTS = [
     "mpsw_get_stats", "mpsw_get_shape", "mpsw_destroy", "mpsw_last_error", "mpsw_debug_laplacian_mpo",
     "mpsw_debug_factor", "mpsw_profile", "mpsw_profile_read", "mpsw_set_graph_mode",
     "mpsw_group_create", "mpsw_group_step", "mpsw_group_destroy", "mpsw_mlp_grad", "mpsw_mlp_train",
-    "mpsw_mlp_forward", "mpsw_rank_model_set", "mpsw_get_sigma_log", "mpsw_autotune", "mpsw_set_source_3d",
+    "mpsw_mlp_forward", "mpsw_rank_model_set", "mpsw_get_sigma_log", "mpsw_autotune", "mpsw_set_launch_shapes", "mpsw_set_source_3d",
 ]
 MLP_NPARAM = 21121
 
@@ -96,6 +96,7 @@ def load():
         "mpsw_rank_model_set": [P, P, I],
         "mpsw_get_sigma_log": [P, I, I, P],
         "mpsw_autotune": [P, I, ctypes.POINTER(I), ctypes.POINTER(I)],
+        "mpsw_set_launch_shapes": [P, I, I],
         "mpsw_profile_read": [P, I, ctypes.POINTER(KProf)],
     }
     for name, args in sig.items():
@@ -230,6 +231,10 @@ class State:
         q, b = ctypes.c_int(), ctypes.c_int()
         _check(load().mpsw_autotune(self._h, int(steps), ctypes.byref(q), ctypes.byref(b)))
         return q.value, b.value
+
+    def set_launch_shapes(self, qr_nwg, jac_block):
+        """Set the launch shapes autotune chooses (QR workgroups per shot, Jacobi block)."""
+        _check(load().mpsw_set_launch_shapes(self._h, int(qr_nwg), int(jac_block)))
 
     def set_graph_mode(self, on=True):
         """Replay captured HIP graphs (three steps per launch) in step()."""
