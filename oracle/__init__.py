@@ -13,6 +13,8 @@ Modules
 fdtd     dense FDTD update (Sec. 2, eq. 2), discrete energy, brute-force operators
 circuit  classical simulation of the incrementer / decrementer circuits
          (Sec. 3.1, eq. 5 and Fig. 1)
+lcu      statevector simulation of the update of eq. 7 as a linear combination
+         of unitaries built from those circuits (Sec. 3.2, eq. 6)
 mps      quantics MPS arithmetic: shift MPOs (Sec. 4.2, eqs. 9-15), Laplacian
          MPO sum (eq. 16), diagonal c^2 MPO (Sec. 4.3), sums, Hadamard
          products, TT-SVD and rounding (QR sweep + truncated SVD sweep, Sec. 4.3)
