@@ -37,9 +37,21 @@ def c2_mps(c2_dense, n, eps_c, ordering="sequential"):
     return M.tt_svd(M.to_sites(c2_dense, ordering), c2_dense.ndim * n, eps_c, chi_max=1 << 30)
 
 
+# Rounding schedules of one step: "three" rounds the
+# Laplacian result, the c^2 product and the update sum (eq. 17); "seven"
+# rounds after each of the 2 ndim shift-operator applications and after their
+# sum as well (the literal reading of a compression after every operator
+# application); "one" rounds only the update sum, so the Laplacian and the c^2
+# product are exact (bonds multiply: usable on small grids only).
+SCHEDULES = ("three", "seven", "one")
+
+
 class MPSStepper:
     def __init__(self, n, lam, eps, chi_max, c2_cores, boundary="periodic",
-                 src=None, wavelet=None, ordering="sequential", ndim=2):
+                 src=None, wavelet=None, ordering="sequential", ndim=2, schedule="three"):
+        if schedule not in SCHEDULES:
+            raise ValueError(f"schedule must be one of {SCHEDULES}")
+        self.schedule = schedule
         self.n, self.K, self.ndim = n, ndim * n, ndim
         self.lam, self.eps, self.chi = lam, eps, chi_max
         self.c2 = c2_cores
@@ -68,8 +80,23 @@ class MPSStepper:
         s_k = 0.0
         if self.wavelet is not None and self.k < len(self.wavelet):
             s_k = float(self.wavelet[self.k])
-        y = self._round(M.laplacian_mps(self.psi, self.n, self.boundary, self.ordering, self.ndim), 0)
-        w = self._round(M.hadamard(self.c2, y), 1)
+        if self.schedule == "one":
+            # no rounding before the last: the Laplacian and the c^2 product
+            # enter the sum at their full bonds
+            w = M.hadamard(self.c2, M.laplacian_mps(self.psi, self.n, self.boundary, self.ordering,
+                                                    self.ndim))
+        else:
+            if self.schedule == "seven":
+                # a rounding after each shift-operator application, then one
+                # after their sum with -2 ndim psi
+                shifted = [self._round(M.apply_mpo(M.shift_mpo_nd(self.n, ax, d, self.boundary,
+                                                                  self.ordering, self.ndim), self.psi), 3)
+                           for ax in range(self.ndim) for d in (+1, -1)]
+                y = self._round(M.direct_sum(shifted + [self.psi],
+                                             [1.0] * (2 * self.ndim) + [-2.0 * self.ndim]), 0)
+            else:
+                y = self._round(M.laplacian_mps(self.psi, self.n, self.boundary, self.ordering, self.ndim), 0)
+            w = self._round(M.hadamard(self.c2, y), 1)
         terms = [self.psi, self.psi_prev, w]
         coeffs = [2.0, -1.0, self.lam * self.lam]
         if self.src is not None:
