@@ -23,6 +23,7 @@ namespace mpsw {
 #define QNT 1024   // threads of the QR-family kernels
 #define MPSW_APPLY_LDS (16 * 256 + 256)   // doubles of LDS for apply_reflector
 #define APNT 512   // threads of k_applyq, k_applyv, k_formq (8 waves, no register spills)
+#define QR_HALF_WSP (8 * 256 + 256)   // doubles of reflector workspace for half of a QR workgroup
 
 __device__ __forceinline__ int ld_acquire(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -85,9 +86,10 @@ typedef double mpsw_d4 __attribute__((ext_vector_type(4)));
 
 template <int BW, int NWV = 16>
 __device__ void apply_reflector(const double* __restrict__ V, int64_t ldv, double* C, int64_t crs, int64_t ccs,
-                                int mj, int bw, int bwc, const double* __restrict__ T, bool trans, double* wsp) {
+                                int mj, int bw, int bwc, const double* __restrict__ T, bool trans, double* wsp,
+                                int t0 = 0) {
   static_assert(BW <= 16, "panel wider than one matrix-core tile");
-  const int t = threadIdx.x, l = t & 63, wv = t >> 6;
+  const int t = threadIdx.x - t0, l = t & 63, wv = t >> 6;
   const int li = l & 15, lk = l >> 4;
   // unit lower trapezoid of V, zero beyond the panel width
   auto vfull = [&](int r, int p) -> double {
@@ -518,12 +520,35 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
       factor_panel<BW, QNT>(c, S, m, n, j1, T, lds, red);
       publish(j1);
     }
-    for (int g = w; g < ngroups; g += P) {   // my other trailing blocks, one group at a time
+    // my other trailing groups, two at a time: waves 0-7 update the first of
+    // a pair and waves 8-15 the second (an empty update when there is none);
+    // both halves pass the same workgroup barriers
+    const int half = t / (QNT / 2);
+    auto apply_pair = [&](int lo0, int hi0, int lo1, int hi1) {
+      const int lo = half ? lo1 : lo0, hi = half ? hi1 : hi0;
+      const int r0 = j * BW, c0 = j * BW, bw = min(BW, n - c0);
+      const int cb = (lo <= hi) ? lo * BW : c0;
+      const int bwc = (lo <= hi) ? min((hi - lo + 1) * BW, n - cb) : 0;
+      apply_reflector<BW, QNT / 128>(S + r0 + (int64_t)m * c0, m, S + r0 + (int64_t)m * cb, 1, m, m - r0, bw, bwc,
+                                     T + (int64_t)j * BW * BW, true, lds + half * QR_HALF_WSP, half * (QNT / 2));
+    };
+    bool have = false;
+    int plo = 0, phi = -1;
+    for (int g = w; g < ngroups; g += P) {
       int lo = max(g * GB, j + 1);
       const int hi = min(g * GB + GB - 1, nbk - 1);
       if (own1 && lo <= j1 && j1 <= hi) lo = j1 + 1;
-      if (lo <= hi) apply(j, lo, hi);
+      if (lo > hi) continue;
+      if (!have) {
+        plo = lo;
+        phi = hi;
+        have = true;
+        continue;
+      }
+      apply_pair(plo, phi, lo, hi);
+      have = false;
     }
+    if (have) apply_pair(plo, phi, 0, -1);
   }
   // R (n x n) from my columns: row-major R (sweep) or R^T column-major (SVD)
   for (int blk = 0; blk < nbk && Rout; ++blk) {
@@ -1115,7 +1140,8 @@ void launch_sync_reset(const DevCtx* d, int nshots, hipStream_t s) {
 }
 
 void launch_qrf(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, size_t lds, hipStream_t s) {
-  lds = std::max(lds, (size_t)MPSW_APPLY_LDS * sizeof(double));   // the panel, or the reflector workspace
+  // the panel, or the reflector workspace (all waves, or two halves)
+  lds = std::max(lds, std::max((size_t)MPSW_APPLY_LDS, (size_t)2 * QR_HALF_WSP) * sizeof(double));
   if (bw == 16)
     hipLaunchKernelGGL(k_qrf<16>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
   else if (bw == 8)
