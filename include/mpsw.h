@@ -204,7 +204,7 @@ int mpsw_profile_read(mpsw_state st, int kclass, mpsw_kprof* out);
 /* Autotuner of the launch shapes for this state's bucket (grid, chi cap,
  * shot count, precision): times `steps` steps from the current state for
  * each candidate Jacobi block width (rule, 8, 16, 32 columns) and then each
- * cap on the workgroups per shot of a QR factorisation (32, 16, 8, 4, 2, 1), keeps
+ * cap on the workgroups per shot of a QR factorisation (32, 16, 8, 4, 3, 2, 1), keeps
  * the fastest pair, and restores the state exactly as it was (fields, bonds,
  * step counters).  The chosen values are returned if the pointers are not
  * NULL.  Synchronises.  Errors: EINVAL, ESTATE, ENOMEM, EHIP. */

@@ -1543,7 +1543,7 @@ int mpsw_autotune(mpsw_state st, int steps, int* qr_nwg, int* jac_block_out) {
   // one factor at a time: the Jacobi block width, then the QR workgroups
   for (int b : {0, 8, 16, 32}) trial(32, b);
   const int bb = best_b;
-  for (int q : {16, 8, 4, 2, 1}) trial(q, bb);
+  for (int q : {16, 8, 4, 3, 2, 1}) trial(q, bb);
   st->tune_qr_nwg = best_q;
   st->tune_jac_b = best_b;
   if (ok) ok = restore();
