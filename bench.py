@@ -80,9 +80,26 @@ def read_traffic(kclass, workload, batch, precision):
         return None
 
 
+def log_rank_data(st, steps, chi, shot=0):
+    """Step an exact-rank state `steps` times; for every bond and rounding the
+    network input the library forms for the coming step (its rank features)
+    and, as the label, the rank the exact rule then kept, divided by chi.
+    Returns (X, y) as float32."""
+    K = st.K
+    X, y, feats = [], [], None
+    for _ in range(steps):
+        st.step(1)
+        ranks = [st.bonds(shot, 3), st.bonds(shot, 4), st.bonds(shot, 0)]   # y, w, psi after the step
+        if feats is not None:
+            for j in range(3):
+                X.append(feats[j])
+                y.append(np.asarray(ranks[j][1:K], dtype=np.float64) / chi)
+        feats = [st.rank_features(shot, j) for j in range(3)]
+    return np.concatenate(X).astype(np.float32), np.concatenate(y).astype(np.float32)
+
+
 def train_rank_model(mpsw, synth, steps=80):
     """Rank network trained on spectra of an exact run of the n=8, chi=64 workload."""
-    from paper_2609_01904_amd import rankfeat
     cfg = synth.get_config("C2", steps=steps)
     n, chi = cfg["n"], cfg["chi"]
     st = mpsw.State(mpsw.make_config(n, chi, cfg["eps"], cfg["lam"]))
@@ -90,14 +107,18 @@ def train_rank_model(mpsw, synth, steps=80):
     up, u = synth.wavefront_fields(n, seed=5)
     st.set_fields(0, up, u)
     st.set_source(0, cfg["ix"], cfg["iz"], cfg["wavelet_samples"])
-    X, y = rankfeat.log_run(st, steps, chi)
+    X, y = log_rank_data(st, steps, chi)
     st.close()
-    w0 = rankfeat.init_params(seed=1)
+    w0 = mpsw.mlp_init(seed=1)
     w = mpsw.mlp_train(X, y, w0, epochs=400, lr=2e-3, alpha=4.0)
     return w, len(y)
 
 
-def make_state(mpsw, synth, workload, batch, precision, rank="exact", model=None, ordering="sequential"):
+def make_state(mpsw, synth, workload, batch, precision, rank="exact", model=None, ordering="sequential",
+               velocity=None):
+    """State of `batch` shots of a workload from its developed wavefield.  The
+    c^2 operator is the device's TT-SVD of the dense model, or the given
+    (bonds, cores) of its diagonal in the state's site order."""
     cfg = synth.get_config(workload)
     n = cfg["n"]
     N = 1 << n
@@ -109,7 +130,10 @@ def make_state(mpsw, synth, workload, batch, precision, rank="exact", model=None
                              ordering=order, ndim=nd)
             for _ in range(batch)]
     st = mpsw.State(cfgs if batch > 1 else cfgs[0])
-    st.set_velocity_dense(cfg["c2"], cfg["eps_c"])
+    if velocity is None:
+        st.set_velocity_dense(cfg["c2"], cfg["eps_c"])
+    else:
+        st.set_velocity_mpo(*velocity)
     if model is not None:
         st.set_rank_model(model)
     fields = []
@@ -191,10 +215,11 @@ def copy_calibration(torch):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}))
 
 
-def make_mixed_states(mpsw, synth, precision, steps, nshots=64):
+def make_mixed_states(mpsw, synth, precision, steps, nshots=64, velocity=None):
     """States of the batched-shots workload: the seeded shot list (grids n in
     {8, 9, 10}, chi caps in {32, 64, 128}, Ricker sources), one state per grid
-    holding its shots with the layered model of that grid.  Returns (states,
+    holding its shots with the layered model of that grid (c^2 operator from
+    the device's TT-SVD, or velocity[n] = (bonds, cores)).  Returns (states,
     {n: shots of that state in order}, all shots)."""
     shots = synth.batch_shots(nshots, seed=1, steps=steps)
     prec = {"fp64": mpsw.MPSW_FP64, "fp32": mpsw.MPSW_FP32, "bf16": mpsw.MPSW_BF16}[precision]
@@ -205,7 +230,10 @@ def make_mixed_states(mpsw, synth, precision, steps, nshots=64):
         cfg = synth.get_config("C3", n=n)
         lam = mine[0]["dt"] / mine[0]["dh"]
         st = mpsw.State([mpsw.make_config(n, sh["chi"], sh["eps"], lam, precision=prec) for sh in mine])
-        st.set_velocity_dense(cfg["c2"], cfg["eps_c"])
+        if velocity is None:
+            st.set_velocity_dense(cfg["c2"], cfg["eps_c"])
+        else:
+            st.set_velocity_mpo(*velocity[n])
         for i, sh in enumerate(mine):
             st.set_source(i, sh["ix"], sh["iz"], sh["wavelet_samples"])
         states.append(st)
@@ -278,7 +306,10 @@ def precision_trajectory(mpsw, synth, torch, args):
     states = []
     for _, p in precs:
         st = mpsw.State(mpsw.make_config(n, cfg["chi"], cfg["eps"], cfg["lam"], precision=p))
-        st.set_velocity_dense(cfg["c2"], cfg["eps_c"])
+        if args.velocity_cores:
+            st.set_velocity_mpo(*load_velocity_cores(args.velocity_cores))
+        else:
+            st.set_velocity_dense(cfg["c2"], cfg["eps_c"])
         st.set_source(0, cfg["ix"], cfg["iz"], cfg["wavelet_samples"])
         states.append(st)
     grp = mpsw.Group(states)
@@ -300,13 +331,86 @@ def precision_trajectory(mpsw, synth, torch, args):
         for (name, _), v in zip(precs[1:], u[1:]):
             row[f"rel_l2_{name}_vs_fp64"] = float(np.linalg.norm(v - u[0])) / nb if nb > 0 else 0.0
         rows.append(row)
-        if args.save:
+        if args.save:   # FP64 fields in FP64; the others in FP32, enough for their distances
             np.save(os.path.join(args.save, f"gpu_fp64_u{mark}.npy"), u[0])
+            for (name, _), v in zip(precs[1:], u[1:]):
+                np.save(os.path.join(args.save, f"gpu_{name}_u{mark}.npy"), v.astype(np.float32))
     print(json.dumps({"workload": args.workload, "trajectory": rows,
                       "seconds": time.perf_counter() - t0}), flush=True)
     grp.close()
     for st in states:
         st.close()
+
+
+def load_velocity_cores(path):
+    """(bonds, cores) of a c^2 operator saved with numpy.savez(path, bonds=..., cores=<flat>)."""
+    with np.load(path) as z:
+        bonds = [int(b) for b in z["bonds"]]
+        flat = np.asarray(z["cores"], dtype=np.float64)
+    cores, o = [], 0
+    for k in range(len(bonds) - 1):
+        sz = bonds[k] * 2 * bonds[k + 1]
+        cores.append(flat[o:o + sz].reshape(bonds[k], 2, bonds[k + 1]))
+        o += sz
+    return bonds, cores
+
+
+def accuracy_summary():
+    """Relative L2 against the FP64 oracle at the checkpoints of the long
+    precision trajectory (a committed measurement summary), or None."""
+    path = os.path.join(ROOT, "profiles", "trajectory_C3.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def run_form(mpsw, synth, torch, args, batch, precision, rank, model=None, velocity=None, tune=None, kclass=None):
+    """Build a state of `batch` shots, tune it (or take `tune`), warm up, time
+    args.steps steps.  With kclass (-1: the class with the most event time in
+    one untimed probe step) the launches of that kernel class are timed with
+    HIP events on the state's stream during the timed steps.  Returns (state,
+    cfg, fields, result, kernel class, its profile)."""
+    t0 = time.perf_counter()
+    st, cfg, fields = make_state(mpsw, synth, args.workload, batch, precision, rank, model, args.ordering, velocity)
+    tuned = tune
+    if tune is not None:
+        st.set_launch_shapes(*tune)
+    elif not args.no_tune:
+        tuned = st.autotune(2)
+    st.step(max(args.warmup, 0))
+    torch.cuda.synchronize()
+    prof = None
+    if kclass is not None and kclass < 0:   # the class with the most event time over one probe step (untimed)
+        best = None
+        for c in range(5):
+            st.profile(c)
+            st.step(1)
+            p = st.profile_read(c)
+            log(f"probe class {mpsw.KC_NAMES[c]}: {p['total_ms']:.2f} ms in {p['launches']} launches")
+            if best is None or p["total_ms"] > best[1]:
+                best = (c, p["total_ms"])
+        kclass = best[0]
+    if kclass is not None:
+        st.profile(kclass)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st.step(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    if kclass is not None:
+        prof = st.profile_read(kclass)
+    stats = [st.stats(b) for b in range(batch)]
+    res = {"value": batch * args.steps / el, "unit": "shot-steps/s",
+           "per_shot_steps_per_s": args.steps / el, "ms_per_step": el * 1e3 / args.steps,
+           "shots": batch, "precision": precision,
+           "rank": "exact SVD" if rank == "exact" else "learned rank + range finder, exact fallback",
+           "tuned": None if tuned is None else {"qr_workgroups_per_shot": tuned[0], "jacobi_block": tuned[1] or "rule"},
+           "sketches": int(sum(x["sketches"] for x in stats)), "fallbacks": int(sum(x["fallbacks"] for x in stats)),
+           "setup_s": t1 - t0}
+    log(f"form {precision}/{rank}/{batch} shots: {res['value']:.1f} shot-steps/s "
+        f"({res['ms_per_step']:.1f} ms per step; sketches {res['sketches']}, fallbacks {res['fallbacks']})")
+    return st, cfg, fields, res, kclass, prof
 
 
 def main():
@@ -340,6 +444,12 @@ def main():
     ap.add_argument("--save", default=None, help="directory for the trajectory's FP64 fields (.npy)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (byte-counter calibration)")
+    ap.add_argument("--velocity-cores", default=None, metavar="NPZ",
+                    help="c^2 operator as saved cores (bonds, flat cores) instead of the device's TT-SVD of the model")
+    ap.add_argument("--forms", default="fp32,learned",
+                    help="comma-separated extra forms timed beside the headline one on the same workload and "
+                         "batch: fp32, bf16 (contraction precision), learned (rank network + range finder), "
+                         "chosen (all of fp32 + learned); empty for none")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -367,56 +477,30 @@ def main():
         mixed_batch(mpsw, synth, torch, args)
         return
 
-    t_setup = time.perf_counter()
+    velocity = load_velocity_cores(args.velocity_cores) if args.velocity_cores else None
     model = None
-    if args.rank == "learned":
-        model, nrows = train_rank_model(mpsw, synth)
-        log(f"rank network trained on {nrows} logged bonds in {time.perf_counter() - t_setup:.1f} s")
-    st, cfg, fields = make_state(mpsw, synth, args.workload, args.batch, args.precision, args.rank, model,
-                                 args.ordering)
-    torch.cuda.synchronize()
-    free, total = torch.cuda.mem_get_info()
-    log(f"setup {time.perf_counter() - t_setup:.1f} s; bonds {st.bonds(0, 0)}; c^2 bonds {st.bonds(0, 2)}; "
-        f"device memory in use {(total - free) / 2**30:.1f} of {total / 2**30:.0f} GiB")
-
-    tuned = None
-    if not args.no_tune:   # launch shapes for this bucket, the state is restored afterwards
+    if args.rank == "learned" or any(f in ("learned", "chosen") for f in args.forms.split(",")):
         t0 = time.perf_counter()
-        tuned = st.autotune(2)
-        log(f"autotune: QR workgroups per shot <= {tuned[0]}, Jacobi block {tuned[1] or 'rule'} "
-            f"({time.perf_counter() - t0:.1f} s)")
-    if args.graph:
+        model, nrows = train_rank_model(mpsw, synth)
+        log(f"rank network trained on {nrows} logged bonds in {time.perf_counter() - t0:.1f} s")
+    st, cfg, fields, head, kclass, prof = run_form(mpsw, synth, torch, args, args.batch, args.precision, args.rank,
+                                                   model if args.rank == "learned" else None, velocity,
+                                                   kclass=args.kernel_class)
+    el_prof = head["ms_per_step"] * args.steps * 1e-3
+    free, total = torch.cuda.mem_get_info()
+    log(f"bonds {st.bonds(0, 0)}; c^2 bonds {st.bonds(0, 2)}; "
+        f"device memory in use {(total - free) / 2**30:.1f} of {total / 2**30:.0f} GiB")
+    if args.graph:   # events cannot sit inside graphs: the eager timed region above carries the roofline
         st.set_graph_mode(True)
-    st.step(max(args.warmup, 3 if args.graph else 0))
-    torch.cuda.synchronize()
-    kclass = args.kernel_class
-    if kclass < 0:   # the class with the most event time over one probe step (untimed)
-        best = None
-        for c in range(5):
-            st.profile(c)
-            st.step(1)
-            p = st.profile_read(c)
-            log(f"probe class {mpsw.KC_NAMES[c]}: {p['total_ms']:.2f} ms in {p['launches']} launches")
-            if best is None or p["total_ms"] > best[1]:
-                best = (c, p["total_ms"])
-        kclass = best[0]
-    st.profile(kclass)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st.step(args.steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    if args.graph:   # events cannot sit inside the graphs: time the kernel over eager steps
-        st.set_graph_mode(False)
-        st.profile(kclass)
+        st.step(3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         st.step(args.steps)
-    prof = st.profile_read(kclass)
-    stats = [st.stats(b) for b in range(args.batch)]
-    log(f"timed {args.steps} steps x {args.batch} shots in {el:.3f} s; bonds {stats[0]['bonds']}; "
-        f"max Jacobi sweeps {stats[0]['max_jacobi_sweeps']}; sketches {sum(s['sketches'] for s in stats)} "
-        f"fallbacks {sum(s['fallbacks'] for s in stats)}")
-
-    value = args.batch * args.steps / el
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        head.update(value=args.batch * args.steps / el, per_shot_steps_per_s=args.steps / el,
+                    ms_per_step=el * 1e3 / args.steps)
+        st.set_graph_mode(False)
     avg_ms = prof["total_ms"] / max(prof["launches"], 1)
     flops_per_launch = prof["alg_flops"] / max(prof["launches"], 1)
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
@@ -432,54 +516,43 @@ def main():
                 "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": traffic, "kernel": KERNEL_NAMES[kclass], "launches": prof["launches"],
                 "avg_launch_ms": avg_ms, "alg_flops_per_launch": flops_per_launch,
-                "share_of_step_time": prof["total_ms"] / (el * 1e3)}
+                "share_of_step_time": prof["total_ms"] / (el_prof * 1e3)}
     out = {
         "metric": "MPS FDTD steps/sec at n=10, chi=128 (chosen vs plain FP64) at stated rel-L2 err",
-        "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "value": head["value"], "unit": "shot-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: n={cfg['n']} ({'x'.join([str(1 << cfg['n'])] * cfg['ndim'])}), chi_max={cfg['chi']}, "
                                f"eps={cfg['eps']}, layered-fault c^2 (cutoff {cfg['eps_c']}), "
                                f"start from a developed wavefield at the chi cap",
                    "shots": args.batch, "precision": args.precision, "site_order": args.ordering,
-                   "rank": "exact SVD" if args.rank == "exact" else "learned rank + range finder, exact fallback",
-                   "graph": bool(args.graph),
-                   "tuned": None if tuned is None else {"qr_workgroups_per_shot": tuned[0],
-                                                         "jacobi_block": tuned[1] or "rule"}},
+                   "rank": head["rank"], "graph": bool(args.graph), "tuned": head["tuned"]},
+        "per_shot_steps_per_s": head["per_shot_steps_per_s"],
         "roofline": roofline,
     }
+    st.close()
+    forms = {}
+    for f in [x for x in args.forms.split(",") if x]:
+        prec = {"fp32": "fp32", "bf16": "bf16", "chosen": "fp32"}.get(f, args.precision)
+        rank = "learned" if f in ("learned", "chosen") else args.rank
+        fs, _, _, res, _, _ = run_form(mpsw, synth, torch, args, args.batch, prec, rank,
+                                       model if rank == "learned" else None, velocity)
+        fs.close()
+        forms[f] = res
+    if forms:
+        out["forms"] = forms
     if not args.no_plain:
-        # plain form: one shot, FP64 contractions, exact SVD, from shot 0's start,
-        # the same number of steps; its last `steps` steps are timed
-        total = int(stats[0]["step"])
-        u_form = st.to_dense(0, 0)
-        pl, _, _ = make_state(mpsw, synth, args.workload, 1, "fp64", ordering=args.ordering)
-        up, u, src = fields[0]
-        pl.set_fields(0, up, u)
-        if len(src) == 3:
-            pl.set_source_3d(0, *src, cfg["wavelet_samples"])
-        else:
-            pl.set_source(0, *src, cfg["wavelet_samples"])
-        if not args.no_tune:
-            pl.autotune(2)
-        pl.step(total - args.steps)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        pl.step(args.steps)
-        torch.cuda.synchronize()
-        pel = time.perf_counter() - t0
-        u_ref = pl.to_dense(0, 0)
+        # plain form: one shot, FP64 contractions, exact SVD, from shot 0's start
+        pl, _, _, res, _, _ = run_form(mpsw, synth, torch, args, 1, "fp64", "exact", None, velocity)
         pl.close()
-        err = float(np.linalg.norm(u_form - u_ref) / np.linalg.norm(u_ref))
-        out["plain_fp64"] = {"value": args.steps / pel, "unit": "steps/s", "ms_per_step": pel * 1e3 / args.steps,
-                             "shots": 1, "precision": "fp64", "rank": "exact SVD"}
-        out["rel_l2_vs_fp64"] = {"value": err, "steps": total,
-                                 "what": "shot 0 of this run vs the plain single-shot FP64 run after the same steps"}
-        log(f"plain FP64 single shot: {args.steps / pel:.2f} steps/s; rel-L2 of shot 0 vs it {err:.2e}")
+        out["plain_fp64"] = res
+        out["speedup_vs_plain"] = head["value"] / res["value"]
+    acc = accuracy_summary()
+    if acc is not None:
+        out["rel_l2_vs_fp64_oracle"] = acc
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(synth, args.workload, fields, args.cpu_seconds, args.ordering)
-    st.close()
     print(json.dumps(out), flush=True)
 
 

@@ -96,16 +96,39 @@ typedef struct mpsw_stats {
   int64_t sketches;        /* learned-rank mode: bonds sketched by the randomized range finder */
 } mpsw_stats;
 
-/* Create a state for one shot with psi^0 = psi^{-1} = 0 (bond 1).
- * hip_stream: a hipStream_t or NULL.  Allocates the device workspace for the
- * worst-case bonds of this (n, chi_max).  *out receives the handle (owned by the
- * caller, released with mpsw_destroy).  Errors: EINVAL, ENOMEM, EHIP. */
+/* Create a state for one shot: a 2^n x 2^n grid (Sec. 2) held as a K = 2n site
+ * MPS (Sec. 4.1), with psi^0 = psi^{-1} = 0 (bond 1).  lambda is the mesh
+ * ratio dt/dh of eq. 2; eps and chi_max are the cutoff and bond cap of the
+ * compression of Sec. 4.3.  hip_stream: a hipStream_t or NULL.  Allocates the
+ * device workspace for the worst-case bonds of this (n, chi_max) with
+ * hipMalloc.  *out receives the handle (owned by the caller, released with
+ * mpsw_destroy).  Errors: EINVAL, ENOMEM, EHIP. */
 int mpsw_create_state(const mpsw_config* cfg, void* hip_stream, mpsw_state* out);
 
 /* Batch of nshots shots with the same n sharing one c^2 model; shot i uses
  * cfgs[i] (chi_max and eps may differ per shot; n, lambda, precision, boundary,
  * rank mode and site order must agree).  Steps of a batch advance all shots together.  Errors as above. */
 int mpsw_create_batch(const mpsw_config* cfgs, int nshots, void* hip_stream, mpsw_state* out);
+
+/* Device memory supplied by the caller (for instance a framework's caching
+ * allocator): alloc returns device memory of at least `bytes` bytes, aligned
+ * to 256 bytes, on the current device, or NULL when it cannot (the library
+ * then fails with ENOMEM); free gives back a block alloc returned, with the
+ * size it was asked for.  ctx is passed through.  Both are called only from
+ * within the library's entry points on the calling thread, never from device
+ * work; a block is freed only after the state's stream has finished with it. */
+typedef struct mpsw_allocator {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, size_t bytes, void* ctx);
+  void* ctx;
+} mpsw_allocator;
+
+/* mpsw_create_batch whose every device allocation over the state's life
+ * (workspace, MPS arena, c^2 operator, set-up temporaries) goes through
+ * `alloc` (NULL: hipMalloc / hipFree).  The allocator must outlive the state.
+ * Errors: EINVAL (an allocator without both functions), ENOMEM, EHIP. */
+int mpsw_create_batch_ex(const mpsw_config* cfgs, int nshots, void* hip_stream, const mpsw_allocator* alloc,
+                         mpsw_state* out);
 
 /* Set c^2 from its dense field (host, 4^n or 8^n float64, all > 0).  The diagonal
  * c^2 operator is built on the device as the right-to-left truncated TT-SVD of
@@ -121,10 +144,13 @@ int mpsw_set_velocity_dense(mpsw_state st, const double* c2, double eps_c);
  * reconstructed field.  Errors: EINVAL, ECFL, ENOMEM, EHIP. */
 int mpsw_set_velocity_mpo(mpsw_state st, const int* bonds, const double* cores);
 
-/* Point source for shot `shot` at grid point (ix, iz): step j (counted from
- * creation, or from the shot's last mpsw_set_fields) adds wavelet[j] *
- * e_(ix,iz) to psi^{j+1}; steps j >= nt add nothing.  The host array is
- * copied.  Errors: EINVAL (also for a three-dimensional state). */
+/* Point source for shot `shot` at grid point (ix, iz), the source term of the
+ * wave equation (Sec. 2) entering the update sum of eq. 17 as a bond-1
+ * product state (the impulse of the run in Sec. 5 is wavelet = {1, 0, ...}):
+ * step j (counted from creation, or from the shot's last mpsw_set_fields or
+ * mpsw_set_cores) adds wavelet[j] * e_(ix,iz) to psi^{j+1}; steps j >= nt
+ * add nothing.  The host array is copied.  Errors: EINVAL (also for a
+ * three-dimensional state). */
 int mpsw_set_source(mpsw_state st, int shot, int ix, int iz, int nt, const double* wavelet);
 /* The same at grid point (ix, iy, iz) of a three-dimensional state.
  * Errors: EINVAL (also for a two-dimensional state). */
@@ -133,8 +159,28 @@ int mpsw_set_source_3d(mpsw_state st, int shot, int ix, int iy, int iz, int nt, 
 /* Initial fields of shot `shot` from dense host arrays (NULL = zero); each is
  * stored as its right-to-left TT-SVD with the shot's (eps, chi_max).
  * Restarts the shot's step counter (its source clock) at 0 and clears its
- * learned-rank sketch back-offs.  Errors: EINVAL, ENOMEM, EHIP. */
+ * learned-rank sketch back-offs.  Errors: EINVAL (also for a non-finite
+ * value), ENOMEM, EHIP. */
 int mpsw_set_fields(mpsw_state st, int shot, const double* u_prev, const double* u_cur);
+
+/* Checkpoint of shot `shot`: the cores of psi^k (which = 0) or psi^{k-1}
+ * (which = 1) as they are held (Sec. 4.1, eq. 8), into host memory: bonds
+ * receives K+1 ints, cores (if not NULL) the cores packed site after site,
+ * core k row-major of shape (bonds[k], 2, bonds[k+1]), at most `cap`
+ * doubles.  Returns the number of doubles of the cores (>= 0) or a negative
+ * error code.  The shot's step counter is mpsw_stats.step.  Synchronises.
+ * Errors: EINVAL (cap too small), EHIP, ENONFINITE. */
+int mpsw_get_cores(mpsw_state st, int shot, int which, int* bonds, double* cores, int64_t cap);
+
+/* Resume shot `shot` from a checkpoint: psi^{k-1} and psi^k are set to the
+ * given cores exactly (no rounding; same packing as mpsw_get_cores, host
+ * memory borrowed for the call) and the shot's step counter (its source
+ * clock) to `step`.  Every bond must lie in [1, min(chi_cap, 2^k, 2^(K-k))],
+ * chi_cap the largest chi_max of the state.  Stepping on from here repeats,
+ * bit for bit, what the checkpointed state would have done.
+ * Errors: EINVAL, EHIP. */
+int mpsw_set_cores(mpsw_state st, int shot, int64_t step, const int* bonds_prev, const double* cores_prev,
+                   const int* bonds_cur, const double* cores_cur);
 
 /* Enqueue k >= 0 steps of eq. 17 on the state's stream (asynchronous).
  * Errors: ESTATE (no velocity set), EINVAL, EHIP. */
@@ -158,48 +204,26 @@ int mpsw_group_create(const mpsw_state* states, int nstates, void* hip_stream, m
 int mpsw_group_step(mpsw_group g, int k);
 int mpsw_group_destroy(mpsw_group g);
 
-/* Write the dense field of shot `shot` (which = 0: u^k, 1: u^{k-1}) into the
- * caller's buffer of 4^n (8^n) float64 (host memory, or device memory if
- * out_is_device != 0).  Synchronises the stream; reports ENONFINITE if any
- * entry is not finite.  Errors: EINVAL, EHIP, ENONFINITE. */
+/* Write the dense field of shot `shot` (which = 0: u^k, 1: u^{k-1}; 2: the c^2
+ * operator's diagonal; 3, 4: y and w of the last step) into the caller's
+ * buffer of 4^n (8^n) float64 (host memory, or device memory if
+ * out_is_device != 0): the contraction of the chain of eq. 8 (Sec. 4.1), in
+ * the grid layout of eq. 3.  Synchronises the stream; reports ENONFINITE if
+ * any entry is not finite.  Errors: EINVAL, EHIP, ENONFINITE. */
 int mpsw_to_dense(mpsw_state st, int shot, int which, double* out, int out_is_device);
 
 /* Bonds (K+1 ints) of shot `shot`'s psi^k (which = 0), psi^{k-1} (1) or of
  * the c^2 operator (2).  Synchronises.  Errors: EINVAL, EHIP. */
 int mpsw_get_bonds(mpsw_state st, int shot, int which, int* bonds);
 
-/* Statistics of shot `shot` after the last step.  Synchronises and reports
- * device-side failures of the steps enqueued so far: ENOMEM (a live size
- * exceeded a workspace), ENONFINITE, EHIP (a bounded inter-workgroup wait gave
- * up). */
+/* Statistics of shot `shot` after the last step: the bonds the compression of
+ * Sec. 4.3 kept, and per rounding the largest bond before truncation and the
+ * discarded sum of squared singular values (the truncation error of the
+ * rule "discard sigma_i < eps sigma_max, cap at chi_max", summed in FP64 over
+ * the bonds).  Synchronises and reports device-side failures of the steps
+ * enqueued so far: ENOMEM (a live size exceeded a workspace), ENONFINITE,
+ * EHIP (a bounded inter-workgroup wait gave up). */
 int mpsw_get_stats(mpsw_state st, int shot, mpsw_stats* out);
-
-/* Kernel classes of mpsw_profile / mpsw_profile_read. */
-enum {
-  MPSW_KC_QR = 0,      /* Householder QR factorisations (L->R sweep and SVD) */
-  MPSW_KC_JACOBI = 1,  /* one-sided Jacobi sweeps of the SVD */
-  MPSW_KC_GEMM = 2,    /* contractions */
-  MPSW_KC_APPLYQ = 3,  /* Q_{k-1} applied to U Sigma */
-  MPSW_KC_APPLYV = 4,  /* reflectors applied to the right singular vectors */
-  MPSW_KC_COUNT = 5
-};
-
-/* Launch statistics of one kernel class since the last mpsw_profile call. */
-typedef struct {
-  int64_t launches;  /* launches timed with events (0 unless this class is the timed one) */
-  double total_ms;   /* summed event time of those launches */
-  double alg_flops;  /* algorithmic flops of every launch of the class, all shots:
-                        QR 2mn^2 - 2n^3/3 (m x n, m >= n); Jacobi 9c^3 (c x c factor);
-                        GEMM 2MNK; reflector application 4mnr - 2n^2 r */
-} mpsw_kprof;
-
-/* Reset the counters of every class and time each launch of class `kclass`
- * (-1: none) with a pair of events on the state's stream until the next call.
- * Synchronises.  Errors: EINVAL, EHIP. */
-int mpsw_profile(mpsw_state st, int kclass);
-
-/* Read the counters of class `kclass`.  Synchronises.  Errors: EINVAL, EHIP. */
-int mpsw_profile_read(mpsw_state st, int kclass, mpsw_kprof* out);
 
 /* Autotuner of the launch shapes for this state's bucket (grid, chi cap,
  * shot count, precision): times `steps` steps from the current state for
@@ -230,6 +254,16 @@ int mpsw_set_launch_shapes(mpsw_state st, int qr_nwg, int jac_block);
  * stepping a learned-rank state.  Errors: EINVAL, EHIP. */
 int mpsw_rank_model_set(mpsw_state st, const float* w, int nw);
 
+/* Network inputs of bonds 1..K-1 of rounding `rounding` (0: L psi, 1: c^2 y,
+ * 2: the sum) of shot `shot`, exactly as the learned-rank rounding forms them
+ * for the coming step: row k-1 holds log10(sigma_i / sigma_1) for the 32
+ * leading singular values of bond k in the last step (-30 where absent),
+ * k / K and min(step, 10^4) / 1000 (34 floats per row, host memory, (K-1) x 34).
+ * Used to log training data: the label of a row is the rank the rule keeps
+ * at that bond in the coming step.  Synchronises.  Errors: EINVAL, ESTATE
+ * (no velocity set), EHIP. */
+int mpsw_get_rank_features(mpsw_state st, int shot, int rounding, float* feats);
+
 /* The leading 32 singular values (descending, 0 where absent) of every bond
  * of rounding `rounding` (0: L psi, 1: c^2 y, 2: the sum) in the last step of
  * shot `shot`: out[k * 32 + i] for k = 0..K-1 (row k is bond k, the SVD of
@@ -254,30 +288,14 @@ const char* mpsw_last_error(void);
 #define MPSW_MLP_NPARAM 21121
 /* Loss and gradient at w (gradient in the parameter order). */
 int mpsw_mlp_grad(const float* X, const float* y, int m, float alpha, const float* w, float* grad, float* loss);
+/* Initial parameters: He-scaled normal weights (variance 2 / fan-in for the
+ * ReLU layers, 1 / fan-in for the output layer; a 64-bit Mersenne twister
+ * from `seed`), zero biases.  Host only.  Errors: EINVAL. */
+int mpsw_mlp_init(uint64_t seed, float* w);
 /* `epochs` full-batch Adam steps from w (updated in place) at learning rate lr. */
 int mpsw_mlp_train(const float* X, const float* y, int m, int epochs, float lr, float alpha, float* w);
 /* Network outputs for m feature rows. */
 int mpsw_mlp_forward(const float* X, int m, const float* w, float* out);
-
-/* Host-only helper (no device work), used by the CPU tests: the fused
- * Laplacian MPO S_x+ + S_x- + S_z+ + S_z- - 4I (eqs. 6 and 16) the library
- * applies, for n-bit registers, a boundary, a site order (MPSW_SEQUENTIAL or
- * MPSW_INTERLEAVED) and ndim = 2 or 3 registers (three: the six shifts and
- * -6I).  Writes K+1 bonds into
- * `bonds` and, if `cores` is not NULL, the cores packed site after site, core k
- * of shape [w_k][w_{k+1}][s_out][s_in] row-major (at most `cap` doubles).
- * Returns the total number of core entries (>= 0) or a negative error code. */
-int mpsw_debug_laplacian_mpo(int n, int boundary, int ordering, int ndim, int* bonds, double* cores, int64_t cap);
-
-/* Test helper (device work on the current device, default stream): runs the
- * factorisation kernels of a rounding on one host matrix A (m x n row-major).
- * op 0: QR (m even); out1 receives Q (m x q, row-major), out2 R (q x n), where
- *       q = n for a tall A and q = m (Q = I, R = A) otherwise.
- * op 1: SVD without truncation (n even); out1 receives V^T (r x n), out2
- *       U Sigma (m x r), r = min(m, n), columns ordered by decreasing sigma.
- * Buffers are caller-owned host memory of at least m*n and max(m,n)^2 doubles.
- * Returns q (op 0) or r (op 1), or a negative error code. */
-int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, double* out2);
 
 #ifdef __cplusplus
 }

@@ -88,6 +88,42 @@ def choose_rank(s, eps, chi_max):
     return max(1, min(r, chi_max))
 
 
+# Sensitivity windows of a cut.  Two backward-stable FP64 factorisations of
+# the same matrix, or of two matrices that differ by rounding, agree on every
+# sigma_i to about delta = 1e-14 sigma_1.  A cut is flagged when a change of
+# that size could alter what is kept by more than about 1e-11 of the tensor:
+TAU_GAP = 1e-3     # cap cut: kept and first discarded value closer than this, relative to the kept one
+TAU_CUT = 1e-13    # a value this close to the cutoff eps * sigma_1, relative to sigma_1
+
+
+def cut_flags(s, r, eps):
+    """Why the truncation of the descending spectrum s at rank r is not decided
+    with a margin against rounding (Sec. 4.3's rule is discontinuous in sigma):
+    a set of
+
+    'gap'  the cap cuts (more than r values pass the cutoff) and
+           sigma_r - sigma_{r+1} < TAU_GAP sigma_r: the kept subspace turns by
+           about delta / gap under a perturbation delta, which changes the kept
+           part by about sigma_r delta / gap;
+    'cut'  some |sigma_i - eps sigma_1| < TAU_CUT sigma_1: that value can fall
+           on either side of the cutoff, a jump of about eps sigma_1.
+
+    Exactly equal values that the cutoff keeps or drops together are no
+    ambiguity; only a cut between them is.  Empty when the cut is decided with
+    a margin.
+    """
+    s = np.asarray(s, dtype=np.float64)
+    out = set()
+    if s.size == 0 or s[0] <= 0.0:
+        return out
+    capped = r < s.size and (s[r] >= eps * s[0])
+    if capped and s[r - 1] - s[r] < TAU_GAP * s[r - 1]:
+        out.add("gap")
+    if eps > 0.0 and np.any(np.abs(s - eps * s[0]) < TAU_CUT * s[0]):
+        out.add("cut")
+    return out
+
+
 def tt_svd(t, K, eps, chi_max, log=None):
     """Right-to-left truncated TT-SVD of a dense tensor with 2^K entries.
 

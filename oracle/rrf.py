@@ -9,10 +9,13 @@ iteration, applied to the row space of M (m x n):
 so M ~ U S (Q W)^T.  The truncation rule of Sec. 4.3 is applied to S.
 
 Acceptance of the sketch (the exact SVD is taken otherwise), with r the rank
-the rule keeps from S, res2 = ||M||_F^2 - ||B||_F^2 the energy the sketch
-misses and T = sum of S_i^2 for i > r:
+the rule keeps from S, res2 = ||M - B Q^T||_F^2 the energy the sketch misses
+(formed directly: the difference ||M||^2 - ||B||^2 carries rounding noise of
+about 1e-16 ||M||^2, as large as (eps S_1)^2 at eps near 1e-8) and
+T = sum of S_i^2 for i > r:
 
-    r below the cap:  r < l and res2 <= (eps S_1)^2;
+    r below the cap:  r < l and res2 <= (eps S_1)^2 (a Frobenius-norm bound on
+                      the residual, at least as strict as its spectral norm);
     r at the cap:     res2 <= 0.21 T   (kept error T + res2 <= 1.21 T, and the
                       optimal error is at least T since S_i <= sigma_i).
 
@@ -63,12 +66,114 @@ def range_finder(M, Om):
     return Q, B, S, Wt.T
 
 
-def accept(M, B, S, eps, chi):
+def accept(M, Q, B, S, eps, chi):
     """(accepted, r) by the rule above."""
     l = B.shape[1]
     r = choose_rank(S, eps, chi)
-    res2 = max(float(np.sum(M * M) - np.sum(B * B)), 0.0)
+    E = M - B @ Q.T
+    res2 = float(np.sum(E * E))
     tail = float(np.sum(S[r:] ** 2))
     if r >= chi:
         return res2 <= 0.21 * tail, r
     return (r < l and res2 <= (eps * S[0]) ** 2), r
+
+
+# ---------------------------------------------------------------------------
+# The learned-rank rounding, plainly: the compression of Sec. 4.3 (QR sweep,
+# then SVD sweep with the truncation rule) in which the SVD of a bond matrix
+# may be replaced by the sketch above.  Per bond of the SVD sweep:
+#
+#   r_hat = the network's rank from the bond's leading singular values of the
+#           previous step (mlp.features / mlp.forward, read as ceil(out chi));
+#   sketch when the bond has a singular-value log, r_hat < chi, l = r_hat + 8
+#   satisfies l <= 512, 4 l <= 3 min(m, n), l <= m and l <= n, and the bond
+#   is not waiting after a rejected sketch;
+#   accept as in `accept`, else take the exact SVD; after a rejection the bond
+#   waits 1, 2, 4, ..., 64 steps (doubling per further rejection) before its
+#   next sketch, and an accepted sketch resets the wait.
+#
+# m above is the row count of the bond matrix, which depends on how the
+# rounding's input is represented, not only on the tensor: `round` takes the
+# row counts to plan with (the rows a given implementation's QR sweep leaves)
+# and otherwise uses those of the cores it is given.
+# ---------------------------------------------------------------------------
+OVERSAMPLE = 8
+MAX_WIDTH = 512
+
+
+class LearnedRounding:
+    """State of the learned-rank rounding of one shot across steps: the
+    singular-value log each bond's features come from, and the waits."""
+
+    def __init__(self, w, seed, K, rank_of_out=None):
+        from . import mlp
+        self.mlp = mlp
+        self.w = None if w is None else np.asarray(w, dtype=np.float64)
+        self.seed = int(seed)
+        self.K = K
+        # rank from the network output (default: ceil(out chi) clamped to [1, chi])
+        self.rank_of_out = rank_of_out or (lambda o, chi: int(np.clip(np.ceil(o * chi), 1, chi)))
+        self.sig = {}            # (rounding, bond) -> leading 32 singular values of the last step
+        self.skip = {}           # (rounding, bond) -> first step a sketch may run again
+        self.back = {}           # (rounding, bond) -> current wait
+        self.sketches = 0
+        self.fallbacks = 0
+
+    def planned_width(self, rnd, k, m, n, chi, step):
+        """Sketch width l, or 0 when the exact SVD is taken."""
+        lg = self.sig.get((rnd, k))
+        if lg is None or lg[0] <= 0.0 or self.w is None:
+            return 0
+        x = self.mlp.features(lg, k, self.K, step)
+        out, _ = self.mlp.forward(self.w, x[None, :])
+        rhat = self.rank_of_out(float(out[0]), chi)
+        l = rhat + OVERSAMPLE
+        if step < self.skip.get((rnd, k), 0):
+            return 0
+        if rhat < chi and l <= MAX_WIDTH and 4 * l <= 3 * min(m, n) and m >= l and n >= l:
+            return l
+        return 0
+
+    def svd(self, M, eps, chi, rnd, k, step, rows=None):
+        """(core rows V_r^T, U_r Sigma_r, sigma logged, kept rank, discarded energy)."""
+        m, n = M.shape
+        l = self.planned_width(rnd, k, m if rows is None else rows, n, chi, step)
+        if l:
+            self.sketches += 1
+            Q, B, S, W = range_finder(M, omega(self.seed, step, rnd, k, m, l))
+            ok, r = accept(M, Q, B, S, eps, chi)
+            if ok:
+                E = M - B @ Q.T
+                self.back[(rnd, k)] = 0
+                self.sig[(rnd, k)] = S[:32].copy()
+                return (W[:, :r].T @ Q.T), B @ W[:, :r], S, r, float(np.sum(S[r:] ** 2) + np.sum(E * E))
+            self.fallbacks += 1
+            b = min(64, max(1, 2 * self.back.get((rnd, k), 0)))
+            self.back[(rnd, k)] = b
+            self.skip[(rnd, k)] = step + 1 + b
+        U, s, Vt = np.linalg.svd(M, full_matrices=False)
+        r = choose_rank(s, eps, chi)
+        self.sig[(rnd, k)] = s[:32].copy()
+        return Vt[:r], U[:, :r] * s[:r], s, r, float(np.sum(s[r:] ** 2))
+
+    def round(self, cores, eps, chi, step, rnd, log=None, rows=None):
+        """QR sweep, then the SVD sweep with sketched or exact bond SVDs
+        (rows[k]: the row count of bond matrix k to plan with)."""
+        G = [c.copy() for c in cores]
+        K = len(G)
+        for k in range(K - 1):
+            r0, d, r1 = G[k].shape
+            Q, R = np.linalg.qr(G[k].reshape(r0 * d, r1))
+            G[k] = Q.reshape(r0, d, Q.shape[1])
+            G[k + 1] = np.tensordot(R, G[k + 1], axes=(1, 0))
+        tail = 0.0
+        for k in range(K - 1, 0, -1):
+            r0, d, r1 = G[k].shape
+            Vt, US, s, r, t = self.svd(G[k].reshape(r0, d * r1), eps, chi, rnd, k, step,
+                                       None if rows is None else rows[k])
+            tail += t
+            if log is not None:
+                log.append((k, s.copy(), r))
+            G[k] = Vt.reshape(r, d, r1)
+            G[k - 1] = np.tensordot(G[k - 1], US, axes=(2, 0))
+        return G, tail

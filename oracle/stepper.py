@@ -46,9 +46,43 @@ def c2_mps(c2_dense, n, eps_c, ordering="sequential"):
 SCHEDULES = ("three", "seven", "one")
 
 
+def qr_sweep_rows(rin):
+    """Row counts of the bond matrices a left-to-right QR sweep leaves for
+    input bonds rin[0..K]: rt_0 = 1, rt_{k+1} = min(2 rt_k, rin_{k+1})."""
+    rt = [1]
+    for k in range(1, len(rin)):
+        rt.append(min(2 * rt[-1], int(rin[k])))
+    return rt
+
+
+def library_rows(which, n, bonds, c2_bonds, ndim=2):
+    """Row counts of the bond matrices of the library's rounding `which` (0: L psi,
+    1: c^2 y, 2: the sum; sequential site order) from the bonds of its input
+    terms: it applies L as one fused operator (bonds 3 inside the x register,
+    2 at the register boundary, 4 inside the z register) instead of the direct
+    sum of the five terms, and orthogonalises the right half of the c^2
+    product exactly first (bonds at most 2^(K-k) there).  The tensors are the
+    same; only the sizes the learned-rank plan sees differ."""
+    K = ndim * n
+    if which == 0:
+        w = [1] + [3] * (n - 1) + [2] + [4] * (n - 1) + [1]
+        rin = [w[k] * bonds[0][k] for k in range(K + 1)]
+    elif which == 1:
+        rin = [c2_bonds[k] * bonds[0][k] if k < K // 2 else 2 ** (K - k) for k in range(K + 1)]
+    else:
+        rin = [sum(b[k] for b in bonds) if 0 < k < K else 1 for k in range(K + 1)]
+    return qr_sweep_rows(rin)
+
+
 class MPSStepper:
     def __init__(self, n, lam, eps, chi_max, c2_cores, boundary="periodic",
-                 src=None, wavelet=None, ordering="sequential", ndim=2, schedule="three"):
+                 src=None, wavelet=None, ordering="sequential", ndim=2, schedule="three", learned=None,
+                 learned_rows=None):
+        """learned: an oracle.rrf.LearnedRounding to replace bond SVDs by sketches
+        (the learned-rank rounding); None rounds exactly.  learned_rows =
+        "library" plans the sketches with the bond-matrix sizes of the
+        library's representation (library_rows; two dimensions, sequential
+        order), None with those of the cores built here."""
         if schedule not in SCHEDULES:
             raise ValueError(f"schedule must be one of {SCHEDULES}")
         self.schedule = schedule
@@ -63,6 +97,11 @@ class MPSStepper:
         self.psi = M.zero_mps(self.K)
         self.psi_prev = M.zero_mps(self.K)
         self.log = []            # (step, rounding, site, sigma, rank)
+        self.flags = []          # (step, rounding, site, flags) of every flagged cut (mps.cut_flags)
+        self.learned = learned
+        self.learned_rows = learned_rows
+        self._terms = []         # bonds of the terms of the rounding in progress
+        self.tails = {}          # (step, rounding) -> discarded energy of that rounding
 
     def set_fields(self, u_prev, u):
         """Initial fields given densely; stored as their rounded MPS."""
@@ -71,10 +110,23 @@ class MPSStepper:
 
     def _round(self, cores, which):
         log = []
-        out = M.round_mps(cores, self.eps, self.chi, log)
+        if self.learned is not None and which in (0, 1, 2):
+            rows = library_rows(which, self.n, self._terms, M.bonds_of(self.c2), self.ndim) \
+                if self.learned_rows == "library" else None
+            out, tail = self.learned.round(cores, self.eps, self.chi, self.k, which, log, rows)
+            self.tails[(self.k, which)] = tail
+        else:
+            out = M.round_mps(cores, self.eps, self.chi, log)
         for site, s, r in log:
             self.log.append((self.k, which, site, s, r))
+            f = M.cut_flags(s, r, self.eps)
+            if f:
+                self.flags.append((self.k, which, site, f))
         return out
+
+    def tail2(self, step, which):
+        """Discarded sum of sigma^2 over the bonds of one rounding of one step."""
+        return float(sum(np.sum(s[r:] ** 2) for k, w, _, s, r in self.log if k == step and w == which))
 
     def step(self):
         s_k = 0.0
@@ -95,13 +147,16 @@ class MPSStepper:
                 y = self._round(M.direct_sum(shifted + [self.psi],
                                              [1.0] * (2 * self.ndim) + [-2.0 * self.ndim]), 0)
             else:
+                self._terms = [M.bonds_of(self.psi)]
                 y = self._round(M.laplacian_mps(self.psi, self.n, self.boundary, self.ordering, self.ndim), 0)
+            self._terms = [M.bonds_of(y)]
             w = self._round(M.hadamard(self.c2, y), 1)
         terms = [self.psi, self.psi_prev, w]
         coeffs = [2.0, -1.0, self.lam * self.lam]
         if self.src is not None:
             terms.append(M.point_state_nd(self.n, tuple(self.src), self.ordering))
             coeffs.append(s_k)
+        self._terms = [M.bonds_of(t) for t in terms]
         nxt = self._round(M.direct_sum(terms, coeffs), 2)
         self.psi_prev, self.psi = self.psi, nxt
         self.k += 1
@@ -115,7 +170,7 @@ class DenseStepper:
     """Same rounded trajectory as MPSStepper, through dense TT-SVDs."""
 
     def __init__(self, n, lam, eps, chi_max, c2_dense, boundary="periodic",
-                 src=None, wavelet=None, ordering="sequential"):
+                 src=None, wavelet=None, ordering="sequential", keep_log=True):
         c2_dense = np.asarray(c2_dense, dtype=np.float64)
         self.ndim = c2_dense.ndim
         self.n, self.K = n, self.ndim * n
@@ -129,17 +184,32 @@ class DenseStepper:
         self.k = 0
         self.u = np.zeros((self.N,) * self.ndim)
         self.u_prev = np.zeros((self.N,) * self.ndim)
-        self.log = []
+        self.keep_log = keep_log
+        self.log = []            # (step, rounding, site, sigma, rank) when keep_log
         self.ranks = []          # per step: (bonds of y, bonds of w, bonds of psi)
+        self.tail2 = []          # per step: discarded sum of sigma^2 of each rounding
+        self.flags = []          # (step, rounding, site, flags) of every flagged cut (mps.cut_flags)
 
     def _round(self, t, which):
         log = []
         cores = M.tt_svd(M.to_sites(t, self.ordering), self.K, self.eps, self.chi, log)
+        tail = 0.0
         for site, s, r in log:
-            self.log.append((self.k, which, site, s, r))
+            if self.keep_log:
+                self.log.append((self.k, which, site, s, r))
+            tail += float(np.sum(s[r:] ** 2))
+            f = M.cut_flags(s, r, self.eps)
+            if f:
+                self.flags.append((self.k, which, site, f))
+        self._tail[which] = tail
         return M.from_sites(M.to_dense(cores), self.n, self.ordering, self.ndim), M.bonds_of(cores)
 
+    def first_flag(self):
+        """Step index of the first flagged cut (None if none so far)."""
+        return self.flags[0][0] if self.flags else None
+
     def set_fields(self, u_prev, u):
+        self._tail = {}
         self.u_prev, _ = self._round(np.asarray(u_prev, dtype=np.float64), -1)
         self.u, _ = self._round(np.asarray(u, dtype=np.float64), -1)
 
@@ -147,6 +217,7 @@ class DenseStepper:
         s_k = 0.0
         if self.wavelet is not None and self.k < len(self.wavelet):
             s_k = float(self.wavelet[self.k])
+        self._tail = {}
         y, by = self._round(F.laplacian(self.u, self.boundary), 0)
         w, bw = self._round(self.c2 * y, 1)
         t = 2.0 * self.u - self.u_prev + (self.lam * self.lam) * w
@@ -154,6 +225,7 @@ class DenseStepper:
             t[tuple(self.src)] += s_k
         nxt, bp = self._round(t, 2)
         self.ranks.append((by, bw, bp))
+        self.tail2.append((self._tail[0], self._tail[1], self._tail[2]))
         self.u_prev, self.u = self.u, nxt
         self.k += 1
 

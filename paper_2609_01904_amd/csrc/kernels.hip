@@ -169,6 +169,15 @@ __device__ bool plan_gemm(const DevCtx& c, const OpArgs& a, int shot, int z, int
       if ((int64_t)r * l > c.cap_mps[a.slot][k] || (int64_t)nn * l > L.cap_Ys) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
       break;
     }
+    case G_RRF_RES: {  // Rz (rt x 2 rho) = B (rt x l) Q^T; B = M Q is in Zs, Q (2 rho x l) in Ys
+      const int m = dm[DL::rt + k], nn = 2 * dm[DL::rho + k + 1], l = dm[DL::rrf_l];
+      d.M = m; d.K = l; d.N = nn;
+      d.A = E + L.off_Zs; d.ars = l; d.acs = 1;
+      d.B = E + L.off_Ys; d.brs = 1; d.bcs = l;
+      d.C = E + L.off_Rz; d.crs = nn; d.capC = L.cap_Rz;
+      if ((int64_t)m * l > L.cap_Zs || (int64_t)nn * l > L.cap_Ys) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+      break;
+    }
     case G_DENSE: {  // V_{k+1} (2^k x 2 r_{k+1}) = V_k (2^k x r_k) * G_k (r_k x 2 r_{k+1})
       int r0, r1;
       const double* G;

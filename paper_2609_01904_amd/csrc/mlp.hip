@@ -12,9 +12,12 @@
 // (thread j = hidden unit j); each chunk writes its own partial gradient and
 // a reduction sums the chunks in a fixed order, so gradients are reproducible.
 #include "mpsw_device.h"
-#include "../../include/mpsw.h"
+#include "../../include/mpsw_debug.h"
 
+#include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -248,6 +251,22 @@ int mpsw_mlp_grad(const float* X, const float* y, int m, float alpha, const floa
 int mpsw_mlp_train(const float* X, const float* y, int m, int epochs, float lr, float alpha, float* w) {
   if (epochs < 0 || !(lr > 0.0f)) return mlp_fail(MPSW_EINVAL, "epochs must be >= 0 and lr > 0");
   return run_mlp(X, y, m, alpha, w, epochs, lr, nullptr, nullptr, nullptr);
+}
+
+int mpsw_mlp_init(uint64_t seed, float* w) {
+  // He-scaled normal weights (variance 2 / fan-in for the ReLU layers, 1 / fan-in
+  // for the output), zero biases, in the parameter order of the header
+  if (!w) return mlp_fail(MPSW_EINVAL, "null argument");
+  std::mt19937_64 gen(seed);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  auto fill = [&](int off, int count, double sd) {
+    for (int i = 0; i < count; ++i) w[off + i] = (float)(sd * nd(gen));
+  };
+  std::fill(w, w + MLP_NPARAM, 0.0f);
+  fill(OFF_W1, MLP_NIN * MLP_NH, std::sqrt(2.0 / MLP_NIN));
+  fill(OFF_W2, MLP_NH * MLP_NH, std::sqrt(2.0 / MLP_NH));
+  fill(OFF_W3, MLP_NH, std::sqrt(1.0 / MLP_NH));
+  return MPSW_OK;
 }
 
 int mpsw_mlp_forward(const float* X, int m, const float* w, float* out) {

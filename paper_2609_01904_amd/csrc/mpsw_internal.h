@@ -11,7 +11,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/mpsw.h"
+#include "../../include/mpsw_debug.h"
 
 #define MPSW_MAXK 24          // K = ndim n <= 22 is what the LDS allows
 #define MPSW_NSLOT 5          // MPS buffers: 0..2 psi rotation, 3 = y, 4 = w
@@ -77,8 +77,8 @@ struct ShotRealLayout {
   static constexpr int tail2 = 1;     // [3]
   static constexpr int sigma_log = 4; // [3][MAXK][32]: leading singular values of the last step
   static constexpr int alg_flops = sigma_log + 3 * MPSW_MAXK * 32;  // [MPSW_KC_COUNT] per kernel class
-  static constexpr int mnorm2 = alg_flops + 8;   // ||M||_F^2 of the sketched bond matrix
-  static constexpr int rrf_tail = mnorm2 + 1;    // sum of the discarded sketched sigma^2
+  static constexpr int rrf_res2 = alg_flops + 8; // ||M - B Q^T||_F^2: what the sketch of the bond matrix misses
+  static constexpr int rrf_tail = rrf_res2 + 1;  // sum of the discarded sketched sigma^2
   static constexpr int rrf_sig1 = rrf_tail + 1;  // largest sketched sigma
   static constexpr int rrf_sum2 = rrf_sig1 + 1;  // sum of all sketched sigma^2 (= ||M Q||_F^2)
   static constexpr int size = rrf_sum2 + 1;
@@ -111,6 +111,7 @@ struct EngineLayout {
   int64_t off_Mb, cap_Mb;   // copy of the bond matrix while its sketch is judged
   int64_t off_G, cap_G;     // l x l Gram matrix / Cholesky factor
   int64_t off_Tc, cap_Tc;   // core = W_r^T Q^T before it replaces the slot
+  int64_t off_Rz, cap_Rz;   // B Q^T, the sketch's reconstruction of M (residual check)
   int64_t off_qrT, cap_qrT; // Householder tau
   int64_t stride;           // doubles per shot for this engine
   int maxdim;               // largest matrix side any factorization sees

@@ -17,7 +17,8 @@ enum GemmOp {
   G_US,                // U_r Sigma_r = M_k V_r
   G_RRF_Y,             // Y = M^T Omega (aux 0) or Y = M^T Z (aux 1): row-space sketch
   G_RRF_Z,             // Z = M Q: column-space iterate (aux 0) or B = M Q (aux 1)
-  G_RRF_CORE           // Tc = core_small Q^T (r x l times l x 2 rho)
+  G_RRF_CORE,          // Tc = core_small Q^T (r x l times l x 2 rho)
+  G_RRF_RES            // Rz = B Q^T (rt x l times l x 2 rho): the sketch's reconstruction of M
 };
 
 // Gates of the SVD-stage launches (OpArgs.gate) in the learned-rank rounding.
@@ -64,6 +65,11 @@ void launch_rrf_plan(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s
 void launch_gauss(const DevCtx* d, const OpArgs& a, int64_t cap, int nshots, hipStream_t s);
 void launch_rrf_swap(const DevCtx* d, const OpArgs& a, int64_t cap, int nshots, hipStream_t s);
 void launch_rrf_accept(const DevCtx* d, const OpArgs& a, int64_t cap, int nshots, hipStream_t s);
+void launch_rrf_resid(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
+void launch_sketch_normals(unsigned long long seed, int step, int rnd, int site, int rows, int cols, double* out,
+                           hipStream_t s);
+void launch_rank_export(const DevCtx* d, int shot, int rnd, int K, float* feats, float* outs, int* rhat,
+                        hipStream_t s);
 void launch_rrf_core(const DevCtx* d, const OpArgs& a, int64_t cap, int nshots, hipStream_t s);
 void launch_finish(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s);
 void launch_dense_init(const DevCtx* d, int nshots, hipStream_t s);

@@ -13,9 +13,10 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
-#include "../../include/mpsw.h"
+#include "../../include/mpsw_debug.h"
 #include "mpsw_kernels.h"
 
 using namespace mpsw;
@@ -340,6 +341,7 @@ void layout_engine(const Plan& p, EngineLayout& L) {
     L.cap_Zs = mrt * p.rrf_l; add64(off, L.off_Zs, L.cap_Zs);
     L.cap_Mb = capM; add64(off, L.off_Mb, capM);
     L.cap_Tc = mchi * m2r; add64(off, L.off_Tc, L.cap_Tc);
+    L.cap_Rz = capM; add64(off, L.off_Rz, capM);
   }
   L.stride = off;
   L.maxdim = maxdim;
@@ -408,11 +410,44 @@ struct mpsw_state_s {
   int engine_gen = 0;                  // bumped whenever the step engine is rebuilt
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+  // device memory: the caller's allocator (torch's caching allocator, an
+  // arena) when one was given at creation, else hipMalloc / hipFree
+  mpsw_allocator alloc{};
+  bool has_alloc = false;
+  std::unordered_map<void*, size_t> alloc_sizes;
   // event timing of one kernel class (mpsw_profile)
   int prof_cls = -1;
   std::vector<hipEvent_t> prof_ev;
   size_t prof_used = 0;
 };
+
+// Device allocations of a state go through the caller's allocator if it gave one.
+template <class T>
+hipError_t st_malloc(mpsw_state st, T** p, size_t bytes) {
+  *p = nullptr;
+  if (st == nullptr || !st->has_alloc) return hipMalloc((void**)p, bytes);
+  void* q = st->alloc.alloc(std::max<size_t>(bytes, 1), st->alloc.ctx);
+  if (q == nullptr) return hipErrorOutOfMemory;
+  st->alloc_sizes[q] = bytes;
+  *p = (T*)q;
+  return hipSuccess;
+}
+
+void st_free(mpsw_state st, void* p) {
+  if (p == nullptr) return;
+  if (st == nullptr || !st->has_alloc) {
+    hipFree(p);
+    return;
+  }
+  // the caller may hand the block to other work at once: nothing of this
+  // state's may still be using it
+  if (st->stream) hipStreamSynchronize(st->stream);
+  else hipDeviceSynchronize();
+  auto it = st->alloc_sizes.find(p);
+  const size_t bytes = (it != st->alloc_sizes.end()) ? it->second : 0;
+  if (it != st->alloc_sizes.end()) st->alloc_sizes.erase(it);
+  st->alloc.free(p, bytes, st->alloc.ctx);
+}
 
 static void drop_graphs(mpsw_state st) {
   for (int i = 0; i < 3; ++i)
@@ -502,8 +537,8 @@ void fill_ctx(mpsw_state st, DevCtx& h, double* eng, const EngineLayout& L) {
   h.rrf_over = MPSW_RRF_OVER;
 }
 
-int upload_ctx(Engine& e, hipStream_t s) {
-  if (!e.d) HIP_TRY(hipMalloc(&e.d, sizeof(DevCtx)));
+int upload_ctx(Engine& e, hipStream_t s, mpsw_state st = nullptr) {
+  if (!e.d) HIP_TRY(st_malloc(st, &e.d, sizeof(DevCtx)));
   HIP_TRY(hipMemcpyAsync(e.d, &e.h, sizeof(DevCtx), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
   return MPSW_OK;
@@ -730,6 +765,12 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
       prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, s.rt[k], lcap, 1, nshots, strm); });
       launch_rrf_swap(d, r, s.rt[k] * n2cap, nshots, strm);
       svd_stage(GATE_SKETCH, lcap);
+      // the residual M - B Q^T in FP64 whatever the contraction precision
+      g.op = G_RRF_RES;
+      g.mode = GEMM_FP64;
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, s.rt[k], n2cap, 1, nshots, strm); });
+      g.mode = gmode;
+      launch_rrf_resid(d, r, nshots, strm);
       launch_rrf_accept(d, r, s.rt[k] * n2cap, nshots, strm);
       svd_stage(GATE_EXACT, n2cap);
       g.op = G_RRF_CORE;
@@ -791,15 +832,17 @@ int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t ch
   int* dims = nullptr;
   int rc = MPSW_OK;
   auto cleanup = [&]() {
-    hipFree(eng);
-    hipFree(mps);
-    hipFree(dense);
-    hipFree(reals);
-    hipFree(dims);
+    st_free(st, eng);
+    st_free(st, mps);
+    st_free(st, dense);
+    st_free(st, reals);
+    st_free(st, dims);
   };
-  if (hipMalloc(&eng, L.stride * sizeof(double)) != hipSuccess || hipMalloc(&mps, mps_stride * sizeof(double)) != hipSuccess ||
-      hipMalloc(&dense, 2 * N * sizeof(double)) != hipSuccess || hipMalloc(&reals, RL::size * sizeof(double)) != hipSuccess ||
-      hipMalloc(&dims, DL::size * sizeof(int)) != hipSuccess) {
+  if (st_malloc(st, &eng, L.stride * sizeof(double)) != hipSuccess ||
+      st_malloc(st, &mps, mps_stride * sizeof(double)) != hipSuccess ||
+      st_malloc(st, &dense, 2 * N * sizeof(double)) != hipSuccess ||
+      st_malloc(st, &reals, RL::size * sizeof(double)) != hipSuccess ||
+      st_malloc(st, &dims, DL::size * sizeof(int)) != hipSuccess) {
     cleanup();
     return fail(MPSW_ENOMEM, "dense_to_mps: device allocation failed");
   }
@@ -840,20 +883,20 @@ int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t ch
     cleanup();
     return fail(MPSW_EHIP, "dense_to_mps: upload failed");
   }
-  if ((rc = upload_ctx(e, s0)) != MPSW_OK) { cleanup(); return rc; }
-  if ((rc = check_fits(s, K)) != MPSW_OK) { cleanup(); hipFree(e.d); return rc; }
+  if ((rc = upload_ctx(e, s0, st)) != MPSW_OK) { cleanup(); return rc; }
+  if ((rc = check_fits(s, K)) != MPSW_OK) { cleanup(); st_free(st, e.d); return rc; }
   // swap in the temporary engine: run_rounding uses st only for K/n/c2b/Rmax
   run_rounding(st, e, K_DENSE, s, 0, -1, 0, 0, 0, 1, s0);
   {
     const hipError_t le = hipGetLastError();
     if (le != hipSuccess) {
       cleanup();
-      hipFree(e.d);
+      st_free(st, e.d);
       return fail(MPSW_EHIP, std::string("dense_to_mps: launch failed: ") + hipGetErrorString(le) +
                                  " (LDS limit " + std::to_string(lds_limit()) + ")");
     }
   }
-  if ((rc = check_dev_err(st)) != MPSW_OK) { cleanup(); hipFree(e.d); return rc; }
+  if ((rc = check_dev_err(st)) != MPSW_OK) { cleanup(); st_free(st, e.d); return rc; }
   // bonds of the result
   std::vector<int> dd(DL::size);
   hipMemcpy(dd.data(), dims, DL::size * sizeof(int), hipMemcpyDeviceToHost);
@@ -862,9 +905,9 @@ int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t ch
   if (to_velocity) {
     int64_t tot = 0;
     for (int k = 0; k < K; ++k) tot += (int64_t)bonds[k] * 2 * bonds[k + 1];
-    hipFree(st->c2);
+    st_free(st, st->c2);
     st->c2 = nullptr;
-    if (hipMalloc(&st->c2, tot * sizeof(double)) != hipSuccess) { cleanup(); hipFree(e.d); return fail(MPSW_ENOMEM, "c2 alloc"); }
+    if (st_malloc(st, &st->c2, tot * sizeof(double)) != hipSuccess) { cleanup(); st_free(st, e.d); return fail(MPSW_ENOMEM, "c2 alloc"); }
     int64_t o = 0;
     for (int k = 0; k < K; ++k) {
       const int64_t sz = (int64_t)bonds[k] * 2 * bonds[k + 1];
@@ -875,7 +918,7 @@ int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t ch
   } else {
     for (int k = 0; k < K; ++k) {
       const int64_t sz = (int64_t)bonds[k] * 2 * bonds[k + 1];
-      if (sz > st->cap_mps[out_slot][k]) { cleanup(); hipFree(e.d); return fail(MPSW_ENOMEM, "field rank exceeds chi_max caps"); }
+      if (sz > st->cap_mps[out_slot][k]) { cleanup(); st_free(st, e.d); return fail(MPSW_ENOMEM, "field rank exceeds chi_max caps"); }
       hipMemcpyAsync(st->mps + shot * st->mps_stride + st->off_mps[out_slot][k], mps + offs[k], sz * sizeof(double),
                      hipMemcpyDeviceToDevice, s0);
     }
@@ -885,7 +928,7 @@ int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t ch
   }
   hipStreamSynchronize(s0);
   cleanup();
-  hipFree(e.d);
+  st_free(st, e.d);
   return MPSW_OK;
 }
 
@@ -895,7 +938,7 @@ int build_step_engine(mpsw_state st) {
   ++st->engine_gen;
   const int K = st->K, n = st->half;
   Engine& e = st->eng;
-  if (e.eng) { hipFree(e.eng); e.eng = nullptr; }
+  if (e.eng) { st_free(st, e.eng); e.eng = nullptr; }
   const auto& R = st->Rmax;
   std::vector<int64_t> r1(K + 1), r2(K + 1), r3(K + 1);
   for (int k = 0; k <= K; ++k) {
@@ -919,22 +962,23 @@ int build_step_engine(mpsw_state st) {
   e.plan.rrf_l = st->learned ? std::min<int64_t>(st->chi_cap + MPSW_RRF_OVER, MPSW_RRF_MAXL) : 0;
   EngineLayout L;
   layout_engine(e.plan, L);
-  if (hipMalloc(&e.eng, (size_t)L.stride * st->B * sizeof(double)) != hipSuccess)
+  if (st_malloc(st, &e.eng, (size_t)L.stride * st->B * sizeof(double)) != hipSuccess)
     return fail(MPSW_ENOMEM, "step workspace allocation failed (" + std::to_string(L.stride * st->B * 8 / (1 << 20)) + " MiB)");
   fill_ctx(st, e.h, e.eng, L);
-  return upload_ctx(e, st->stream);
+  return upload_ctx(e, st->stream, st);
 }
 
 int upload_lap(mpsw_state st) {
   std::vector<double> w;
   for (auto& c : st->lap.cores) w.insert(w.end(), c.begin(), c.end());
-  HIP_TRY(hipMalloc(&st->lapW, std::max<size_t>(1, w.size()) * sizeof(double)));
+  HIP_TRY(st_malloc(st, &st->lapW, std::max<size_t>(1, w.size()) * sizeof(double)));
   HIP_TRY(hipMemcpy(st->lapW, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
   return MPSW_OK;
 }
 
-int create_group(const mpsw_config* cfgs, int nshots, void* stream, mpsw_state* out) {
+int create_group(const mpsw_config* cfgs, int nshots, void* stream, const mpsw_allocator* alloc, mpsw_state* out) {
   if (!cfgs || !out || nshots < 1) return fail(MPSW_EINVAL, "null argument or nshots < 1");
+  if (alloc && (!alloc->alloc || !alloc->free)) return fail(MPSW_EINVAL, "allocator needs both alloc and free");
   const mpsw_config& c0 = cfgs[0];
   for (int i = 0; i < nshots; ++i) {
     const mpsw_config& c = cfgs[i];
@@ -954,6 +998,10 @@ int create_group(const mpsw_config* cfgs, int nshots, void* stream, mpsw_state* 
       return fail(MPSW_EINVAL, "shots of one batch must share n, ndim, lambda, precision, boundary, rank mode and site order");
   }
   mpsw_state st = new mpsw_state_s();
+  if (alloc) {
+    st->alloc = *alloc;
+    st->has_alloc = true;
+  }
   st->B = nshots;
   st->gemm_mode = (c0.precision == MPSW_FP32) ? GEMM_FP32 : (c0.precision == MPSW_BF16) ? GEMM_BF16X6 : GEMM_FP64;
   st->learned = (c0.rank_mode == MPSW_RANK_LEARNED);
@@ -982,12 +1030,12 @@ int create_group(const mpsw_config* cfgs, int nshots, void* stream, mpsw_state* 
     mpsw_destroy(st);
     return code;
   };
-  if (hipMalloc(&st->mps, (size_t)st->mps_stride * nshots * sizeof(double)) != hipSuccess ||
-      hipMalloc(&st->dims, (size_t)DL::size * nshots * sizeof(int)) != hipSuccess ||
-      hipMalloc(&st->reals, (size_t)RL::size * nshots * sizeof(double)) != hipSuccess ||
-      hipMalloc(&st->err, sizeof(int)) != hipSuccess ||
-      hipMalloc(&st->sync, (size_t)MPSW_SYNC_STRIDE * nshots * sizeof(int)) != hipSuccess ||
-      hipMalloc(&st->dense, (size_t)2 * p2(K) * sizeof(double)) != hipSuccess)
+  if (st_malloc(st, &st->mps, (size_t)st->mps_stride * nshots * sizeof(double)) != hipSuccess ||
+      st_malloc(st, &st->dims, (size_t)DL::size * nshots * sizeof(int)) != hipSuccess ||
+      st_malloc(st, &st->reals, (size_t)RL::size * nshots * sizeof(double)) != hipSuccess ||
+      st_malloc(st, &st->err, sizeof(int)) != hipSuccess ||
+      st_malloc(st, &st->sync, (size_t)MPSW_SYNC_STRIDE * nshots * sizeof(int)) != hipSuccess ||
+      st_malloc(st, &st->dense, (size_t)2 * p2(K) * sizeof(double)) != hipSuccess)
     return bail(fail(MPSW_ENOMEM, "state allocation failed"));
   if ((rc = upload_lap(st)) != MPSW_OK) return bail(rc);
   std::vector<int> hd((size_t)DL::size * nshots, 0);
@@ -1014,15 +1062,15 @@ int upload_wavelets(mpsw_state st) {
   for (auto& w : st->wavelets) ntm = std::max<int>(ntm, (int)w.size());
   std::vector<double> buf((size_t)ntm * st->B, 0.0);
   for (int i = 0; i < st->B; ++i) std::copy(st->wavelets[i].begin(), st->wavelets[i].end(), buf.begin() + (size_t)i * ntm);
-  hipFree(st->wavelet);
+  st_free(st, st->wavelet);
   st->wavelet = nullptr;
-  HIP_TRY(hipMalloc(&st->wavelet, buf.size() * sizeof(double)));
+  HIP_TRY(st_malloc(st, &st->wavelet, buf.size() * sizeof(double)));
   HIP_TRY(hipMemcpy(st->wavelet, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
   st->nt_max = ntm;
   if (st->eng.eng) {
     st->eng.h.wavelet = st->wavelet;
     st->eng.h.nt_max = ntm;
-    return upload_ctx(st->eng, st->stream);
+    return upload_ctx(st->eng, st->stream, st);
   }
   return MPSW_OK;
 }
@@ -1037,7 +1085,7 @@ int contract_dense(mpsw_state st, int shot, int slot, std::vector<double>& out) 
     EngineLayout L;
     std::memset(&L, 0, sizeof(L));
     fill_ctx(st, tmp.h, nullptr, L);
-    int rc = upload_ctx(tmp, st->stream);
+    int rc = upload_ctx(tmp, st->stream, st);
     if (rc != MPSW_OK) return rc;
     use = &tmp;
   }
@@ -1056,7 +1104,7 @@ int contract_dense(mpsw_state st, int shot, int slot, std::vector<double>& out) 
   const double* src = st->dense + (((K - 1) & 1) ? 0 : half);
   HIP_TRY(hipMemcpyAsync(out.data(), src, half * sizeof(double), hipMemcpyDeviceToHost, st->stream));
   int rc = check_dev_err(st);
-  if (tmp.d) hipFree(tmp.d);
+  if (tmp.d) st_free(st, tmp.d);
   return rc;
 }
 
@@ -1070,29 +1118,95 @@ extern "C" {
 const char* mpsw_last_error(void) { return g_last_error.c_str(); }
 
 int mpsw_create_state(const mpsw_config* cfg, void* hip_stream, mpsw_state* out) {
-  return create_group(cfg, 1, hip_stream, out);
+  return create_group(cfg, 1, hip_stream, nullptr, out);
 }
 
 int mpsw_create_batch(const mpsw_config* cfgs, int nshots, void* hip_stream, mpsw_state* out) {
-  return create_group(cfgs, nshots, hip_stream, out);
+  return create_group(cfgs, nshots, hip_stream, nullptr, out);
+}
+
+int mpsw_create_batch_ex(const mpsw_config* cfgs, int nshots, void* hip_stream, const mpsw_allocator* alloc,
+                         mpsw_state* out) {
+  return create_group(cfgs, nshots, hip_stream, alloc, out);
+}
+
+int mpsw_get_cores(mpsw_state st, int shot, int which, int* bonds, double* cores, int64_t cap) {
+  if (!st || !bonds) return fail(MPSW_EINVAL, "null argument");
+  if (shot < 0 || shot >= st->B || which < 0 || which > 1) return fail(MPSW_EINVAL, "shot or field out of range");
+  const int K = st->K, slot = which ? st->prev : st->cur;
+  HIP_TRY(hipStreamSynchronize(st->stream));
+  std::vector<int> dd(DL::size);
+  HIP_TRY(hipMemcpy(dd.data(), st->dims + (int64_t)shot * DL::size, DL::size * sizeof(int), hipMemcpyDeviceToHost));
+  int64_t tot = 0;
+  for (int k = 0; k <= K; ++k) bonds[k] = dd[DL::bonds + slot * (MPSW_MAXK + 1) + k];
+  for (int k = 0; k < K; ++k) tot += (int64_t)bonds[k] * 2 * bonds[k + 1];
+  if (tot > INT32_MAX) return fail(MPSW_EINVAL, "cores exceed the int range");
+  if (cores) {
+    if (cap < tot) return fail(MPSW_EINVAL, "cores buffer too small (" + std::to_string(tot) + " doubles needed)");
+    int64_t o = 0;
+    for (int k = 0; k < K; ++k) {
+      const int64_t sz = (int64_t)bonds[k] * 2 * bonds[k + 1];
+      HIP_TRY(hipMemcpy(cores + o, st->mps + (int64_t)shot * st->mps_stride + st->off_mps[slot][k], sz * sizeof(double),
+                        hipMemcpyDeviceToHost));
+      o += sz;
+    }
+  }
+  const int rc = check_dev_err(st);
+  return rc == MPSW_OK ? (int)tot : rc;
+}
+
+int mpsw_set_cores(mpsw_state st, int shot, int64_t step, const int* bonds_prev, const double* cores_prev,
+                   const int* bonds_cur, const double* cores_cur) {
+  if (!st || !bonds_prev || !cores_prev || !bonds_cur || !cores_cur) return fail(MPSW_EINVAL, "null argument");
+  if (shot < 0 || shot >= st->B) return fail(MPSW_EINVAL, "shot out of range");
+  if (step < 0 || step > (1 << 30)) return fail(MPSW_EINVAL, "step out of range");
+  const int K = st->K;
+  const int* bs[2] = {bonds_prev, bonds_cur};
+  const double* cs[2] = {cores_prev, cores_cur};
+  const int slots[2] = {st->prev, st->cur};
+  for (int t = 0; t < 2; ++t) {
+    if (bs[t][0] != 1 || bs[t][K] != 1) return fail(MPSW_EINVAL, "bonds[0] and bonds[K] must be 1");
+    for (int k = 1; k < K; ++k)
+      if (bs[t][k] < 1 || bs[t][k] > st->Rmax[k]) return fail(MPSW_EINVAL, "bond outside [1, min(chi, 2^k, 2^(K-k))]");
+    for (int k = 0; k < K; ++k)
+      if ((int64_t)bs[t][k] * 2 * bs[t][k + 1] > st->cap_mps[slots[t]][k]) return fail(MPSW_EINVAL, "core exceeds its slot");
+  }
+  HIP_TRY(hipStreamSynchronize(st->stream));
+  std::vector<int> dd(DL::size);
+  HIP_TRY(hipMemcpy(dd.data(), st->dims + (int64_t)shot * DL::size, DL::size * sizeof(int), hipMemcpyDeviceToHost));
+  for (int t = 0; t < 2; ++t) {
+    int64_t o = 0;
+    for (int k = 0; k < K; ++k) {
+      const int64_t sz = (int64_t)bs[t][k] * 2 * bs[t][k + 1];
+      HIP_TRY(hipMemcpy(st->mps + (int64_t)shot * st->mps_stride + st->off_mps[slots[t]][k], cs[t] + o,
+                        sz * sizeof(double), hipMemcpyHostToDevice));
+      o += sz;
+    }
+    for (int k = 0; k <= K; ++k) dd[DL::bonds + slots[t] * (MPSW_MAXK + 1) + k] = bs[t][k];
+  }
+  // the shot's source clock is the checkpoint's; its sketch back-offs restart
+  dd[DL::step] = (int)step;
+  for (int i = 0; i < 6 * MPSW_MAXK; ++i) dd[DL::rrf_skip + i] = 0;
+  HIP_TRY(hipMemcpy(st->dims + (int64_t)shot * DL::size, dd.data(), DL::size * sizeof(int), hipMemcpyHostToDevice));
+  return MPSW_OK;
 }
 
 int mpsw_destroy(mpsw_state st) {
   if (!st) return MPSW_OK;
   if (st->stream) hipStreamSynchronize(st->stream);
   else hipDeviceSynchronize();
-  hipFree(st->mps);
-  hipFree(st->dims);
-  hipFree(st->reals);
-  hipFree(st->c2);
-  hipFree(st->lapW);
-  hipFree(st->wavelet);
-  hipFree(st->dense);
-  hipFree(st->err);
-  hipFree(st->sync);
-  hipFree(st->eng.eng);
-  hipFree(st->eng.d);
-  hipFree(st->mlp_w);
+  st_free(st, st->mps);
+  st_free(st, st->dims);
+  st_free(st, st->reals);
+  st_free(st, st->c2);
+  st_free(st, st->lapW);
+  st_free(st, st->wavelet);
+  st_free(st, st->dense);
+  st_free(st, st->err);
+  st_free(st, st->sync);
+  st_free(st, st->eng.eng);
+  st_free(st, st->eng.d);
+  st_free(st, st->mlp_w);
   for (hipEvent_t ev : st->prof_ev) hipEventDestroy(ev);
   drop_graphs(st);
   if (st->cap_stream) hipStreamDestroy(st->cap_stream);
@@ -1134,9 +1248,9 @@ int mpsw_set_velocity_mpo(mpsw_state st, const int* bonds, const double* cores) 
     if (bonds[k + 1] < 1 || bonds[k + 1] > (1 << 20)) return fail(MPSW_EINVAL, "bad bond");
     tot += (int64_t)bonds[k] * 2 * bonds[k + 1];
   }
-  hipFree(st->c2);
+  st_free(st, st->c2);
   st->c2 = nullptr;
-  HIP_TRY(hipMalloc(&st->c2, tot * sizeof(double)));
+  HIP_TRY(st_malloc(st, &st->c2, tot * sizeof(double)));
   HIP_TRY(hipMemcpy(st->c2, cores, tot * sizeof(double), hipMemcpyHostToDevice));
   st->c2b.assign(bonds, bonds + K + 1);
   std::vector<double> dense;
@@ -1184,6 +1298,11 @@ int mpsw_set_fields(mpsw_state st, int shot, const double* u_prev, const double*
   if (!st) return fail(MPSW_EINVAL, "null state");
   if (shot < 0 || shot >= st->B) return fail(MPSW_EINVAL, "shot out of range");
   const double* fields[2] = {u_prev, u_cur};
+  const int64_t N = p2(st->K);
+  for (int t = 0; t < 2; ++t)
+    if (fields[t])
+      for (int64_t i = 0; i < N; ++i)
+        if (!std::isfinite(fields[t][i])) return fail(MPSW_EINVAL, "non-finite field value");
   const int slots[2] = {st->prev, st->cur};
   for (int t = 0; t < 2; ++t) {
     if (!fields[t]) {
@@ -1191,14 +1310,14 @@ int mpsw_set_fields(mpsw_state st, int shot, const double* u_prev, const double*
       EngineLayout L;
       std::memset(&L, 0, sizeof(L));
       fill_ctx(st, tmp.h, nullptr, L);
-      int rc = upload_ctx(tmp, st->stream);
+      int rc = upload_ctx(tmp, st->stream, st);
       if (rc != MPSW_OK) return rc;
       OpArgs a{};
       a.slot = slots[t];
       a.shot = shot;
       launch_zero_state(tmp.d, a, st->B, st->stream);
       hipStreamSynchronize(st->stream);
-      hipFree(tmp.d);
+      st_free(st, tmp.d);
       continue;
     }
     int rc = dense_to_mps(st, fields[t], st->cfg[shot].eps, st->cfg[shot].chi_max, shot, slots[t], false);
@@ -1494,11 +1613,12 @@ int mpsw_autotune(mpsw_state st, int steps, int* qr_nwg, int* jac_block_out) {
   double *sm = nullptr, *sr = nullptr;
   int* sd = nullptr;
   auto cleanup = [&]() {
-    hipFree(sm);
-    hipFree(sd);
-    hipFree(sr);
+    st_free(st, sm);
+    st_free(st, sd);
+    st_free(st, sr);
   };
-  if (hipMalloc(&sm, nm * 8) != hipSuccess || hipMalloc(&sd, nd * 4) != hipSuccess || hipMalloc(&sr, nr * 8) != hipSuccess) {
+  if (st_malloc(st, &sm, nm * 8) != hipSuccess || st_malloc(st, &sd, nd * 4) != hipSuccess ||
+      st_malloc(st, &sr, nr * 8) != hipSuccess) {
     cleanup();
     return fail(MPSW_ENOMEM, "tuning snapshot");
   }
@@ -1573,16 +1693,71 @@ int mpsw_set_launch_shapes(mpsw_state st, int qr_nwg, int jac_block) {
 
 int mpsw_rank_model_set(mpsw_state st, const float* w, int nw) {
   if (!st || !w || nw != MLP_NPARAM) return fail(MPSW_EINVAL, "null argument or wrong parameter count");
-  if (!st->mlp_w) HIP_TRY(hipMalloc(&st->mlp_w, MLP_NPARAM * sizeof(float)));
+  if (!st->mlp_w) HIP_TRY(st_malloc(st, &st->mlp_w, MLP_NPARAM * sizeof(float)));
   HIP_TRY(hipMemcpy(st->mlp_w, w, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice));
   st->have_model = true;
   if (st->have_velocity) {   // the step engine's context points at the parameters
     st->eng.h.mlp_w = st->mlp_w;
-    int rc = upload_ctx(st->eng, st->stream);
+    int rc = upload_ctx(st->eng, st->stream, st);
     if (rc != MPSW_OK) return rc;
     drop_graphs(st);
   }
   return MPSW_OK;
+}
+
+// Network inputs (and, with a network installed, outputs and ranks) of every
+// bond of one rounding, as the learned-rank rounding forms them at the next step.
+static int rank_export(mpsw_state st, int shot, int rounding, float* feats, float* outs, int* rhat) {
+  if (!st) return fail(MPSW_EINVAL, "null state");
+  if (shot < 0 || shot >= st->B || rounding < 0 || rounding > 2) return fail(MPSW_EINVAL, "shot or rounding out of range");
+  if (!st->have_velocity) return fail(MPSW_ESTATE, "no velocity set");
+  const int K = st->K;
+  if (K < 2) return fail(MPSW_EINVAL, "a single site has no bond");
+  const size_t nf = (size_t)K * MLP_NIN, nb = (size_t)K;
+  char* buf = nullptr;
+  HIP_TRY(st_malloc(st, &buf, nf * sizeof(float) + nb * (sizeof(float) + sizeof(int))));
+  float* df = (float*)buf;
+  float* dout = df + nf;
+  int* dr = (int*)(dout + nb);
+  hipMemsetAsync(buf, 0, nf * sizeof(float) + nb * (sizeof(float) + sizeof(int)), st->stream);
+  launch_rank_export(st->eng.d, shot, rounding, K, df, dout, dr, st->stream);
+  std::vector<float> hf(nf), ho(nb);
+  std::vector<int> hr(nb);
+  hipError_t e = hipMemcpyAsync(hf.data(), df, nf * sizeof(float), hipMemcpyDeviceToHost, st->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(ho.data(), dout, nb * sizeof(float), hipMemcpyDeviceToHost, st->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(hr.data(), dr, nb * sizeof(int), hipMemcpyDeviceToHost, st->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  st_free(st, buf);
+  if (e != hipSuccess) return fail(MPSW_EHIP, hipGetErrorString(e));
+  for (int k = 1; k < K; ++k) {
+    if (feats) std::memcpy(feats + (size_t)(k - 1) * MLP_NIN, hf.data() + (size_t)k * MLP_NIN, MLP_NIN * sizeof(float));
+    if (outs) outs[k - 1] = ho[k];
+    if (rhat) rhat[k - 1] = hr[k];
+  }
+  return check_dev_err(st);
+}
+
+int mpsw_get_rank_features(mpsw_state st, int shot, int rounding, float* feats) {
+  if (!feats) return fail(MPSW_EINVAL, "null argument");
+  return rank_export(st, shot, rounding, feats, nullptr, nullptr);
+}
+
+int mpsw_debug_sketch_normals(uint64_t seed, int step, int rounding, int site, int rows, int cols, double* out) {
+  if (!out || rows < 1 || cols < 1 || rows > 4096 || cols > 1024 || step < 0 || rounding < 0 || site < 0)
+    return fail(MPSW_EINVAL, "bad argument");
+  double* d = nullptr;
+  HIP_TRY(hipMalloc(&d, (size_t)rows * cols * sizeof(double)));
+  launch_sketch_normals((unsigned long long)seed, step, rounding, site, rows, cols, d, nullptr);
+  hipError_t e = hipMemcpy(out, d, (size_t)rows * cols * sizeof(double), hipMemcpyDeviceToHost);
+  hipFree(d);
+  if (e != hipSuccess) return fail(MPSW_EHIP, hipGetErrorString(e));
+  return MPSW_OK;
+}
+
+int mpsw_debug_rank_plan(mpsw_state st, int shot, int rounding, float* outs, int* rhat) {
+  if (!outs || !rhat) return fail(MPSW_EINVAL, "null argument");
+  if (st && !st->have_model) return fail(MPSW_ESTATE, "no rank network installed");
+  return rank_export(st, shot, rounding, nullptr, outs, rhat);
 }
 
 int mpsw_get_sigma_log(mpsw_state st, int shot, int rounding, double* out) {
@@ -1772,6 +1947,137 @@ int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, doubl
 
 // Host-side helper exported for tests: the fused Laplacian MPO cores
 // ([wl][wr][s'][s] per site, packed) and bonds (K+1) for a register of n bits.
+int mpsw_debug_sketch(const double* A, int m, int n, int l, double eps, int chi, uint64_t seed, int step, int rounding,
+                      int site, double* sig, double* stats, int* rank, int* accepted) {
+  if (!A || !sig || !stats || !rank || !accepted) return fail(MPSW_EINVAL, "null argument");
+  if (m < 2 || n < 2 || (n & 1) || m > 4096 || n > 4096 || l < 1 || l > 32 || l > m || l > n || chi < 1 ||
+      !(eps >= 0.0) || rounding < 0 || rounding > 2 || site < 1 || site > MPSW_MAXK - 2 || step < 0)
+    return fail(MPSW_EINVAL, "bad argument");
+  const int k = site, K = site + 1;
+  SweepCaps sc;
+  sc.rin.assign(K + 1, 1);
+  sc.rt.assign(K + 1, 1);
+  sc.rho.assign(K + 1, 1);
+  sc.rt[k] = m;
+  sc.rho[k + 1] = n / 2;
+  sc.rho[k] = l;
+  Plan p;
+  p.K = K;
+  p.half = std::max(1, K / 2);
+  p.sw = {sc};
+  p.rrf_l = l;
+  EngineLayout L;
+  layout_engine(p, L);
+  const int64_t core_cap = (int64_t)l * n + 2;
+  double *eng = nullptr, *mps = nullptr, *reals = nullptr;
+  int *dims = nullptr, *err = nullptr, *sync = nullptr;
+  auto cleanup = [&]() { hipFree(eng); hipFree(mps); hipFree(reals); hipFree(dims); hipFree(err); hipFree(sync); };
+  if (hipMalloc(&eng, L.stride * 8) || hipMalloc(&mps, core_cap * 8) || hipMalloc(&reals, RL::size * 8) ||
+      hipMalloc(&dims, DL::size * 4) || hipMalloc(&err, 4) || hipMalloc(&sync, MPSW_SYNC_STRIDE * 4)) {
+    cleanup();
+    return fail(MPSW_ENOMEM, "debug_sketch: allocation failed");
+  }
+  Engine e;
+  DevCtx& h = e.h;
+  std::memset(&h, 0, sizeof(h));
+  h.K = K; h.n = std::max(1, K / 2); h.half = h.n; h.ndim = 2; h.B = 1;
+  h.mps = mps; h.mps_stride = core_cap;
+  for (int q = 0; q < K; ++q) { h.off_mps[0][q] = 0; h.cap_mps[0][q] = core_cap; }
+  h.dims = dims; h.reals = reals; h.eng = eng; h.L = L; h.err = err; h.sync = sync;
+  h.seed = (unsigned long long)seed;
+  h.rrf_over = MPSW_RRF_OVER;
+  for (int q = 0; q <= K; ++q) { h.c2b[q] = 1; h.wb[q] = 1; }
+  // the plan of the sketch set by hand: width l, this step
+  std::vector<int> hd(DL::size, 0);
+  std::vector<double> hr(RL::size, 0.0);
+  hd[DL::chi] = chi;
+  hd[DL::rt + k] = m;
+  hd[DL::rho + k + 1] = n / 2;
+  hd[DL::step] = step;
+  hd[DL::rrf] = 1;
+  hd[DL::rrf_l] = l;
+  hr[RL::eps] = eps;
+  hipMemcpy(dims, hd.data(), DL::size * 4, hipMemcpyHostToDevice);
+  hipMemcpy(reals, hr.data(), RL::size * 8, hipMemcpyHostToDevice);
+  hipMemset(err, 0, 4);
+  hipMemcpy(eng + L.off_M, A, (size_t)m * n * 8, hipMemcpyHostToDevice);
+  int rc = upload_ctx(e, nullptr);
+  if (rc != MPSW_OK) { cleanup(); return rc; }
+  hipStream_t s0 = nullptr;
+  const DevCtx* d = e.d;
+  // the launch sequence of the learned-rank rounding for one bond (sketch,
+  // SVD stage on B = M Q, residual, acceptance)
+  OpArgs r{};
+  r.shot = -1; r.site = k; r.slot = 0; r.aux = rounding; r.gate = GATE_SKETCH;
+  launch_gauss(d, r, (int64_t)m * l, 1, s0);
+  OpArgs g{};
+  g.mode = GEMM_FP64; g.gate = GATE_SKETCH; g.shot = -1; g.site = k;
+  auto orth = [&](int which, int64_t mcap) {
+    OpArgs q = r;
+    q.op = 3;
+    q.aux = which;
+    const int bw = qr_panel(mcap);
+    launch_sync_reset(d, 1, s0);
+    launch_qrf(d, q, bw, std::max(1, cdiv(l, bw)), 1, (size_t)mcap * bw * 8, s0);
+    launch_formq(d, q, bw, std::max(1, cdiv(l, 16)), 1, s0);
+  };
+  g.op = G_RRF_Y; g.aux = 0;
+  launch_gemm(d, g, n, l, 1, 1, s0);
+  orth(0, n);
+  g.op = G_RRF_Z;
+  launch_gemm(d, g, m, l, 1, 1, s0);
+  orth(1, m);
+  g.op = G_RRF_Y; g.aux = 1;
+  launch_gemm(d, g, n, l, 1, 1, s0);
+  orth(0, n);
+  g.op = G_RRF_Z;
+  launch_gemm(d, g, m, l, 1, 1, s0);
+  launch_rrf_swap(d, r, (int64_t)m * n, 1, s0);
+  {
+    const int64_t rows = std::max<int64_t>(m, l), ccap = std::min<int64_t>(m, l);
+    OpArgs v{};
+    v.shot = -1; v.site = k; v.slot = 0; v.aux = rounding; v.gate = GATE_SKETCH;
+    launch_sync_reset(d, 1, s0);
+    const int bw1 = qr_panel(rows), bw2 = qr_panel(ccap);
+    OpArgs q = v;
+    q.op = 1;
+    launch_qrf(d, q, bw1, std::max(1, cdiv(ccap, bw1)), 1, (size_t)rows * bw1 * 8, s0);
+    q.op = 2;
+    launch_qrf(d, q, bw2, std::max(1, cdiv(ccap, bw2)), 1, (size_t)ccap * bw2 * 8, s0);
+    const int b = jac_block(ccap);
+    const int64_t nb = cdiv(ccap, b);
+    launch_jac(d, v, b, (int)std::max<int64_t>(1, (nb + (nb & 1)) / 2), 1, (size_t)2 * b * (ccap + 1) * 8, ccap, s0);
+    launch_jacfin(d, v, 1, s0);
+    launch_applyv(d, v, bw1, std::max(1, cdiv(l, 16)), 1, s0);
+    OpArgs gu{};
+    gu.mode = GEMM_FP64; gu.gate = GATE_SKETCH; gu.shot = -1; gu.site = k; gu.slot = 0; gu.op = G_US;
+    launch_gemm(d, gu, m, l, 1, 1, s0);
+  }
+  g.op = G_RRF_RES;
+  launch_gemm(d, g, m, n, 1, 1, s0);
+  launch_rrf_resid(d, r, 1, s0);
+  launch_rrf_accept(d, r, (int64_t)m * n, 1, s0);
+  hipDeviceSynchronize();
+  std::vector<int> d1(DL::size);
+  std::vector<double> r1(RL::size);
+  hipMemcpy(d1.data(), dims, DL::size * 4, hipMemcpyDeviceToHost);
+  hipMemcpy(r1.data(), reals, RL::size * 8, hipMemcpyDeviceToHost);
+  for (int i = 0; i < 32; ++i) sig[i] = r1[RL::sigma_log + (rounding * MPSW_MAXK + k) * 32 + i];
+  stats[0] = r1[RL::rrf_res2];
+  stats[1] = r1[RL::rrf_tail];
+  stats[2] = r1[RL::rrf_sig1];
+  *rank = d1[DL::rho + k];
+  *accepted = (d1[DL::rrf] == 2) ? 1 : 0;
+  int he = 0;
+  hipMemcpy(&he, err, 4, hipMemcpyDeviceToHost);
+  const hipError_t le = hipGetLastError();
+  cleanup();
+  hipFree(e.d);
+  if (le != hipSuccess) return fail(MPSW_EHIP, std::string("debug_sketch: ") + hipGetErrorString(le));
+  if (he) return fail(MPSW_ENOMEM, "debug_sketch: device error bits " + std::to_string(he));
+  return MPSW_OK;
+}
+
 int mpsw_debug_laplacian_mpo(int n, int boundary, int ordering, int ndim, int* bonds, double* cores, int64_t cap) {
   if ((ndim != 2 && ndim != 3) || n < 1 || n * ndim > 22 || !bonds) return fail(MPSW_EINVAL, "bad argument");
   if (ordering != MPSW_SEQUENTIAL && ordering != MPSW_INTERLEAVED) return fail(MPSW_EINVAL, "unknown site order");

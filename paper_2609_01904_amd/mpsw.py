@@ -19,14 +19,15 @@ MPSW_SEQUENTIAL, MPSW_INTERLEAVED = 0, 1
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ECFL", -6: "ENONFINITE"}
 
 EXPORTS = [
-    "mpsw_create_state", "mpsw_create_batch", "mpsw_set_velocity_dense", "mpsw_set_velocity_mpo",
+    "mpsw_create_state", "mpsw_create_batch", "mpsw_create_batch_ex", "mpsw_get_cores", "mpsw_set_cores", "mpsw_set_velocity_dense", "mpsw_set_velocity_mpo",
     "mpsw_set_source", "mpsw_set_fields", "mpsw_step", "mpsw_to_dense", "mpsw_get_bonds",
     "mpsw_get_stats", "mpsw_get_shape", "mpsw_destroy", "mpsw_last_error", "mpsw_debug_laplacian_mpo",
     "mpsw_debug_factor", "mpsw_profile", "mpsw_profile_read", "mpsw_set_graph_mode",
     "mpsw_group_create", "mpsw_group_step", "mpsw_group_destroy", "mpsw_mlp_grad", "mpsw_mlp_train",
-    "mpsw_mlp_forward", "mpsw_rank_model_set", "mpsw_get_sigma_log", "mpsw_autotune", "mpsw_set_launch_shapes", "mpsw_set_source_3d",
+    "mpsw_mlp_forward", "mpsw_mlp_init", "mpsw_rank_model_set", "mpsw_get_rank_features", "mpsw_debug_rank_plan", "mpsw_debug_sketch_normals", "mpsw_debug_sketch", "mpsw_get_sigma_log", "mpsw_autotune", "mpsw_set_launch_shapes", "mpsw_set_source_3d",
 ]
 MLP_NPARAM = 21121
+MLP_NIN = 34
 
 KC_QR, KC_JACOBI, KC_GEMM, KC_APPLYQ, KC_APPLYV = 0, 1, 2, 3, 4
 KC_NAMES = {KC_QR: "qr", KC_JACOBI: "jacobi", KC_GEMM: "gemm", KC_APPLYQ: "applyq", KC_APPLYV: "applyv"}
@@ -52,6 +53,40 @@ class Stats(ctypes.Structure):
                 ("fallbacks", ctypes.c_int64), ("max_jacobi_sweeps", ctypes.c_int), ("sketches", ctypes.c_int64)]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+class TorchAllocator:
+    """Device memory for a state from torch's caching allocator: each block the
+    library asks for is a uint8 tensor kept alive until the library frees it."""
+
+    def __init__(self, device="cuda"):
+        import torch
+        self.blocks = {}
+
+        def _alloc(nbytes, ctx):
+            try:
+                t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+            except RuntimeError:
+                return None
+            self.blocks[t.data_ptr()] = t
+            return t.data_ptr()
+
+        def _free(ptr, nbytes, ctx):
+            self.blocks.pop(ptr, None)
+
+        self._fns = (ALLOC_FN(_alloc), FREE_FN(_free))   # the callbacks must outlive the state
+        self.struct = Allocator(self._fns[0], self._fns[1], None)
+
+    def bytes_held(self):
+        return sum(t.numel() for t in self.blocks.values())
+
+
 class KProf(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("alg_flops", ctypes.c_double)]
 
@@ -72,6 +107,9 @@ def load():
     sig = {
         "mpsw_create_state": [ctypes.POINTER(Config), P, ctypes.POINTER(P)],
         "mpsw_create_batch": [ctypes.POINTER(Config), I, P, ctypes.POINTER(P)],
+        "mpsw_create_batch_ex": [ctypes.POINTER(Config), I, P, ctypes.POINTER(Allocator), ctypes.POINTER(P)],
+        "mpsw_get_cores": [P, I, I, P, P, ctypes.c_int64],
+        "mpsw_set_cores": [P, I, ctypes.c_int64, P, P, P, P],
         "mpsw_set_velocity_dense": [P, P, D],
         "mpsw_set_velocity_mpo": [P, P, P],
         "mpsw_set_source": [P, I, I, I, I, P],
@@ -93,6 +131,11 @@ def load():
         "mpsw_mlp_grad": [P, P, I, ctypes.c_float, P, P, P],
         "mpsw_mlp_train": [P, P, I, I, ctypes.c_float, ctypes.c_float, P],
         "mpsw_mlp_forward": [P, I, P, P],
+        "mpsw_mlp_init": [ctypes.c_uint64, P],
+        "mpsw_get_rank_features": [P, I, I, P],
+        "mpsw_debug_rank_plan": [P, I, I, P, P],
+        "mpsw_debug_sketch_normals": [ctypes.c_uint64, I, I, I, I, I, P],
+        "mpsw_debug_sketch": [P, I, I, I, D, I, ctypes.c_uint64, I, I, I, P, P, P, P],
         "mpsw_rank_model_set": [P, P, I],
         "mpsw_get_sigma_log": [P, I, I, P],
         "mpsw_autotune": [P, I, ctypes.POINTER(I), ctypes.POINTER(I)],
@@ -135,10 +178,17 @@ def _stream_handle(stream):
 class State:
     """One shot (cfg is a Config) or a batch (cfg is a list of Configs)."""
 
-    def __init__(self, cfg, stream=None):
+    def __init__(self, cfg, stream=None, allocator=None):
         lib = load()
         self._h = ctypes.c_void_p()
-        if isinstance(cfg, (list, tuple)):
+        self.allocator = allocator   # kept alive as long as the state
+        if allocator is not None:
+            cfgs = list(cfg) if isinstance(cfg, (list, tuple)) else [cfg]
+            arr = (Config * len(cfgs))(*cfgs)
+            _check(lib.mpsw_create_batch_ex(arr, len(cfgs), _stream_handle(stream), ctypes.byref(allocator.struct),
+                                            ctypes.byref(self._h)))
+            self.n, self.ndim = cfgs[0].n, cfgs[0].ndim or 2
+        elif isinstance(cfg, (list, tuple)):
             arr = (Config * len(cfg))(*cfg)
             _check(lib.mpsw_create_batch(arr, len(cfg), _stream_handle(stream), ctypes.byref(self._h)))
             self.n, self.ndim = cfg[0].n, cfg[0].ndim or 2
@@ -189,6 +239,32 @@ class State:
                 args.append(p)
         _check(load().mpsw_set_fields(self._h, shot, args[0], args[1]))
 
+    def get_cores(self, shot=0, which=0):
+        """(bonds, [core_k of shape (b_k, 2, b_{k+1})]) of psi^k (which 0) or psi^{k-1} (1)."""
+        lib = load()
+        b = np.zeros(self.K + 1, dtype=np.int32)
+        tot = _check(lib.mpsw_get_cores(self._h, shot, which, b.ctypes.data_as(ctypes.c_void_p), None, 0))
+        buf = np.zeros(max(tot, 1))
+        _check(lib.mpsw_get_cores(self._h, shot, which, b.ctypes.data_as(ctypes.c_void_p),
+                                  buf.ctypes.data_as(ctypes.c_void_p), buf.size))
+        cores, o = [], 0
+        for k in range(self.K):
+            sz = int(b[k]) * 2 * int(b[k + 1])
+            cores.append(buf[o:o + sz].reshape(int(b[k]), 2, int(b[k + 1])))
+            o += sz
+        return [int(x) for x in b], cores
+
+    def set_cores(self, shot, step, prev, cur):
+        """Resume from a checkpoint: prev and cur are (bonds, cores) of psi^{k-1} and psi^k."""
+        args = []
+        keep = []
+        for bonds, cores in (prev, cur):
+            bb = np.ascontiguousarray(bonds, dtype=np.int32)
+            cc, pc = _f64(np.concatenate([np.ravel(x) for x in cores]))
+            keep += [bb, cc]
+            args += [bb.ctypes.data_as(ctypes.c_void_p), pc]
+        _check(load().mpsw_set_cores(self._h, shot, int(step), *args))
+
     def step(self, k=1):
         _check(load().mpsw_step(self._h, int(k)))
 
@@ -219,6 +295,20 @@ class State:
         """Parameters of the rank network for the learned-rank rounding."""
         w = np.ascontiguousarray(w, dtype=np.float32)
         _check(load().mpsw_rank_model_set(self._h, w.ctypes.data_as(ctypes.c_void_p), int(w.size)))
+
+    def rank_features(self, shot=0, rounding=0):
+        """Rank-network inputs of bonds 1..K-1 of one rounding for the coming step ((K-1) x 34)."""
+        out = np.zeros((self.K - 1, MLP_NIN), dtype=np.float32)
+        _check(load().mpsw_get_rank_features(self._h, shot, rounding, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def debug_rank_plan(self, shot=0, rounding=0):
+        """(network outputs, proposed ranks) of bonds 1..K-1 of one rounding for the coming step."""
+        o = np.zeros(self.K - 1, dtype=np.float32)
+        r = np.zeros(self.K - 1, dtype=np.int32)
+        _check(load().mpsw_debug_rank_plan(self._h, shot, rounding, o.ctypes.data_as(ctypes.c_void_p),
+                                           r.ctypes.data_as(ctypes.c_void_p)))
+        return o, r
 
     def sigma_log(self, shot=0, rounding=0):
         """Leading 32 singular values of every bond of one rounding in the last step (K x 32)."""
@@ -302,6 +392,13 @@ def mlp_train(X, y, w, epochs, lr, alpha):
     return w
 
 
+def mlp_init(seed=0):
+    """He-scaled normal initial parameters of the rank network (the library's generator)."""
+    w = np.zeros(MLP_NPARAM, dtype=np.float32)
+    _check(load().mpsw_mlp_init(int(seed), w.ctypes.data_as(ctypes.c_void_p)))
+    return w
+
+
 def mlp_forward(X, w):
     X, px = _f32(X)
     w, pw = _f32(w)
@@ -326,6 +423,28 @@ def debug_laplacian_mpo(n, boundary=MPSW_PERIODIC, ordering=MPSW_SEQUENTIAL, ndi
         cores.append(buf[o:o + sz].reshape(bonds[k], bonds[k + 1], 2, 2))
         o += sz
     return [int(b) for b in bonds], cores
+
+
+def debug_sketch_normals(seed, step, rounding, site, rows, cols):
+    """The library's Gaussian test matrix for one sketch key (rows x cols)."""
+    out = np.zeros((rows, cols))
+    _check(load().mpsw_debug_sketch_normals(int(seed), int(step), int(rounding), int(site), int(rows), int(cols),
+                                            out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def debug_sketch(A, l, eps, chi, seed, step, rounding, site):
+    """Run the library's sketch of one bond matrix: (sigma of B (32), residual,
+    discarded sketched sigma^2, largest sketched sigma, kept rank, accepted)."""
+    a, p = _f64(A)
+    m, n = a.shape
+    sig = np.zeros(32)
+    st = np.zeros(3)
+    r, ok = ctypes.c_int(), ctypes.c_int()
+    _check(load().mpsw_debug_sketch(p, m, n, int(l), float(eps), int(chi), int(seed), int(step), int(rounding),
+                                    int(site), sig.ctypes.data_as(ctypes.c_void_p), st.ctypes.data_as(ctypes.c_void_p),
+                                    ctypes.byref(r), ctypes.byref(ok)))
+    return sig, float(st[0]), float(st[1]), float(st[2]), r.value, bool(ok.value)
 
 
 def debug_factor(op, A):

@@ -1,5 +1,5 @@
 """C-ABI checks that need no GPU: the library loads, exports every function
-declared in include/mpsw.h, validates arguments before touching the device,
+declared in include/*.h, validates arguments before touching the device,
 and its host-built Laplacian MPO is the 5-point operator (eqs. 6, 16)."""
 import os
 import re
@@ -21,9 +21,13 @@ def lib():
 
 
 def _header_functions(repo_root):
-    text = open(os.path.join(repo_root, "include", "mpsw.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mpsw_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    inc = os.path.join(repo_root, "include")
+    for h in sorted(os.listdir(inc)):
+        if h.endswith(".h"):
+            text = re.sub(r"/\*.*?\*/", "", open(os.path.join(inc, h)).read(), flags=re.S)
+            names |= set(re.findall(r"\b(mpsw_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_exports_every_declared_symbol(lib, repo_root):

@@ -15,6 +15,7 @@ from oracle import fdtd as F
 from oracle import mps as M
 from oracle import stepper as S
 import synth
+from helpers import oracle_c2, oracle_velocity
 
 pytestmark = pytest.mark.gpu
 ORD = {0: "sequential", 1: "interleaved"}
@@ -80,8 +81,7 @@ def test_untruncated_3d_step_equals_fdtd(mpsw, n, boundary, ordering):
     wav = rng.standard_normal(8)
     src = (N // 2, 1, N - 1)
     st = make_state(mpsw, n, 1 << 20, 0.0, lam, boundary, ordering)
-    st.set_velocity_dense(c2, 0.0)
-    c2r = st.to_dense(0, 2)
+    c2r = oracle_velocity(st, c2, 0.0, ordering)
     up, u = rng.standard_normal((N, N, N)), rng.standard_normal((N, N, N))
     st.set_fields(0, up, u)
     st.set_source_3d(0, src[0], src[1], src[2], wav)
@@ -104,7 +104,7 @@ def test_each_rounding_matches_oracle_3d(mpsw, ordering):
     lam = 0.3
     c2m = S.c2_mps(c2, n, 1e-8, o)
     st = make_state(mpsw, n, chi, eps, lam, ordering=ordering)
-    st.set_velocity_dense(c2, 1e-8)
+    st.set_velocity_mpo(M.bonds_of(c2m), c2m)
     up, u = rng.standard_normal((N, N, N)), rng.standard_normal((N, N, N))
     st.set_fields(0, up, u)
     psi = M.tt_svd(M.to_sites(u, o), 3 * n, eps, chi)
@@ -130,9 +130,9 @@ def test_truncated_3d_trajectory_matches_oracle(mpsw, ordering):
     wav = synth.ricker(steps, 0.02, 4.0)
     src = (N // 2, N // 3, 1)
     st = make_state(mpsw, n, chi, eps, lam, ordering=ordering)
-    st.set_velocity_dense(c2, 1e-6)
+    c2r = oracle_velocity(st, c2, 1e-6, ordering)
     st.set_source_3d(0, src[0], src[1], src[2], wav)
-    ds = S.DenseStepper(n, lam, eps, chi, st.to_dense(0, 2), src=src, wavelet=wav, ordering=o)
+    ds = S.DenseStepper(n, lam, eps, chi, c2r, src=src, wavelet=wav, ordering=o)
     for _ in range(steps):
         ds.step()
     st.step(steps)
@@ -187,7 +187,9 @@ def test_c3d_step_matches_oracle(mpsw):
     step against the oracle step from the same fields."""
     import torch
     import bench
-    st, cfg, fields = bench.make_state(mpsw, synth, "C3D", 4, "fp64")
+    cfg0 = synth.get_config("C3D")
+    bonds, cores, c2r = oracle_c2(cfg0["c2"], cfg0["eps_c"])
+    st, cfg, fields = bench.make_state(mpsw, synth, "C3D", 4, "fp64", velocity=(bonds, cores))
     q, b = st.autotune(1)
     _say("C3D autotuned:", q, b)
     st.step(1)
@@ -197,7 +199,6 @@ def test_c3d_step_matches_oracle(mpsw):
     before = {s: (st.to_dense(s, 1), st.to_dense(s, 0), st.stats(s)["step"]) for s in sample}
     st.step(1)
     torch.cuda.synchronize()
-    c2r = st.to_dense(0, 2)
     for s in sample:
         up, u, k = before[s]
         ds = S.DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], c2r, src=fields[s][2],

@@ -11,6 +11,7 @@ import pytest
 from oracle import fdtd as F
 from oracle import stepper as S
 import synth
+from helpers import oracle_velocity
 
 pytestmark = pytest.mark.gpu
 
@@ -45,8 +46,7 @@ def test_two_site_grid_equals_fdtd(mpsw, boundary, ordering):
     c2 = 0.5 + rng.random((2, 2))
     wav = rng.standard_normal(8)
     st = mpsw.State(mpsw.make_config(n, 2, 0.0, lam, boundary=boundary, ordering=ordering))
-    st.set_velocity_dense(c2, 0.0)
-    c2r = st.to_dense(0, 2)
+    c2r = oracle_velocity(st, c2, 0.0, ordering)
     up, u = rng.standard_normal((2, 2)), rng.standard_normal((2, 2))
     st.set_fields(0, up, u)
     st.set_source(0, 1, 0, wav)
@@ -64,8 +64,7 @@ def _against_dense_stepper(mpsw, n, chi, eps, steps, seed):
     lam = 0.5
     wav = synth.ricker(steps, 0.004, 20.0)
     st = mpsw.State(mpsw.make_config(n, chi, eps, lam))
-    st.set_velocity_dense(c2, 1e-8)
-    c2r = st.to_dense(0, 2)
+    c2r = oracle_velocity(st, c2, 1e-8)
     up, u = synth.random_fields(n, seed=seed)
     st.set_fields(0, up, u)
     src = (N // 3, 2)

@@ -17,6 +17,7 @@ import pytest
 
 from oracle import stepper as S
 import synth
+from helpers import oracle_c2
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +47,9 @@ def test_c3_batched_step_matches_oracle_on_sampled_shots(mpsw):
     import bench
     B = 128
     _say("full-size C3 state,", B, "shots")
-    st, cfg, fields = bench.make_state(mpsw, synth, "C3", B, "fp64")
+    cfg0 = synth.get_config("C3")
+    bonds, cores, c2r = oracle_c2(cfg0["c2"], cfg0["eps_c"])
+    st, cfg, fields = bench.make_state(mpsw, synth, "C3", B, "fp64", velocity=(bonds, cores))
     q, b = st.autotune(1)
     _say("autotuned: QR workgroups per shot", q, "Jacobi block", b)
     st.step(2)
@@ -56,7 +59,6 @@ def test_c3_batched_step_matches_oracle_on_sampled_shots(mpsw):
     before = {s: (st.to_dense(s, 1), st.to_dense(s, 0), st.stats(s)["step"]) for s in sample}
     st.step(1)
     torch.cuda.synchronize()
-    c2r = st.to_dense(0, 2)
     for s in range(B):
         bonds = st.bonds(s, 0)
         assert len(bonds) == K + 1 and bonds[0] == 1 and bonds[-1] == 1
@@ -82,7 +84,9 @@ def test_c5_step_matches_oracle(mpsw):
     oracle step from the same fields."""
     import torch
     import bench
-    st, cfg, fields = bench.make_state(mpsw, synth, "C5", 1, "fp64")
+    cfg0 = synth.get_config("C5")
+    bonds, cores, c2r = oracle_c2(cfg0["c2"], cfg0["eps_c"])
+    st, cfg, fields = bench.make_state(mpsw, synth, "C5", 1, "fp64", velocity=(bonds, cores))
     st.step(1)
     torch.cuda.synchronize()
     n = cfg["n"]
@@ -90,7 +94,7 @@ def test_c5_step_matches_oracle(mpsw):
     st.step(1)
     torch.cuda.synchronize()
     g = st.to_dense(0, 0)
-    ds = S.DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], st.to_dense(0, 2), src=fields[0][2],
+    ds = S.DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], c2r, src=fields[0][2],
                         wavelet=cfg["wavelet_samples"])
     ds.u_prev, ds.u, ds.k = up, u, k
     ds.step()

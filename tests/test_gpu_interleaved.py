@@ -14,6 +14,7 @@ from oracle import fdtd as F
 from oracle import mps as M
 from oracle import stepper as S
 import synth
+from helpers import oracle_c2, oracle_velocity
 
 pytestmark = pytest.mark.gpu
 IL = "interleaved"
@@ -44,7 +45,7 @@ def make_state(mpsw, n, chi, eps, lam, boundary=0):
 
 
 def test_velocity_and_fields_interleaved(mpsw):
-    for n in (4, 6, 8):
+    for n in (4, 6, 8, 10):
         _say("interleaved velocity", n)
         c2 = synth.layered_fault_velocity(n)
         st = make_state(mpsw, n, 16, 1e-8, 1e-4)
@@ -77,8 +78,7 @@ def test_untruncated_interleaved_step_equals_fdtd(mpsw, n, boundary):
     wav = rng.standard_normal(10)
     src = (N // 2 + 1, 1)
     st = make_state(mpsw, n, 1 << n, 0.0, lam, boundary)
-    st.set_velocity_dense(c2, 0.0)
-    c2r = st.to_dense(0, 2)
+    c2r = oracle_velocity(st, c2, 0.0, IL)
     up, u = synth.random_fields(n, seed=n, smooth=False)
     st.set_fields(0, up, u)
     st.set_source(0, src[0], src[1], wav)
@@ -97,7 +97,7 @@ def test_each_rounding_matches_oracle_interleaved(mpsw):
     lam = 0.5
     c2m = S.c2_mps(c2, n, 1e-8, IL)
     st = make_state(mpsw, n, chi, eps, lam)
-    st.set_velocity_dense(c2, 1e-8)
+    st.set_velocity_mpo(M.bonds_of(c2m), c2m)
     up, u = synth.random_fields(n, seed=7)
     st.set_fields(0, up, u)
     psi = M.tt_svd(M.to_sites(u, IL), 2 * n, eps, chi)
@@ -117,9 +117,8 @@ def test_c2_prefix_matches_oracle_interleaved(mpsw):
     cfg = synth.get_config("C2", steps=steps)
     n = cfg["n"]
     st = make_state(mpsw, n, cfg["chi"], cfg["eps"], cfg["lam"])
-    st.set_velocity_dense(cfg["c2"], cfg["eps_c"])
+    c2r = oracle_velocity(st, cfg["c2"], cfg["eps_c"], IL)
     st.set_source(0, cfg["ix"], cfg["iz"], cfg["wavelet_samples"])
-    c2r = st.to_dense(0, 2)
     ds = S.DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], c2r, src=(cfg["ix"], cfg["iz"]),
                         wavelet=cfg["wavelet_samples"], ordering=IL)
     for _ in range(steps):
@@ -160,7 +159,9 @@ def test_c3_step_matches_oracle_interleaved(mpsw):
     shots' next step against the oracle step from the same fields."""
     import torch
     import bench
-    st, cfg, fields = bench.make_state(mpsw, synth, "C3", 4, "fp64", ordering=IL)
+    cfg0 = synth.get_config("C3")
+    bonds, cores, c2r = oracle_c2(cfg0["c2"], cfg0["eps_c"], IL)
+    st, cfg, fields = bench.make_state(mpsw, synth, "C3", 4, "fp64", ordering=IL, velocity=(bonds, cores))
     st.step(1)
     torch.cuda.synchronize()
     n = cfg["n"]
@@ -168,7 +169,6 @@ def test_c3_step_matches_oracle_interleaved(mpsw):
     before = {s: (st.to_dense(s, 1), st.to_dense(s, 0), st.stats(s)["step"]) for s in sample}
     st.step(1)
     torch.cuda.synchronize()
-    c2r = st.to_dense(0, 2)
     for s in sample:
         up, u, k = before[s]
         ds = S.DenseStepper(n, cfg["lam"], cfg["eps"], cfg["chi"], c2r, src=fields[s][2],

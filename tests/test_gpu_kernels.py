@@ -27,7 +27,8 @@ def _graded(m, n, seed, decay=12.0):
 
 
 @pytest.mark.parametrize("m,n", [(32, 8), (128, 32), (64, 40), (300, 100), (512, 200), (8, 8), (16, 40),
-                                 (2048, 100), (4096, 48)])   # 8- and 4-wide panels (LDS)
+                                 (2048, 100), (4096, 48),    # 8- and 4-wide panels (LDS)
+                                 (1024, 1024), (2048, 512), (2048, 2048), (4096, 1024)])   # the n = 10, 11 TT-SVDs
 def test_qr(mpsw, m, n):
     print("qr", m, n, flush=True)
     A = np.random.default_rng(m + n).standard_normal((m, n))
@@ -41,7 +42,8 @@ def test_qr(mpsw, m, n):
 
 
 @pytest.mark.parametrize("m,n", [(8, 8), (16, 32), (64, 64), (32, 64), (64, 40), (100, 256), (256, 256), (300, 128),
-                                 (512, 400), (400, 600)])   # factors of 257-512 columns
+                                 (512, 400), (400, 600),    # factors of 257-512 columns
+                                 (2048, 504), (1024, 504)])  # bond matrices of the n = 11 TT-SVD
 def test_svd(mpsw, m, n):
     print("svd", m, n, flush=True)
     A = _graded(m, n, seed=m * 7 + n)

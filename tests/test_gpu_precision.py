@@ -9,34 +9,28 @@ operand into three BF16 parts and keeps six of the nine partial products
 FP32 accumulation; the FP32 sums of each 16-deep slice are accumulated in
 FP64.
 
-Targets after 80 steps of a truncating run on the layered model: 1e-10 for
-FP64, 1e-3 for BF16, and 1e-6 for FP32 unless the sensitivity floor of FP32
-arithmetic is above it.  The floor at perturbation delta (two oracle runs, one
-perturbed by delta relative noise before every rounding) is linear in delta,
-about 23 delta here, and does not depend on eps: it is how the leapfrog scheme
-carries per-step errors over 80 steps.  At FP32's unit roundoff u = 2^-24 it
-is 1.4e-6, already above the 1e-6 target.  The GPU's FP32 rounding does not
-enter once per entry of a rounding's input: a rounding chains about 3K FP32
-contractions (operator apply, QR sweep, SVD sweep), each adding up to 6u per
-entry (two operand roundings and the FP32 sums of up to four matrix-core
-steps of a 16-deep slice), which add in norm to sqrt(3K) 6u = 36u at K = 12.
-FP32 is held to the floor at delta = 32u = 2^-19.
+Targets of the precision forms: 1e-10 for FP64, 1e-3 for BF16, 1e-6 for
+FP32.  The FP32 target is out of reach on this workload, and the test says
+so instead of widening it: the sensitivity floor at perturbation delta (two
+oracle runs, one perturbed by delta relative noise before every rounding) is
+linear in delta, about 23 delta here, and does not depend on eps; at FP32's
+unit roundoff u = 2^-24 it is already 1.4e-6, above 1e-6.  FP32 operands
+enter more than once per rounding: a rounding chains about 3K contractions
+(operator apply, QR sweep, SVD sweep), each rounding its operands to FP32 and
+summing a 16-deep slice in FP32, so its effective perturbation is some tens
+of u.  The FP32 form is held to 32 times the floor at delta = u (the floor of
+a perturbation of 32 u, the size that chain of roundings adds up to), and
+its measured distance is printed beside the 1e-6 target.
 """
-import sys
-
 import numpy as np
 import pytest
 
 from oracle import stepper as S
 import synth
 import sensitivity
+from helpers import oracle_c2, rel, say
 
 pytestmark = pytest.mark.gpu
-
-
-def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 @pytest.fixture(scope="module")
@@ -49,11 +43,6 @@ def mpsw():
     return m
 
 
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
-
-
 @pytest.fixture(scope="module")
 def reference():
     # no bond cap is reached (chi = 64 is the largest bond of n = 6), so the
@@ -62,45 +51,47 @@ def reference():
     n, eps, chi, steps = 6, 1e-6, 64, 80
     N = 1 << n
     cfg = synth.get_config("C2", n=n, steps=steps)
-    return dict(n=n, eps=eps, chi=chi, steps=steps, lam=cfg["lam"], c2=cfg["c2"],
-                src=(N // 2, 1), wav=synth.ricker(steps, cfg["dt"], 40.0), eps_c=cfg["eps_c"])
+    bonds, cores, c2r = oracle_c2(cfg["c2"], cfg["eps_c"])
+    return dict(n=n, eps=eps, chi=chi, steps=steps, lam=cfg["lam"], c2_bonds=bonds, c2_cores=cores, c2r=c2r,
+                src=(N // 2, 1), wav=synth.ricker(steps, cfg["dt"], 40.0))
 
 
 def _run(mpsw, ref, precision):
     st = mpsw.State(mpsw.make_config(ref["n"], ref["chi"], ref["eps"], ref["lam"], precision=precision))
-    st.set_velocity_dense(ref["c2"], ref["eps_c"])
+    st.set_velocity_mpo(ref["c2_bonds"], ref["c2_cores"])
     st.set_source(0, ref["src"][0], ref["src"][1], ref["wav"])
     st.step(ref["steps"])
     out = st.to_dense(0, 0)
-    c2r = st.to_dense(0, 2)
     st.close()
-    return out, c2r
+    return out
 
 
 @pytest.fixture(scope="module")
-def oracle_field(mpsw, reference):
+def oracle_field(reference):
     ref = reference
-    _, c2r = _run(mpsw, ref, mpsw.MPSW_FP64)
-    ds = S.DenseStepper(ref["n"], ref["lam"], ref["eps"], ref["chi"], c2r, src=ref["src"], wavelet=ref["wav"])
+    ds = S.DenseStepper(ref["n"], ref["lam"], ref["eps"], ref["chi"], ref["c2r"], src=ref["src"],
+                        wavelet=ref["wav"])
     for _ in range(ref["steps"]):
         ds.step()
     return ds.dense()
 
 
 @pytest.fixture(scope="module")
-def fp32_floor(mpsw, reference):
+def fp32_floor(reference):
+    """Sensitivity floor at delta = u32 = 2^-24 (oracle runs only)."""
     ref = reference
-    _, c2r = _run(mpsw, ref, mpsw.MPSW_FP64)
-    return sensitivity.floor(ref["n"], ref["lam"], ref["eps"], ref["chi"], c2r, ref["src"], ref["wav"],
-                             ref["steps"], delta=2.0 ** -19)
+    return sensitivity.floor(ref["n"], ref["lam"], ref["eps"], ref["chi"], ref["c2r"], ref["src"], ref["wav"],
+                             ref["steps"], delta=2.0 ** -24)
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_precision_against_fp64_oracle(mpsw, reference, oracle_field, fp32_floor, prec):
-    tol = {0: 1e-10, 1: max(1e-6, fp32_floor), 2: 1e-3}[prec]
-    _say("precision", prec, "tolerance", tol, "floor at 32 u32", fp32_floor)
-    got, _ = _run(mpsw, reference, prec)
+    tol = {0: 1e-10, 1: 32.0 * fp32_floor, 2: 1e-3}[prec]
+    say("precision", prec, "tolerance", tol, "floor at u32", fp32_floor)
+    got = _run(mpsw, reference, prec)
     err = rel(got, oracle_field)
-    _say(f"precision {prec}: rel-L2 vs FP64 oracle after {reference['steps']} steps = {err:.3e}")
+    say(f"precision {prec}: rel-L2 vs FP64 oracle after {reference['steps']} steps = {err:.3e}"
+        + (f" (target 1e-6: {'met' if err <= 1e-6 else f'missed by {err / 1e-6:.0f}x'}; "
+           f"floor at u32 {fp32_floor:.2e})" if prec == 1 else ""))
     assert np.all(np.isfinite(got))
     assert err < tol, err

@@ -41,7 +41,7 @@ def test_exact_recovery_of_low_rank_matrix():
     assert np.all(S[5:] < 1e-12)
     assert np.allclose(Q.T @ Q, np.eye(8), atol=1e-13)
     assert np.allclose(B @ Q.T, M, atol=1e-12)
-    ok, r = rrf.accept(M, B, S, eps=1e-6, chi=10)
+    ok, r = rrf.accept(M, Q, B, S, eps=1e-6, chi=10)
     assert ok and r == 5
 
 
@@ -51,23 +51,40 @@ def test_acceptance_rule():
     M = _matrix(64, 64, s, seed=4)
     Om = rrf.omega(seed=9, step=1, rnd=2, site=5, m=64, l=10)
     Q, B, S, W = rrf.range_finder(M, Om)
-    ok, r = rrf.accept(M, B, S, eps=1e-8, chi=40)
+    ok, r = rrf.accept(M, Q, B, S, eps=1e-8, chi=40)
     assert not ok and r == 10
     # fast decay beyond the cutoff inside the sketch -> accept, same rank as exact
     s = np.concatenate([np.ones(6), 1e-9 * np.ones(20)])
     M = _matrix(64, 64, s, seed=5)
     Q, B, S, W = rrf.range_finder(M, Om)
-    ok, r = rrf.accept(M, B, S, eps=1e-6, chi=40)
+    ok, r = rrf.accept(M, Q, B, S, eps=1e-6, chi=40)
     assert ok and r == 6
     # capped: in-sketch tail large against what the sketch misses -> accept
     s = np.concatenate([np.ones(8), 0.5 * np.ones(2), 1e-8 * np.ones(10)])
     M = _matrix(64, 64, s, seed=6)
     Q, B, S, W = rrf.range_finder(M, Om)
-    ok, r = rrf.accept(M, B, S, eps=1e-6, chi=8)
+    ok, r = rrf.accept(M, Q, B, S, eps=1e-6, chi=8)
     assert ok and r == 8
     # capped with a flat spectrum beyond the sketch -> reject
     s = np.concatenate([np.ones(8), 0.5 * np.ones(30)])
     M = _matrix(64, 64, s, seed=7)
     Q, B, S, W = rrf.range_finder(M, Om)
-    ok, r = rrf.accept(M, B, S, eps=1e-6, chi=8)
+    ok, r = rrf.accept(M, Q, B, S, eps=1e-6, chi=8)
+    assert not ok
+
+
+def test_residual_is_formed_directly():
+    """At a small cutoff a sketch that misses singular values above it must be
+    rejected; ||M||^2 - ||B||^2 would lose them in its rounding noise."""
+    eps = 1e-10
+    s = np.concatenate([np.ones(4), 1e-9 * np.ones(8)])   # 8 values 10x above the cutoff
+    M = _matrix(64, 48, s, seed=8)
+    Om = rrf.omega(seed=3, step=0, rnd=0, site=1, m=64, l=4)   # width 4 sees only the leading values
+    Q, B, S, W = rrf.range_finder(M, Om)
+    missed = 8 * 1e-18
+    diff2 = float(np.sum(M * M) - np.sum(B * B))
+    assert abs(diff2 - missed) > 10 * missed   # the difference of squares is rounding noise here
+    E = M - B @ Q.T
+    assert np.isclose(np.sum(E * E), missed, rtol=1e-6)
+    ok, r = rrf.accept(M, Q, B, S, eps=eps, chi=40)
     assert not ok
