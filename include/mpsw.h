@@ -294,6 +294,19 @@ int mpsw_mlp_grad(const float* X, const float* y, int m, float alpha, const floa
 int mpsw_mlp_init(uint64_t seed, float* w);
 /* `epochs` full-batch Adam steps from w (updated in place) at learning rate lr. */
 int mpsw_mlp_train(const float* X, const float* y, int m, int epochs, float lr, float alpha, float* w);
+/* mpsw_mlp_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): X, y,
+ * w, grad and loss are DEVICE pointers owned by the caller (same layouts as
+ * mpsw_mlp_grad), and the per-chunk partial sums live in a static device
+ * array of the library (about 21.6 MB per device, held until the process
+ * ends), so m is at most 8192.  Enqueued on hip_stream (NULL = the default
+ * stream), asynchronous, no allocation, no synchronisation; the results
+ * equal mpsw_mlp_grad's bit for bit.  All calls on one device share the
+ * scratch array: calls that overlap on one device (different streams or
+ * threads without ordering) race.  Errors: EINVAL (null pointer, m outside
+ * [1, 8192]), EHIP. */
+int mpsw_mlp_grad_noalloc(const float* X, const float* y, int m, float alpha, const float* w, float* grad,
+                          float* loss, void* hip_stream);
 /* Network outputs for m feature rows. */
 int mpsw_mlp_forward(const float* X, int m, const float* w, float* out);
 

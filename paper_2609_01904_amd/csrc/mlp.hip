@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <string>
 #include <vector>
@@ -179,6 +180,15 @@ __global__ void k_adam(float* W, const float* __restrict__ grad, float* m1, floa
   W[p] -= lr * ah / (sqrtf(bh) + e);
 }
 
+// Scratch of the allocation-free gradient call: the per-chunk partial
+// gradients and losses of up to MLP_STATIC_MAX_ROWS samples.  One copy per
+// device, held until the process ends; every call overwrites all of what it
+// reads (each chunk writes its whole partial, the reduction writes the whole
+// gradient), so nothing needs clearing between calls.
+constexpr int MLP_STATIC_MAX_ROWS = 8192;
+constexpr int MLP_STATIC_CHUNKS = MLP_STATIC_MAX_ROWS / MLP_S;
+static __device__ __align__(256) float scratch[(size_t)MLP_STATIC_CHUNKS * MLP_NPARAM + MLP_STATIC_CHUNKS];
+
 }  // namespace mpsw
 
 using namespace mpsw;
@@ -251,6 +261,40 @@ int mpsw_mlp_grad(const float* X, const float* y, int m, float alpha, const floa
 int mpsw_mlp_train(const float* X, const float* y, int m, int epochs, float lr, float alpha, float* w) {
   if (epochs < 0 || !(lr > 0.0f)) return mlp_fail(MPSW_EINVAL, "epochs must be >= 0 and lr > 0");
   return run_mlp(X, y, m, alpha, w, epochs, lr, nullptr, nullptr, nullptr);
+}
+
+int mpsw_mlp_grad_noalloc(const float* X, const float* y, int m, float alpha, const float* w, float* grad,
+                          float* loss, void* hip_stream) {
+  if (!X || !y || !w || !grad || !loss) return mlp_fail(MPSW_EINVAL, "null argument");
+  if (m < 1 || m > MLP_STATIC_MAX_ROWS)
+    return mlp_fail(MPSW_EINVAL, "m must be in [1, " + std::to_string(MLP_STATIC_MAX_ROWS) + "] for the static scratch");
+  // the device address of this device's copy of the scratch array, looked up
+  // once per device with that device current (the array's name in host code
+  // is not a device address)
+  static std::mutex mu;
+  static float* addr[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return mlp_fail(MPSW_EHIP, "no current device");
+  float* sp = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) return mlp_fail(MPSW_EHIP, std::string("scratch address: ") + hipGetErrorString(e));
+      addr[dev] = (float*)p;
+    }
+    sp = addr[dev];
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int nchunk = (m + MLP_S - 1) / MLP_S;
+  float* gpart = sp;
+  float* lpart = sp + (size_t)MLP_STATIC_CHUNKS * MLP_NPARAM;
+  hipLaunchKernelGGL(k_mlp<true>, dim3(nchunk), dim3(MLP_NH), 0, s, X, y, m, alpha, w, nullptr, gpart, lpart);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, gpart, lpart, nchunk, grad, loss);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return mlp_fail(MPSW_EHIP, std::string("network kernels: ") + hipGetErrorString(e));
+  return MPSW_OK;
 }
 
 int mpsw_mlp_init(uint64_t seed, float* w) {

@@ -24,7 +24,7 @@ EXPORTS = [
     "mpsw_get_stats", "mpsw_get_shape", "mpsw_destroy", "mpsw_last_error", "mpsw_debug_laplacian_mpo",
     "mpsw_debug_factor", "mpsw_profile", "mpsw_profile_read", "mpsw_set_graph_mode",
     "mpsw_group_create", "mpsw_group_step", "mpsw_group_destroy", "mpsw_mlp_grad", "mpsw_mlp_train",
-    "mpsw_mlp_forward", "mpsw_mlp_init", "mpsw_rank_model_set", "mpsw_get_rank_features", "mpsw_debug_rank_plan", "mpsw_debug_sketch_normals", "mpsw_debug_sketch", "mpsw_get_sigma_log", "mpsw_autotune", "mpsw_set_launch_shapes", "mpsw_set_source_3d",
+    "mpsw_mlp_forward", "mpsw_mlp_init", "mpsw_mlp_grad_noalloc", "mpsw_rank_model_set", "mpsw_get_rank_features", "mpsw_debug_rank_plan", "mpsw_debug_sketch_normals", "mpsw_debug_sketch", "mpsw_get_sigma_log", "mpsw_autotune", "mpsw_set_launch_shapes", "mpsw_set_source_3d",
 ]
 MLP_NPARAM = 21121
 MLP_NIN = 34
@@ -132,6 +132,7 @@ def load():
         "mpsw_mlp_train": [P, P, I, I, ctypes.c_float, ctypes.c_float, P],
         "mpsw_mlp_forward": [P, I, P, P],
         "mpsw_mlp_init": [ctypes.c_uint64, P],
+        "mpsw_mlp_grad_noalloc": [P, P, I, ctypes.c_float, P, P, P, P],
         "mpsw_get_rank_features": [P, I, I, P],
         "mpsw_debug_rank_plan": [P, I, I, P, P],
         "mpsw_debug_sketch_normals": [ctypes.c_uint64, I, I, I, I, I, P],
@@ -380,6 +381,18 @@ def mlp_grad(X, y, w, alpha):
     _check(load().mpsw_mlp_grad(px, py, X.shape[0], float(alpha), pw, g.ctypes.data_as(ctypes.c_void_p),
                                 loss.ctypes.data_as(ctypes.c_void_p)))
     return float(loss[0]), g
+
+
+def mlp_grad_noalloc(X, y, w, grad, loss, alpha, stream=None):
+    """Enqueue the rank network's loss and gradient on device tensors (torch,
+    CUDA, float32, contiguous): X (m x 34), y (m), w, grad (MLP_NPARAM), loss (1)."""
+    for t in (X, y, w, grad, loss):
+        if not (t.is_cuda and t.is_contiguous() and str(t.dtype) == "torch.float32"):
+            raise ValueError("device float32 contiguous tensors expected")
+    P = ctypes.c_void_p
+    _check(load().mpsw_mlp_grad_noalloc(P(X.data_ptr()), P(y.data_ptr()), int(X.shape[0]), float(alpha),
+                                        P(w.data_ptr()), P(grad.data_ptr()), P(loss.data_ptr()),
+                                        _stream_handle(stream)))
 
 
 def mlp_train(X, y, w, epochs, lr, alpha):
