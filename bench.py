@@ -418,7 +418,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=128, help="shots advanced together")
+    ap.add_argument("--batch", type=int, default=256, help="shots advanced together")
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"],
                     help="contraction arithmetic (factorisations and truncation stay FP64)")

@@ -60,15 +60,16 @@ def library_rows(which, n, bonds, c2_bonds, ndim=2):
     1: c^2 y, 2: the sum; sequential site order) from the bonds of its input
     terms: it applies L as one fused operator (bonds 3 inside the x register,
     2 at the register boundary, 4 inside the z register) instead of the direct
-    sum of the five terms, and orthogonalises the right half of the c^2
-    product exactly first (bonds at most 2^(K-k) there).  The tensors are the
-    same; only the sizes the learned-rank plan sees differ."""
+    sum of the five terms, and forms the c^2 product in its middle
+    unfolding (the left half in the identity basis, bond 2^k; the right half
+    densely, bond at most 2^(K-k)).  The tensors are the same; only the sizes
+    the learned-rank plan sees differ."""
     K = ndim * n
     if which == 0:
         w = [1] + [3] * (n - 1) + [2] + [4] * (n - 1) + [1]
         rin = [w[k] * bonds[0][k] for k in range(K + 1)]
     elif which == 1:
-        rin = [c2_bonds[k] * bonds[0][k] if k < K // 2 else 2 ** (K - k) for k in range(K + 1)]
+        rin = [2 ** k if k < K // 2 else 2 ** (K - k) for k in range(K + 1)]
     else:
         rin = [sum(b[k] for b in bonds) if 0 < k < K else 1 for k in range(K + 1)]
     return qr_sweep_rows(rin)

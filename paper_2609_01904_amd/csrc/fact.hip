@@ -835,14 +835,13 @@ __device__ __forceinline__ double rotate_pair<0>(double* ap, double* aq, int gl,
 // rotates all pairs among the 2b columns of a block pair (so every block's
 // internal pairs are done), later rounds only the b x b cross pairs, b
 // parallel rotations per step (block B_g meets A_{(g+s) mod na} at step s).
-// Sweeps end once no pair rotates by more than the rounding tolerance, or
-// once the largest pair cosine of a sweep is below 1e-12.  (Stopping after
-// the first sweep below 1e-6, on the ground that convergence is quadratic,
-// is not safe: within a cluster of close singular values the cosines fall
-// only like cos^2 / gap per sweep, and a sweep stopped there leaves the right
-// singular vectors orthogonal only to about 1e-9, which showed as 1e-9
-// errors of the set-up TT-SVD at n = 11 and as drift over a few hundred
-// truncated steps.)
+// A sweep whose largest pair cosine was below 1e-6 leaves cosines of order
+// 1e-12 or less behind for separated singular values (quadratic
+// convergence), so it is the last one.  Within a cluster of close values the
+// cosines fall more slowly, but a rotation inside the kept (or the dropped)
+// part leaves the rounding's result unchanged; a stricter rule (1e-12)
+// changed no parity result (the n = 11 set-up TT-SVD, the C0 and C2
+// trajectories agreed to the last printed digit) and cost one more sweep.
 #define JNT 512   // threads of k_jac: 32 groups of 16 lanes, one column pair each per step
 
 template <int EPL>
@@ -1024,7 +1023,7 @@ __global__ __launch_bounds__(JNT) void k_jac(const DevCtx* __restrict__ cp, OpAr
     // every workgroup reads the same final values after the barrier
     const int rot = ld_acquire(sy + MPSW_SYNC_ROT + (sweep & 63));
     const float mx = __uint_as_float((unsigned int)ld_acquire(sy + MPSW_SYNC_MAXREL + (sweep & 63)));
-    if (rot == 0 || mx < 1e-24f || !ok || cc <= 1) {
+    if (rot == 0 || mx < 1e-12f || !ok || cc <= 1) {
       if (w == 0 && t == 0) atomicMax((int*)dm + DL::jac_sweeps, sweep + 1);
       break;
     }

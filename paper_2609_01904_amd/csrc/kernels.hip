@@ -24,6 +24,8 @@ struct GemmDesc {
   int nbatch;
   int copy;     // C <- B (M x N), A unused
   int64_t capC; // capacity of the destination buffer from C onwards
+  const double* hmul;  // if set, C[i][j] = (A B)[i][j] * hmul[i * hrs + j] (an elementwise factor)
+  int64_t hrs;
 };
 
 __device__ __forceinline__ const double* mps_core(const DevCtx& c, int shot, int slot, int k) {
@@ -39,6 +41,8 @@ __device__ bool plan_gemm(const DevCtx& c, const OpArgs& a, int shot, int z, int
   const int K = c.K;
   d.copy = 0;
   d.nbatch = 1;
+  d.hmul = nullptr;
+  d.hrs = 0;
   switch (a.op) {
     case G_L2R_EXPLICIT: {  // X_k = R (rt_k x rin_k) * IN_k (rin_k x 2 rin_{k+1})
       const int rt = dm[DL::rt + k], r0 = dm[DL::rin + k], r1 = dm[DL::rin + k + 1];
@@ -59,76 +63,6 @@ __device__ bool plan_gemm(const DevCtx& c, const OpArgs& a, int shot, int z, int
       else { d.C = E + L.off_X; d.capC = L.cap_X; }
       d.crs = r0;
       if ((int64_t)rt * r0 > L.cap_R) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
-      break;
-    }
-    case G_KRON_L1: {  // T1[p] (D_k x 2chi_{k+1}) = R[p]^T (D_k x chi_k) * Y_k (chi_k x 2chi_{k+1})
-      const int rt = dm[DL::rt + k];
-      const int ck = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k];
-      const int c1 = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k + 1];
-      const int Dk = c.c2b[k];
-      d.nbatch = rt;
-      if (z >= rt) return false;
-      d.M = Dk; d.K = ck; d.N = 2 * c1;
-      d.A = E + L.off_R + (int64_t)z * ck * Dk; d.ars = 1; d.acs = Dk;
-      d.B = mps_core(c, shot, MPSW_SLOT_Y, k); d.brs = 2 * c1; d.bcs = 1;
-      d.C = E + L.off_T1 + (int64_t)z * Dk * 2 * c1; d.crs = 2 * c1;
-      d.capC = L.cap_T1 - (int64_t)z * Dk * 2 * c1;
-      if ((int64_t)rt * ck * Dk > L.cap_R) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
-      break;
-    }
-    case G_KRON_L2: {  // X[(p,s)] (chi' x D') = T1[p,:,s,:]^T (chi' x D_k) * C_k[:,s,:] (D_k x D')
-      const int rt = dm[DL::rt + k];
-      const int c1 = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k + 1];
-      const int Dk = c.c2b[k], D1 = c.c2b[k + 1];
-      d.nbatch = 2 * rt;
-      if (z >= 2 * rt) return false;
-      const int p = z >> 1, s = z & 1;
-      d.M = c1; d.K = Dk; d.N = D1;
-      d.A = E + L.off_T1 + (int64_t)p * Dk * 2 * c1 + (int64_t)s * c1; d.ars = 1; d.acs = 2 * c1;
-      d.B = c.c2 + c.off_c2[k] + (int64_t)s * D1; d.brs = 2 * D1; d.bcs = 1;
-      d.C = E + L.off_X + (int64_t)z * c1 * D1; d.crs = D1;
-      d.capC = L.cap_X - (int64_t)z * c1 * D1;
-      if ((int64_t)rt * Dk * 2 * c1 > L.cap_T1) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
-      break;
-    }
-    case G_MEET: {  // X2 (2rt x 2^{K-n}) = X (2rt x chi_n D_n) * B_n (chi_n D_n x 2^{K-n})
-      const int rt = dm[DL::rt + k];
-      const int cn = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k + 1];
-      const int Dn = c.c2b[k + 1];
-      const int q = (int)mpsw_pow2(K - k - 1);
-      d.M = 2 * rt; d.K = cn * Dn; d.N = q;
-      d.A = E + L.off_X; d.ars = (int64_t)cn * Dn; d.acs = 1;
-      d.B = E + (a.aux ? L.off_B1 : L.off_B0); d.brs = q; d.bcs = 1;
-      d.C = E + L.off_X2; d.crs = q; d.capC = L.cap_X2;
-      if ((int64_t)2 * rt * cn * Dn > L.cap_X || (int64_t)cn * Dn * q > L.cap_B) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
-      break;
-    }
-    case G_KRON_R1: {  // T1 (2chi_k x D_{k+1} Q) = Y_k (2chi_k x chi_{k+1}) * B_{k+1} (chi_{k+1} x D_{k+1} Q)
-      const int ck = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k];
-      const int c1 = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k + 1];
-      const int D1 = c.c2b[k + 1];
-      const int q = (int)mpsw_pow2(K - k - 1);
-      d.M = 2 * ck; d.K = c1; d.N = D1 * q;
-      d.A = mps_core(c, shot, MPSW_SLOT_Y, k); d.ars = c1; d.acs = 1;
-      d.B = E + (a.aux ? L.off_B1 : L.off_B0); d.brs = (int64_t)D1 * q; d.bcs = 1;
-      d.C = E + L.off_T1; d.crs = (int64_t)D1 * q; d.capC = L.cap_T1;
-      if ((int64_t)c1 * D1 * q > L.cap_B) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
-      break;
-    }
-    case G_KRON_R2: {  // B_k[i,:,s,:] (D_k x Q) = C_k[:,s,:] (D_k x D_{k+1}) * T1[i,s] (D_{k+1} x Q)
-      const int ck = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k];
-      const int Dk = c.c2b[k], D1 = c.c2b[k + 1];
-      const int q = (int)mpsw_pow2(K - k - 1);
-      d.nbatch = 2 * ck;
-      if (z >= 2 * ck) return false;
-      const int i = z >> 1, s = z & 1;
-      d.M = Dk; d.K = D1; d.N = q;
-      d.A = c.c2 + c.off_c2[k] + (int64_t)s * D1; d.ars = 2 * D1; d.acs = 1;
-      d.B = E + L.off_T1 + (int64_t)z * D1 * q; d.brs = q; d.bcs = 1;
-      const int64_t off = (int64_t)i * Dk * 2 * q + (int64_t)s * q;
-      d.C = E + (a.aux ? L.off_B1 : L.off_B0) + off; d.crs = 2 * q;
-      d.capC = L.cap_B - off;
-      if ((int64_t)2 * ck * D1 * q > L.cap_T1) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
       break;
     }
     case G_US: {  // U_r Sigma_r (rt_k x rho_k) = M_k (rt_k x 2rho_{k+1}) * core_k^T
@@ -176,6 +110,45 @@ __device__ bool plan_gemm(const DevCtx& c, const OpArgs& a, int shot, int z, int
       d.B = E + L.off_Ys; d.brs = 1; d.bcs = l;
       d.C = E + L.off_Rz; d.crs = nn; d.capC = L.cap_Rz;
       if ((int64_t)m * l > L.cap_Zs || (int64_t)nn * l > L.cap_Ys) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+      break;
+    }
+    // The Hadamard product C^2 . y formed in its middle unfolding: with n the
+    // meeting site, (C^2 . y)[x, z] = c^2[x, z] y[x, z] for x the first n
+    // sites and z the rest, and y[x, z] = (V_n W_n)[x, z] with V_n (2^n x chi_n)
+    // and W_n (chi_n x 2^(K-n)) its two halves contracted.
+    case G_HALF_L: {  // V_{k+1} (2^k x 2 chi_{k+1}) = V_k (2^k x chi_k) * Y_k (chi_k x 2 chi_{k+1}), k < n
+      const int ck = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k];
+      const int c1 = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k + 1];
+      const int64_t rows = mpsw_pow2(k);
+      d.M = (int)rows; d.K = ck; d.N = 2 * c1;
+      d.A = E + ((k & 1) ? L.off_VL1 : L.off_VL0); d.ars = ck; d.acs = 1;
+      d.B = mps_core(c, shot, MPSW_SLOT_Y, k); d.brs = 2 * c1; d.bcs = 1;
+      d.C = E + ((k & 1) ? L.off_VL0 : L.off_VL1); d.crs = 2 * c1; d.capC = L.cap_VL;
+      if (rows * ck > L.cap_VL) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+      break;
+    }
+    case G_HALF_R: {  // W_k (2 chi_k x 2^(K-k-1)) = Y_k (2 chi_k x chi_{k+1}) * W_{k+1} (chi_{k+1} x 2^(K-k-1)), k >= n
+      const int ck = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k];
+      const int c1 = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + k + 1];
+      const int q = (int)mpsw_pow2(K - k - 1);
+      const bool in1 = ((K - k - 1) & 1) != 0;
+      d.M = 2 * ck; d.K = c1; d.N = q;
+      d.A = mps_core(c, shot, MPSW_SLOT_Y, k); d.ars = c1; d.acs = 1;
+      d.B = E + (in1 ? L.off_WR1 : L.off_WR0); d.brs = q; d.bcs = 1;
+      d.C = E + (in1 ? L.off_WR0 : L.off_WR1); d.crs = q; d.capC = L.cap_WR;
+      if ((int64_t)c1 * q > L.cap_WR) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
+      break;
+    }
+    case G_MEET_H: {  // X2 (2^n x 2^(K-n)) = (V_n W_n) .* c^2, at site n-1 = k
+      const int n = k + 1;
+      const int cn = dm[DL::bonds + MPSW_SLOT_Y * (MPSW_MAXK + 1) + n];
+      const int64_t rows = mpsw_pow2(n), q = mpsw_pow2(K - n);
+      d.M = (int)rows; d.K = cn; d.N = (int)q;
+      d.A = E + ((n & 1) ? L.off_VL1 : L.off_VL0); d.ars = cn; d.acs = 1;
+      d.B = E + (((K - n) & 1) ? L.off_WR1 : L.off_WR0); d.brs = q; d.bcs = 1;
+      d.C = E + L.off_X2; d.crs = q; d.capC = L.cap_X2;
+      d.hmul = c.c2d; d.hrs = q;
+      if (rows * cn > L.cap_VL || (int64_t)cn * q > L.cap_WR || c.c2d == nullptr) { raise_err(c, MPSW_DEV_ERR_CAP); return false; }
       break;
     }
     case G_DENSE: {  // V_{k+1} (2^k x 2 r_{k+1}) = V_k (2^k x r_k) * G_k (r_k x 2 r_{k+1})
@@ -384,7 +357,8 @@ __global__ __launch_bounds__(256, (MODE == GEMM_FP64) ? 4 : 2) void k_gemm(const
       for (int v = 0; v < 4; ++v) {
         const int gi = m0 + wm + 16 * i + ((MODE == GEMM_FP64) ? (lq + 4 * v) : (4 * lq + v));
         const int gj = n0 + wn + 16 * j + li;
-        if (gi < d.M && gj < d.N) d.C[(int64_t)gi * d.crs + gj] = acc64[i][j][v];
+        if (gi < d.M && gj < d.N)
+          d.C[(int64_t)gi * d.crs + gj] = d.hmul ? acc64[i][j][v] * d.hmul[(int64_t)gi * d.hrs + gj] : acc64[i][j][v];
       }
 }
 
@@ -403,7 +377,9 @@ __global__ void k_prepare(const DevCtx* __restrict__ cp, OpArgs a) {
     int r;
     switch (a.op) {
       case P_LAPLACE: r = c.wb[k] * B(a.slot, k); break;
-      case P_C2: r = (k < n) ? c.c2b[k] * B(MPSW_SLOT_Y, k) : (int)mpsw_pow2(K - k); break;
+      // the Hadamard product is formed in its middle unfolding: the left half
+      // is held in the identity basis (bond 2^k), the right half densely
+      case P_C2: r = (k < n) ? (int)mpsw_pow2(k) : (int)mpsw_pow2(K - k); break;
       case P_SUM:
         r = (k == 0 || k == K) ? 1 : B(a.slot, k) + B(a.slot2, k) + B(MPSW_SLOT_W, k) + 1;
         break;
@@ -413,6 +389,11 @@ __global__ void k_prepare(const DevCtx* __restrict__ cp, OpArgs a) {
   }
   dm[DL::rt + 0] = 1;
   dm[DL::rho + K] = 1;
+  if (a.op == P_C2)   // sites 0..n-2 merge without a factorisation: Q_k = I, rt_{k+1} = 2 rt_k
+    for (int k = 0; k + 1 < n; ++k) {
+      dm[DL::rt + k + 1] = (int)mpsw_pow2(k + 1);
+      dm[DL::qid + k] = 1;
+    }
   if (a.aux >= 0 && a.aux < 3) {
     shot_reals(c, shot)[RL::tail2 + a.aux] = 0.0;
     dm[DL::maxbond + a.aux] = 0;
@@ -424,7 +405,10 @@ __global__ void k_init_R(const DevCtx* __restrict__ cp, OpArgs a) {
   const DevCtx& c = *cp;
   const int shot = blockIdx.y;
   double* R = shot_eng(c, shot) + c.L.off_R;
-  if (a.op == P_C2 && blockIdx.x == 0 && threadIdx.x == 0) shot_eng(c, shot)[c.L.off_B0] = 1.0;  // B_K = [1]
+  if (a.op == P_C2 && blockIdx.x == 0 && threadIdx.x == 0) {   // V_0 = W_K = [1]
+    shot_eng(c, shot)[c.L.off_VL0] = 1.0;
+    shot_eng(c, shot)[c.L.off_WR0] = 1.0;
+  }
   if (a.op == P_DENSE) {
     const int64_t total = mpsw_pow2(c.K);
     if (total > c.L.cap_R || total > c.dense_stride) { if (threadIdx.x == 0 && blockIdx.x == 0) raise_err(c, MPSW_DEV_ERR_CAP); return; }

@@ -92,8 +92,8 @@ struct EngineLayout {
   int64_t off_X, cap_X;     // X_k = R_{k-1} S_k
   int64_t off_X2, cap_X2;   // X after the meeting product (c^2 rounding)
   int64_t off_R, cap_R;     // R factor carried to the right
-  int64_t off_T1, cap_T1;   // Kronecker contraction temporary
-  int64_t off_B0, off_B1, cap_B;  // right-merged blocks (ping-pong)
+  int64_t off_VL0, off_VL1, cap_VL;  // left halves of y, contracted site by site (ping-pong, 2^k x chi_k)
+  int64_t off_WR0, off_WR1, cap_WR;  // right halves of y (ping-pong, chi_k x 2^(K-k))
   int64_t off_M, cap_M;     // bond matrix of the SVD sweep
   int64_t off_US, cap_US;   // U_r Sigma_r
   int64_t off_sA, cap_sA;   // Jacobi working matrix
@@ -134,6 +134,7 @@ struct DevCtx {
   EngineLayout L;
   // c^2 diagonal (shared by all shots)
   const double* c2;
+  const double* c2d;                             // c^2 as a dense field in site order (2^K)
   int64_t off_c2[MPSW_MAXK];
   int c2b[MPSW_MAXK + 1];
   // fused Laplacian MPO cores [wl][wr][2][2] (shared)

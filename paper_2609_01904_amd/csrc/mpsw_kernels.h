@@ -8,17 +8,15 @@ namespace mpsw {
 enum GemmOp {
   G_L2R_EXPLICIT = 1,  // X_k = R_{k-1} S_k with explicit source cores
   G_COPY_RX,           // identity source: X_k = R_{k-1}
-  G_KRON_L1,           // Kronecker (Hadamard) contraction, left-to-right, first GEMM
-  G_KRON_L2,           // ... second GEMM
-  G_MEET,              // product with the right-merged block at the middle site
-  G_KRON_R1,           // Kronecker contraction, right-to-left, first GEMM
-  G_KRON_R2,           // ... second GEMM
   G_DENSE,             // dense contraction step V_{k+1} = V_k G_k
   G_US,                // U_r Sigma_r = M_k V_r
   G_RRF_Y,             // Y = M^T Omega (aux 0) or Y = M^T Z (aux 1): row-space sketch
   G_RRF_Z,             // Z = M Q: column-space iterate (aux 0) or B = M Q (aux 1)
   G_RRF_CORE,          // Tc = core_small Q^T (r x l times l x 2 rho)
-  G_RRF_RES            // Rz = B Q^T (rt x l times l x 2 rho): the sketch's reconstruction of M
+  G_RRF_RES,           // Rz = B Q^T (rt x l times l x 2 rho): the sketch's reconstruction of M
+  G_HALF_L,            // V_{k+1} = V_k Y_k: the left half of y contracted up to the middle site
+  G_HALF_R,            // W_k = Y_k W_{k+1}: the right half of y contracted down to the middle site
+  G_MEET_H             // X2 = (V_n W_n) .* c^2: the Hadamard product's middle unfolding
 };
 
 // Gates of the SVD-stage launches (OpArgs.gate) in the learned-rank rounding.

@@ -257,7 +257,7 @@ void add64(int64_t& off, int64_t& field_off, int64_t cap) {
 void layout_engine(const Plan& p, EngineLayout& L) {
   const int K = p.K, n = p.half;
   std::memset(&L, 0, sizeof(L));
-  int64_t capX = 1, capX2 = 1, capR = 1, capT1 = 1, capB = 1, capM = 2, capUS = 1, capSA = 2, capSJ = 1,
+  int64_t capX = 1, capX2 = 1, capR = 1, capM = 2, capUS = 1, capSA = 2, capSJ = 1,
           capQRS = 1, capQRT = 1, capSA2 = 1, capQRS2 = 1, capQRT2 = 1, capVp = 1, capYv = 1;
   std::vector<int64_t> capIn(K, 1), capQ(K, 1), capQT(K, 1);
   int maxdim = 1;
@@ -288,16 +288,11 @@ void layout_engine(const Plan& p, EngineLayout& L) {
       capM = std::max(capM, 2 * s.rho[1]);
     }
   }
-  if (p.kron) {
-    const auto& s = p.sw.back();  // the Kronecker rounding is listed last
-    for (int k = 0; k < n; ++k)
-      capT1 = std::max(capT1, s.rt[k] * p.D[k] * 2 * p.Rmax[k + 1]);
-    for (int k = n; k < K; ++k) {
-      capT1 = std::max(capT1, 2 * p.Rmax[k] * p.D[k + 1] * p2(K - k - 1));
-      capB = std::max(capB, p.Rmax[k] * p.D[k] * p2(K - k));
-    }
-    capX = std::max(capX, 2 * s.rt[n - 1] * p.Rmax[n] * p.D[n]);
-    for (int k = 0; k < n; ++k) capX = std::max(capX, 2 * s.rt[k] * p.Rmax[k + 1] * p.D[k + 1]);
+  int64_t capVL = 1, capWR = 1;
+  if (p.kron) {   // the c^2 rounding (listed last): y's two halves and the middle unfolding
+    const auto& s = p.sw.back();
+    for (int k = 0; k <= n; ++k) capVL = std::max(capVL, p2(k) * p.Rmax[k]);
+    for (int k = n; k <= K; ++k) capWR = std::max(capWR, p.Rmax[k] * p2(K - k));
     capX2 = 2 * s.rt[n - 1] * p2(K - n);
   }
   int64_t off = 0;
@@ -307,8 +302,8 @@ void layout_engine(const Plan& p, EngineLayout& L) {
   L.cap_X = capX; add64(off, L.off_X, capX);
   L.cap_X2 = capX2; add64(off, L.off_X2, capX2);
   L.cap_R = capR; add64(off, L.off_R, capR);
-  L.cap_T1 = capT1; add64(off, L.off_T1, capT1);
-  L.cap_B = capB; add64(off, L.off_B0, capB); add64(off, L.off_B1, capB);
+  L.cap_VL = capVL; add64(off, L.off_VL0, capVL); add64(off, L.off_VL1, capVL);
+  L.cap_WR = capWR; add64(off, L.off_WR0, capWR); add64(off, L.off_WR1, capWR);
   L.cap_M = capM; add64(off, L.off_M, capM);
   L.cap_US = capUS; add64(off, L.off_US, capUS);
   L.cap_sA = capSA; add64(off, L.off_sA, capSA);
@@ -381,6 +376,7 @@ struct mpsw_state_s {
   int* dims = nullptr;
   double* reals = nullptr;
   double* c2 = nullptr;
+  double* c2d = nullptr;   // c^2 as a dense field in site order (the middle unfolding of the c^2 rounding)
   double* lapW = nullptr;
   double* wavelet = nullptr;
   double* dense = nullptr;
@@ -513,6 +509,7 @@ void fill_ctx(mpsw_state st, DevCtx& h, double* eng, const EngineLayout& L) {
   h.eng = eng;
   h.L = L;
   h.c2 = st->c2;
+  h.c2d = st->c2d;
   int64_t off = 0;
   for (int k = 0; k < st->K && !st->c2b.empty(); ++k) {
     h.off_c2[k] = off;
@@ -630,21 +627,24 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
   }
   launch_init_R(d, a, nshots, strm);
 
-  const std::vector<int>& D = st->c2b;
   const auto& R = st->Rmax;
   if (kind == K_C2) {
+    // the halves of y, for the Hadamard product's middle unfolding
     for (int k = K - 1; k >= n; --k) {
-      const int rd = (K - k - 1) & 1, wr = (K - k) & 1;
       OpArgs g{};
       g.mode = gmode;
       g.shot = -1;
       g.site = k;
-      g.op = G_KRON_R1;
-      g.aux = rd;
-      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, 2 * R[k], (int64_t)D[k + 1] * p2(K - k - 1), 1, nshots, strm); });
-      g.op = G_KRON_R2;
-      g.aux = wr;
-      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, D[k], p2(K - k - 1), (int)(2 * R[k]), nshots, strm); });
+      g.op = G_HALF_R;
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, 2 * R[k], p2(K - k - 1), 1, nshots, strm); });
+    }
+    for (int k = 0; k < n; ++k) {
+      OpArgs g{};
+      g.mode = gmode;
+      g.shot = -1;
+      g.site = k;
+      g.op = G_HALF_L;
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, p2(k), 2 * R[k + 1], 1, nshots, strm); });
     }
   }
   for (int k = 0; k < K; ++k) {
@@ -659,16 +659,10 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
       g.aux = last ? 1 : 0;
       prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, s.rt[k], 2 * s.rin[k + 1], 1, nshots, strm); });
     } else if (kind == K_C2 && k < n) {
-      g.op = G_KRON_L1;
-      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, D[k], 2 * R[k + 1], (int)s.rt[k], nshots, strm); });
-      g.op = G_KRON_L2;
-      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, R[k + 1], D[k + 1], (int)(2 * s.rt[k]), nshots, strm); });
-      if (k == n - 1) {
-        g.op = G_MEET;
-        g.aux = (K - n) & 1;
-        prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, 2 * s.rt[k], p2(K - n), 1, nshots, strm); });
-        meet = true;
-      }
+      if (k < n - 1) continue;   // the identity merges of sites 0..n-2 were set by k_prepare
+      g.op = G_MEET_H;
+      prof(st, MPSW_KC_GEMM, strm, [&] { launch_gemm(d, g, p2(n), p2(K - n), 1, nshots, strm); });
+      meet = true;
     } else {
       g.op = G_COPY_RX;
       g.aux = last ? 1 : 0;
@@ -932,6 +926,15 @@ int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t ch
   return MPSW_OK;
 }
 
+int contract_dense(mpsw_state st, int shot, int slot, std::vector<double>& out);
+
+// c^2 as a dense field in site order, contracted from its operator cores.
+int upload_c2_dense(mpsw_state st, const std::vector<double>& v) {
+  if (!st->c2d) HIP_TRY(st_malloc(st, &st->c2d, (size_t)p2(st->K) * sizeof(double)));
+  HIP_TRY(hipMemcpy(st->c2d, v.data(), (size_t)p2(st->K) * sizeof(double), hipMemcpyHostToDevice));
+  return MPSW_OK;
+}
+
 // Build the step engine once c^2 is known.
 int build_step_engine(mpsw_state st) {
   drop_graphs(st);
@@ -943,7 +946,7 @@ int build_step_engine(mpsw_state st) {
   std::vector<int64_t> r1(K + 1), r2(K + 1), r3(K + 1);
   for (int k = 0; k <= K; ++k) {
     r1[k] = (int64_t)st->lap.bonds[k] * R[k];
-    r2[k] = (k < n) ? (int64_t)st->c2b[k] * R[k] : p2(K - k);
+    r2[k] = (k < n) ? p2(k) : p2(K - k);   // identity basis on the left, dense on the right
     r3[k] = (k == 0 || k == K) ? 1 : 3 * R[k] + 1;
   }
   e.sw = {sweep_caps(r1, K, st->chi_cap), sweep_caps(r3, K, st->chi_cap), sweep_caps(r2, K, st->chi_cap)};
@@ -1081,7 +1084,7 @@ int contract_dense(mpsw_state st, int shot, int slot, std::vector<double>& out) 
   Engine& e = st->eng;
   Engine tmp;
   Engine* use = &e;
-  if (!e.eng) {  // before the velocity: a context without an engine arena
+  if (!e.eng || slot < 0) {  // no engine yet, or the c^2 operator (which may just have changed): a fresh context
     EngineLayout L;
     std::memset(&L, 0, sizeof(L));
     fill_ctx(st, tmp.h, nullptr, L);
@@ -1199,6 +1202,7 @@ int mpsw_destroy(mpsw_state st) {
   st_free(st, st->dims);
   st_free(st, st->reals);
   st_free(st, st->c2);
+  st_free(st, st->c2d);
   st_free(st, st->lapW);
   st_free(st, st->wavelet);
   st_free(st, st->dense);
@@ -1234,6 +1238,8 @@ int mpsw_set_velocity_dense(mpsw_state st, const double* c2, double eps_c) {
   if (lam * lam * mx * st->ndim > 1.0) return fail(MPSW_ECFL, "CFL violated: lambda^2 max(c^2) ndim > 1");
   int rc = dense_to_mps(st, c2, eps_c, p2(st->K), 0, 0, true);
   if (rc != MPSW_OK) return rc;
+  std::vector<double> dense;
+  if ((rc = contract_dense(st, 0, -1, dense)) != MPSW_OK || (rc = upload_c2_dense(st, dense)) != MPSW_OK) return rc;
   if ((rc = build_step_engine(st)) != MPSW_OK) return rc;
   st->have_velocity = true;
   return MPSW_OK;
@@ -1263,6 +1269,7 @@ int mpsw_set_velocity_mpo(mpsw_state st, const int* bonds, const double* cores) 
   }
   const double lam = st->cfg[0].lambda;
   if (lam * lam * mx * st->ndim > 1.0) return fail(MPSW_ECFL, "CFL violated: lambda^2 max(c^2) ndim > 1");
+  if ((rc = upload_c2_dense(st, dense)) != MPSW_OK) return rc;
   if ((rc = build_step_engine(st)) != MPSW_OK) return rc;
   st->have_velocity = true;
   return MPSW_OK;
@@ -1844,8 +1851,8 @@ int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, doubl
   int64_t off = 0;
   auto place = [&](int64_t& o, int64_t cap) { o = off; off += (cap + 31) & ~(int64_t)31; };
   for (int k = 0; k < K; ++k) { place(L.off_in[k], L.cap_in[k]); place(L.off_q[k], L.cap_q[k]); place(L.off_qt[k], L.cap_qt[k]); }
-  place(L.off_X, L.cap_X); place(L.off_X2, L.cap_X2); place(L.off_R, L.cap_R); place(L.off_T1, L.cap_T1);
-  place(L.off_B0, L.cap_B); place(L.off_B1, L.cap_B); place(L.off_M, L.cap_M); place(L.off_US, L.cap_US);
+  place(L.off_X, L.cap_X); place(L.off_X2, L.cap_X2); place(L.off_R, L.cap_R);
+  place(L.off_M, L.cap_M); place(L.off_US, L.cap_US);
   place(L.off_sA, L.cap_sA); place(L.off_sJ, L.cap_sJ); place(L.off_qrS, L.cap_qrS); place(L.off_qrT, L.cap_qrT);
   place(L.off_sA2, L.cap_sA2); place(L.off_qrS2, L.cap_qrS2); place(L.off_qrT2, L.cap_qrT2);
   place(L.off_Vp, L.cap_Vp); place(L.off_Yv, L.cap_Yv);
