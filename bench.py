@@ -374,6 +374,8 @@ def run_form(mpsw, synth, torch, args, batch, precision, rank, model=None, veloc
     t0 = time.perf_counter()
     st, cfg, fields = make_state(mpsw, synth, args.workload, batch, precision, rank, model, args.ordering, velocity)
     tuned = tune
+    if tune is None and args.shapes:
+        tune = tuned = tuple(int(x) for x in args.shapes.split(","))
     if tune is not None:
         st.set_launch_shapes(*tune)
     elif not args.no_tune:
@@ -423,6 +425,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"],
                     help="contraction arithmetic (factorisations and truncation stay FP64)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--shapes", default=None, metavar="Q,B",
+                    help="launch shapes (QR workgroups per shot, Jacobi block; 0 = the width rule) instead of "
+                         "the autotuner, e.g. the pair it picked in an earlier run")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the single-shot FP64 reference run (plain form, rel-L2 of shot 0)")
     ap.add_argument("--rank", default="exact", choices=["exact", "learned"],

@@ -1,9 +1,9 @@
 """The measured workload at full size, in the launch configuration the
 benchmark times: n = 10 (1024 x 1024), chi = 128, eps = 1e-6, the layered
-velocity model, 128 shots advanced together with autotuned launch shapes,
+velocity model, 256 shots advanced together with autotuned launch shapes,
 starting from developed wavefields whose middle bonds sit at the chi cap.
 
-The oracle cannot step 128 shots of this size in a test, so sampled shots are
+The oracle cannot step 256 shots of this size in a test, so sampled shots are
 checked one by one: each sampled shot's two fields before a step are handed to
 the dense-detour oracle stepper (Sec. 4.3 roundings as right-to-left truncated
 TT-SVDs of the dense tensors), which takes the same step; the GPU result must
@@ -45,7 +45,7 @@ def rel(a, b):
 def test_c3_batched_step_matches_oracle_on_sampled_shots(mpsw):
     import torch
     import bench
-    B = 128
+    B = 256
     _say("full-size C3 state,", B, "shots")
     cfg0 = synth.get_config("C3")
     bonds, cores, c2r = oracle_c2(cfg0["c2"], cfg0["eps_c"])
@@ -55,7 +55,7 @@ def test_c3_batched_step_matches_oracle_on_sampled_shots(mpsw):
     st.step(2)
     torch.cuda.synchronize()
     n, N, K = cfg["n"], 1 << cfg["n"], 2 * cfg["n"]
-    sample = [0, 1, 45, 64, 100, 127]
+    sample = [0, 1, 45, 128, 200, 255]
     before = {s: (st.to_dense(s, 1), st.to_dense(s, 0), st.stats(s)["step"]) for s in sample}
     st.step(1)
     torch.cuda.synchronize()
