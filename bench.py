@@ -123,7 +123,7 @@ def make_state(mpsw, synth, workload, batch, precision, rank="exact", model=None
     n = cfg["n"]
     N = 1 << n
     prec = {"fp64": mpsw.MPSW_FP64, "fp32": mpsw.MPSW_FP32, "bf16": mpsw.MPSW_BF16}[precision]
-    rmode = mpsw.MPSW_RANK_LEARNED if rank == "learned" else mpsw.MPSW_RANK_EXACT
+    rmode = {"learned": mpsw.MPSW_RANK_LEARNED, "previous": mpsw.MPSW_RANK_PREVIOUS}.get(rank, mpsw.MPSW_RANK_EXACT)
     order = mpsw.MPSW_INTERLEAVED if ordering == "interleaved" else mpsw.MPSW_SEQUENTIAL
     nd = cfg["ndim"]
     cfgs = [mpsw.make_config(n, cfg["chi"], cfg["eps"], cfg["lam"], precision=prec, rank_mode=rmode, seed=11,
@@ -406,7 +406,8 @@ def run_form(mpsw, synth, torch, args, batch, precision, rank, model=None, veloc
     res = {"value": batch * args.steps / el, "unit": "shot-steps/s",
            "per_shot_steps_per_s": args.steps / el, "ms_per_step": el * 1e3 / args.steps,
            "shots": batch, "precision": precision,
-           "rank": "exact SVD" if rank == "exact" else "learned rank + range finder, exact fallback",
+           "rank": {"exact": "exact SVD", "learned": "learned rank + range finder, exact fallback",
+                    "previous": "previous step's rank + range finder, exact fallback"}[rank],
            "tuned": None if tuned is None else {"qr_workgroups_per_shot": tuned[0], "jacobi_block": tuned[1] or "rule"},
            "sketches": int(sum(x["sketches"] for x in stats)), "fallbacks": int(sum(x["fallbacks"] for x in stats)),
            "setup_s": t1 - t0}
@@ -430,9 +431,10 @@ def main():
                          "the autotuner, e.g. the pair it picked in an earlier run")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the single-shot FP64 reference run (plain form, rel-L2 of shot 0)")
-    ap.add_argument("--rank", default="exact", choices=["exact", "learned"],
+    ap.add_argument("--rank", default="exact", choices=["exact", "learned", "previous"],
                     help="learned: rank network (trained here on spectra logged from a short exact run of the "
-                         "n=8, chi=64 layered-model workload) + randomized range finder with exact fallback")
+                         "n=8, chi=64 layered-model workload) + randomized range finder with exact fallback; "
+                         "previous: the same range finder at each bond's rank of the previous step, no network")
     ap.add_argument("--graph", action="store_true",
                     help="replay captured HIP graphs (three steps per launch) in the timed region; "
                          "the roofline kernel is then timed over an equal eager region after it")
@@ -454,7 +456,8 @@ def main():
     ap.add_argument("--forms", default="fp32,learned",
                     help="comma-separated extra forms timed beside the headline one on the same workload and "
                          "batch: fp32, bf16 (contraction precision), learned (rank network + range finder), "
-                         "chosen (all of fp32 + learned); empty for none")
+                         "previous (range finder at the previous step's ranks), chosen (all of fp32 + learned); "
+                         "empty for none")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -540,7 +543,7 @@ def main():
     forms = {}
     for f in [x for x in args.forms.split(",") if x]:
         prec = {"fp32": "fp32", "bf16": "bf16", "chosen": "fp32"}.get(f, args.precision)
-        rank = "learned" if f in ("learned", "chosen") else args.rank
+        rank = "learned" if f in ("learned", "chosen") else "previous" if f == "previous" else args.rank
         fs, _, _, res, _, _ = run_form(mpsw, synth, torch, args, args.batch, prec, rank,
                                        model if rank == "learned" else None, velocity)
         fs.close()

@@ -61,7 +61,12 @@ enum {
 enum { MPSW_FP64 = 0, MPSW_FP32 = 1, MPSW_BF16 = 2 };
 enum { MPSW_PERIODIC = 0, MPSW_OPEN = 1 };                     /* shift boundary */
 enum { MPSW_SEQUENTIAL = 0, MPSW_INTERLEAVED = 1 };            /* site order */
-enum { MPSW_RANK_EXACT = 0, MPSW_RANK_LEARNED = 1 };           /* truncation rank mode */
+/* truncation rank mode: the exact SVD of every bond (Sec. 4.3); a randomized
+ * range finder at the rank the network proposes; or at the bond's kept rank of
+ * the previous step, with no network (the baseline the network is judged
+ * against).  The two sketch modes share the width rule, the residual test and
+ * the exact fallback described at mpsw_rank_model_set. */
+enum { MPSW_RANK_EXACT = 0, MPSW_RANK_LEARNED = 1, MPSW_RANK_PREVIOUS = 2 };
 
 typedef struct mpsw_config {
   int n;              /* grid 2^n x 2^n, 1 <= n <= 11; K = 2n sites (the tallest QR of a
@@ -71,7 +76,7 @@ typedef struct mpsw_config {
   double lambda;      /* mesh ratio dt/dh of eq. 2, > 0 */
   int precision;      /* MPSW_FP64 | MPSW_FP32 | MPSW_BF16 */
   int boundary;       /* MPSW_PERIODIC (cyclic shifts) | MPSW_OPEN (eq. 11 as printed) */
-  int rank_mode;      /* MPSW_RANK_EXACT | MPSW_RANK_LEARNED */
+  int rank_mode;      /* MPSW_RANK_EXACT | MPSW_RANK_LEARNED | MPSW_RANK_PREVIOUS */
   uint64_t seed;      /* seed of the library's own random sketches */
   int ordering;       /* MPSW_SEQUENTIAL (x bits, then z bits; eq. 3) | MPSW_INTERLEAVED
                          (x_{n-1} z_{n-1} ... x_0 z_0).  Dense fields passed in and out
@@ -251,7 +256,9 @@ int mpsw_set_launch_shapes(mpsw_state st, int qr_nwg, int jac_block);
  * power iteration sketches the bond matrix (Gaussian test matrix from the
  * state's seed), the SVD stage runs on the sketch, and a FP64 residual test
  * keeps it or runs the exact SVD (counted in mpsw_stats.fallbacks).  Required before
- * stepping a learned-rank state.  Errors: EINVAL, EHIP. */
+ * stepping a learned-rank state.  A MPSW_RANK_PREVIOUS state takes r as the
+ * rank the same bond kept in the same rounding at the previous step and needs
+ * no network.  Errors: EINVAL, EHIP. */
 int mpsw_rank_model_set(mpsw_state st, const float* w, int nw);
 
 /* Network inputs of bonds 1..K-1 of rounding `rounding` (0: L psi, 1: c^2 y,

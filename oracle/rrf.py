@@ -105,12 +105,16 @@ class LearnedRounding:
     """State of the learned-rank rounding of one shot across steps: the
     singular-value log each bond's features come from, and the waits."""
 
-    def __init__(self, w, seed, K, rank_of_out=None):
+    def __init__(self, w, seed, K, rank_of_out=None, prev_rank=False):
         from . import mlp
         self.mlp = mlp
         self.w = None if w is None else np.asarray(w, dtype=np.float64)
         self.seed = int(seed)
         self.K = K
+        # baseline without a network: sketch at the rank the bond kept in the
+        # same rounding at the previous step
+        self.prev_rank = bool(prev_rank)
+        self.rank = {}           # (rounding, bond) -> rank kept at the last step
         # rank from the network output (default: ceil(out chi) clamped to [1, chi])
         self.rank_of_out = rank_of_out or (lambda o, chi: int(np.clip(np.ceil(o * chi), 1, chi)))
         self.sig = {}            # (rounding, bond) -> leading 32 singular values of the last step
@@ -122,11 +126,16 @@ class LearnedRounding:
     def planned_width(self, rnd, k, m, n, chi, step):
         """Sketch width l, or 0 when the exact SVD is taken."""
         lg = self.sig.get((rnd, k))
-        if lg is None or lg[0] <= 0.0 or self.w is None:
+        if lg is None or lg[0] <= 0.0 or (self.w is None and not self.prev_rank):
             return 0
-        x = self.mlp.features(lg, k, self.K, step)
-        out, _ = self.mlp.forward(self.w, x[None, :])
-        rhat = self.rank_of_out(float(out[0]), chi)
+        if self.prev_rank:
+            rhat = self.rank.get((rnd, k), 0)
+            if rhat < 1:
+                return 0
+        else:
+            x = self.mlp.features(lg, k, self.K, step)
+            out, _ = self.mlp.forward(self.w, x[None, :])
+            rhat = self.rank_of_out(float(out[0]), chi)
         l = rhat + OVERSAMPLE
         if step < self.skip.get((rnd, k), 0):
             return 0
@@ -146,6 +155,7 @@ class LearnedRounding:
                 E = M - B @ Q.T
                 self.back[(rnd, k)] = 0
                 self.sig[(rnd, k)] = S[:32].copy()
+                self.rank[(rnd, k)] = r
                 return (W[:, :r].T @ Q.T), B @ W[:, :r], S, r, float(np.sum(S[r:] ** 2) + np.sum(E * E))
             self.fallbacks += 1
             b = min(64, max(1, 2 * self.back.get((rnd, k), 0)))
@@ -154,6 +164,7 @@ class LearnedRounding:
         U, s, Vt = np.linalg.svd(M, full_matrices=False)
         r = choose_rank(s, eps, chi)
         self.sig[(rnd, k)] = s[:32].copy()
+        self.rank[(rnd, k)] = r
         return Vt[:r], U[:, :r] * s[:r], s, r, float(np.sum(s[r:] ** 2))
 
     def round(self, cores, eps, chi, step, rnd, log=None, rows=None):

@@ -29,10 +29,35 @@ __device__ __forceinline__ int ld_acquire(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// s_waitcnt vmcnt(0), the export and LDS counters left at their maxima (GFX9
+// encoding): every vector-memory operation of this wave has completed, the
+// L2 write-back or invalidate of a fence included.
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Publication between the workgroups of one shot, which may sit on different
+// XCDs (each with its own L2).  One thread of the producer releases (an
+// agent-scope fence, i.e. an L2 write-back, then a relaxed flag update), one
+// thread of the consumer acquires (relaxed spins, then an agent-scope fence,
+// i.e. an L2 invalidate), and workgroup barriers order the other waves on
+// both sides.  Two waits make that chain hold for every wave: before the
+// producer's barrier every wave waits for its own stores, so the write-back
+// covers all of them; and each fence's cache operation completes before the
+// thread that issued it goes on to the flag or to the barrier, since a fence
+// orders its cache operation only against later accesses of its own wave, not
+// against those of the waves a barrier then releases.
+__device__ __forceinline__ void release_agent() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  wait_vmem();
+}
+__device__ __forceinline__ void acquire_agent() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  wait_vmem();
+}
+
 // One thread waits until *p >= v (bounded).  The spin uses relaxed loads and
-// a single acquire fence follows: an acquire load per spin would invalidate
-// the L2 of the waiting workgroup's XCD on every iteration, evicting the data
-// every other workgroup on that XCD is working on.
+// a single acquire follows: an acquire load per spin would invalidate the L2
+// of the waiting workgroup's XCD on every iteration, evicting the data every
+// other workgroup on that XCD is working on.
 __device__ void wait_geq(const DevCtx& c, const int* p, int v) {
   int it = 0;
   while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) {
@@ -45,18 +70,19 @@ __device__ void wait_geq(const DevCtx& c, const int* p, int v) {
     }
     __builtin_amdgcn_s_sleep(1);
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  acquire_agent();
 }
 
-// Barrier of the nwg workgroups of one shot (arrival counter, monotone).
-// __syncthreads completes every wave's stores within the workgroup; the one
-// agent-scope release (arrival) and acquire (wait) of thread 0 then publish
-// them to, and pick up those of, the other workgroups.
+// Barrier of the nwg workgroups of one shot (arrival counter, monotone):
+// every wave's stores complete, then thread 0 releases them with its arrival
+// and acquires the other workgroups' with its wait.
 __device__ void shot_barrier(const DevCtx& c, int* ctr, int nwg, int& epoch) {
+  wait_vmem();
   __syncthreads();
   ++epoch;
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    release_agent();
+    __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     wait_geq(c, ctr, epoch * nwg);
   }
   __syncthreads();
@@ -492,9 +518,13 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
     }
   }
   __syncthreads();
-  auto publish = [&](int j) {
+  auto publish = [&](int j) {   // see release_agent
+    wait_vmem();
     __syncthreads();
-    if (t == 0) __hip_atomic_store(flags + j, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (t == 0) {
+      release_agent();
+      __hip_atomic_store(flags + j, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   };
   // panel j's reflector on blocks b0..b1 (adjacent, at most 16 columns)
   auto apply = [&](int j, int b0, int b1) {
@@ -1108,6 +1138,7 @@ __global__ __launch_bounds__(256) void k_jacfin(const DevCtx* __restrict__ cp, O
     if (a.aux >= 0 && a.aux < 3) {
       double* lg = re + RL::sigma_log + (a.aux * MPSW_MAXK + k) * 32;
       for (int i = 0; i < 32; ++i) lg[i] = (i < cc) ? sig[order[i]] : 0.0;
+      dm[DL::prank + a.aux * MPSW_MAXK + k] = r;   // a rejected sketch's rank is overwritten by the exact pass
     }
     rank_s = r;
   }

@@ -68,7 +68,8 @@ struct ShotDimsLayout {
   static constexpr int rrf_skip = fallbacks + 1;            // [3][MAXK]
   static constexpr int rrf_back = rrf_skip + 3 * MPSW_MAXK; // [3][MAXK]
   static constexpr int src_iy = rrf_back + 3 * MPSW_MAXK;   // source y (three-dimensional states)
-  static constexpr int size = src_iy + 1;
+  static constexpr int prank = src_iy + 1;                  // [3][MAXK] rank kept per rounding and bond, last step
+  static constexpr int size = prank + 3 * MPSW_MAXK;
 };
 
 // Per-shot double block layout (offsets in doubles, separate small array).
@@ -153,6 +154,7 @@ struct DevCtx {
   const float* mlp_w;                            // rank network parameters (MLP_NPARAM)
   unsigned long long seed;                       // of the Gaussian test matrices
   int rrf_over;                                  // oversampling p of the sketch width
+  int rank_prev;                                 // 1: sketch at the previous step's rank, no network
 };
 
 __host__ __device__ inline int64_t mpsw_pow2(int e) { return (int64_t)1 << e; }

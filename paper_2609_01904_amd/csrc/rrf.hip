@@ -95,15 +95,18 @@ __global__ __launch_bounds__(MLP_NH) void k_rrf_plan(const DevCtx* __restrict__ 
   const double* lg = re + RL::sigma_log + (a.aux * MPSW_MAXK + k) * 32;
   rank_features(c, dm, re, a.aux, k, x, j);
   __syncthreads();
-  const float o = rank_net(c.mlp_w, x, h1, h2, j);
+  // the network's rank, or (baseline mode, no network) the rank this bond
+  // kept in this rounding at the previous step
+  const float o = c.rank_prev ? 0.0f : rank_net(c.mlp_w, x, h1, h2, j);
   if (j == 0) {
-    const int rhat = rank_of(o, chi);
+    // (0 in baseline mode while the bond has no rank of a previous step: no sketch)
+    const int rhat = c.rank_prev ? dm[DL::prank + a.aux * MPSW_MAXK + k] : rank_of(o, chi);
     const int l = rhat + c.rrf_over;
     // a sketch pays off only well below the full width and below the cap (a
     // capped bond's flat tail rarely lets the residual test certify the
     // capped error), and needs a sigma log
     const bool waiting = (a.aux >= 0 && a.aux < 3) && dm[DL::step] < dm[DL::rrf_skip + a.aux * MPSW_MAXK + k];
-    const int ok = (lg[0] > 0.0) && (rhat < chi) && (l <= MPSW_RRF_MAXL) && (4 * l <= 3 * cc) && m >= l && nn >= l &&
+    const int ok = (lg[0] > 0.0) && (rhat >= 1) && (rhat < chi) && (l <= MPSW_RRF_MAXL) && (4 * l <= 3 * cc) && m >= l && nn >= l &&
                    !waiting;
     dm[DL::rrf] = ok ? 1 : 0;
     dm[DL::rrf_l] = ok ? l : 0;

@@ -399,7 +399,8 @@ struct mpsw_state_s {
   int gemm_mode = 0;                   // GemmMode of the step's contractions
   int tune_qr_nwg = 32;                // most workgroups per shot of a QR factorisation
   int tune_jac_b = 0;                  // Jacobi block width (0: rule from the column count)
-  bool learned = false;                // learned-rank rounding (rank network + sketch)
+  bool learned = false;                // sketched rounding (rank network or previous rank + sketch)
+  bool rank_prev = false;              // the sketch rank is the previous step's, no network
   float* mlp_w = nullptr;              // rank network parameters on the device
   bool have_model = false;
   bool graph_mode = false;
@@ -532,6 +533,7 @@ void fill_ctx(mpsw_state st, DevCtx& h, double* eng, const EngineLayout& L) {
   h.mlp_w = st->mlp_w;
   h.seed = (unsigned long long)st->cfg[0].seed;
   h.rrf_over = MPSW_RRF_OVER;
+  h.rank_prev = st->rank_prev ? 1 : 0;
 }
 
 int upload_ctx(Engine& e, hipStream_t s, mpsw_state st = nullptr) {
@@ -994,7 +996,8 @@ int create_group(const mpsw_config* cfgs, int nshots, void* stream, const mpsw_a
     if (c.precision != MPSW_FP64 && c.precision != MPSW_FP32 && c.precision != MPSW_BF16)
       return fail(MPSW_EINVAL, "unknown precision");
     if (c.boundary != MPSW_PERIODIC && c.boundary != MPSW_OPEN) return fail(MPSW_EINVAL, "unknown boundary");
-    if (c.rank_mode != MPSW_RANK_EXACT && c.rank_mode != MPSW_RANK_LEARNED) return fail(MPSW_EINVAL, "unknown rank mode");
+    if (c.rank_mode != MPSW_RANK_EXACT && c.rank_mode != MPSW_RANK_LEARNED && c.rank_mode != MPSW_RANK_PREVIOUS)
+      return fail(MPSW_EINVAL, "unknown rank mode");
     if (c.ordering != MPSW_SEQUENTIAL && c.ordering != MPSW_INTERLEAVED) return fail(MPSW_EINVAL, "unknown site order");
     if (c.n != c0.n || c.lambda != c0.lambda || c.precision != c0.precision || c.boundary != c0.boundary ||
         c.rank_mode != c0.rank_mode || c.ordering != c0.ordering || nd != (c0.ndim ? c0.ndim : 2))
@@ -1007,7 +1010,8 @@ int create_group(const mpsw_config* cfgs, int nshots, void* stream, const mpsw_a
   }
   st->B = nshots;
   st->gemm_mode = (c0.precision == MPSW_FP32) ? GEMM_FP32 : (c0.precision == MPSW_BF16) ? GEMM_BF16X6 : GEMM_FP64;
-  st->learned = (c0.rank_mode == MPSW_RANK_LEARNED);
+  st->learned = (c0.rank_mode != MPSW_RANK_EXACT);
+  st->rank_prev = (c0.rank_mode == MPSW_RANK_PREVIOUS);
   st->n = c0.n;
   st->ndim = c0.ndim ? c0.ndim : 2;
   st->K = st->ndim * c0.n;
@@ -1190,6 +1194,7 @@ int mpsw_set_cores(mpsw_state st, int shot, int64_t step, const int* bonds_prev,
   // the shot's source clock is the checkpoint's; its sketch back-offs restart
   dd[DL::step] = (int)step;
   for (int i = 0; i < 6 * MPSW_MAXK; ++i) dd[DL::rrf_skip + i] = 0;
+  for (int i = 0; i < 3 * MPSW_MAXK; ++i) dd[DL::prank + i] = 0;
   HIP_TRY(hipMemcpy(st->dims + (int64_t)shot * DL::size, dd.data(), DL::size * sizeof(int), hipMemcpyHostToDevice));
   return MPSW_OK;
 }
@@ -1333,6 +1338,7 @@ int mpsw_set_fields(mpsw_state st, int shot, const double* u_prev, const double*
   const int zero = 0;   // this shot's source clock restarts, and so do the sketch back-offs
   HIP_TRY(hipMemcpy(st->dims + (int64_t)shot * DL::size + DL::step, &zero, sizeof(int), hipMemcpyHostToDevice));
   HIP_TRY(hipMemset(st->dims + (int64_t)shot * DL::size + DL::rrf_skip, 0, sizeof(int) * 6 * MPSW_MAXK));
+  HIP_TRY(hipMemset(st->dims + (int64_t)shot * DL::size + DL::prank, 0, sizeof(int) * 3 * MPSW_MAXK));
   st->step = 0;
   return MPSW_OK;
 }
@@ -1383,7 +1389,7 @@ int mpsw_step(mpsw_state st, int k) {
   if (!st) return fail(MPSW_EINVAL, "null state");
   if (k < 0) return fail(MPSW_EINVAL, "k must be >= 0");
   if (!st->have_velocity) return fail(MPSW_ESTATE, "set the velocity before stepping");
-  if (st->learned && !st->have_model) return fail(MPSW_ESTATE, "set the rank model before stepping a learned-rank state");
+  if (st->learned && !st->rank_prev && !st->have_model) return fail(MPSW_ESTATE, "set the rank model before stepping a learned-rank state");
   if (st->graph_mode) {
     int rc = ensure_cap_stream(st);
     if (rc != MPSW_OK) return rc;
@@ -1454,7 +1460,7 @@ int mpsw_group_step(mpsw_group g, int k) {
   const int ns = (int)g->states.size();
   for (mpsw_state st : g->states) {
     if (!st->have_velocity) return fail(MPSW_ESTATE, "set the velocity of every state before stepping");
-    if (st->learned && !st->have_model) return fail(MPSW_ESTATE, "set the rank model of every learned-rank state");
+    if (st->learned && !st->rank_prev && !st->have_model) return fail(MPSW_ESTATE, "set the rank model of every learned-rank state");
   }
   // order after the states' own pending work
   for (int i = 0; i < ns; ++i) {
@@ -1613,7 +1619,7 @@ int mpsw_get_stats(mpsw_state st, int shot, mpsw_stats* out) {
 int mpsw_autotune(mpsw_state st, int steps, int* qr_nwg, int* jac_block_out) {
   if (!st || steps < 1) return fail(MPSW_EINVAL, "null state or steps < 1");
   if (!st->have_velocity) return fail(MPSW_ESTATE, "set the velocity before tuning");
-  if (st->learned && !st->have_model) return fail(MPSW_ESTATE, "set the rank model before tuning");
+  if (st->learned && !st->rank_prev && !st->have_model) return fail(MPSW_ESTATE, "set the rank model before tuning");
   HIP_TRY(hipStreamSynchronize(st->stream));
   // snapshot of everything a step changes: MPS arena, dims, reals, rotation
   const size_t nm = (size_t)st->mps_stride * st->B, nd = (size_t)DL::size * st->B, nr = (size_t)RL::size * st->B;

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libmpsw.so")
 
 MPSW_FP64, MPSW_FP32, MPSW_BF16 = 0, 1, 2
 MPSW_PERIODIC, MPSW_OPEN = 0, 1
-MPSW_RANK_EXACT, MPSW_RANK_LEARNED = 0, 1
+MPSW_RANK_EXACT, MPSW_RANK_LEARNED, MPSW_RANK_PREVIOUS = 0, 1, 2
 MPSW_SEQUENTIAL, MPSW_INTERLEAVED = 0, 1
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ECFL", -6: "ENONFINITE"}
 

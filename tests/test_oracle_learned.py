@@ -71,3 +71,22 @@ def test_accepted_sketch_misses_only_values_below_the_cutoff():
     assert r == 12
     assert np.linalg.norm(US @ Vt - Mx) ** 2 <= tail * (1 + 1e-6)
     assert tail < 40 * (1e-8) ** 2 * 1.01
+
+
+def test_previous_rank_baseline_sketches_at_the_last_kept_rank():
+    """The baseline without a network: the first rounding has no rank to go
+    by (exact SVDs), the second sketches every bond at the rank it kept, and
+    on a tensor of exact rank r those sketches (width r + 8) are all accepted
+    and give the exact rounding."""
+    K, r, chi, eps = 12, 16, 64, 1e-10
+    T, bonds = low_rank_sum(K, r, seed=4)
+    exact = M.round_mps(T, eps, chi)
+    lr = rrf.LearnedRounding(None, seed=5, K=K, prev_rank=True)
+    lr.round(T, eps, chi, step=0, rnd=2)
+    assert lr.sketches == 0
+    assert all(lr.rank[(2, k)] == bonds[k] for k in range(1, K))
+    second, tail = lr.round(T, eps, chi, step=1, rnd=2)
+    assert lr.sketches > 0 and lr.fallbacks == 0
+    assert M.bonds_of(second) == M.bonds_of(exact)
+    ref = M.to_dense(exact)
+    assert np.linalg.norm(M.to_dense(second) - ref) < 1e-12 * np.linalg.norm(ref)
