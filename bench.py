@@ -204,6 +204,21 @@ def cpu_baseline(synth, workload, fields, seconds, ordering="sequential"):
                       f"({model}, {os.cpu_count()} logical CPUs visible)"}
 
 
+def write_metrics(st, path, steps):
+    """Per-step record of shot 0: one JSON line per step."""
+    K = st.K
+    with open(path, "w") as f:
+        for _ in range(steps):
+            st.step(1)
+            s = st.stats(0)
+            rec = {"step": s["step"], "bonds": s["bonds"], "max_exact_bond": s["max_exact_bond"],
+                   "tail2": s["tail2"], "max_jacobi_sweeps": s["max_jacobi_sweeps"],
+                   "sketches": s["sketches"], "fallbacks": s["fallbacks"],
+                   "sigma_middle": [[float(x) for x in st.sigma_log(0, r)[K // 2][:8]] for r in range(3)]}
+            f.write(json.dumps(rec) + "\n")
+    log(f"per-step metrics of shot 0 for {steps} steps in {path}")
+
+
 def copy_calibration(torch):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     nbytes = 1 << 30
@@ -449,6 +464,12 @@ def main():
                          "workload from rest in FP64, FP32 and BF16 contractions (one group), the "
                          "relative L2 of FP32 and BF16 against FP64 at these comma-separated steps")
     ap.add_argument("--save", default=None, help="directory for the trajectory's FP64 fields (.npy)")
+    ap.add_argument("--metrics", default=None, metavar="JSONL",
+                    help="after the timed steps, step shot 0 of the headline state --metrics-steps more steps "
+                         "one at a time and write one JSON line per step: bonds, largest pre-truncation bond "
+                         "and FP64 tail sum per rounding, Jacobi sweeps, sketches and fallbacks, the leading "
+                         "singular values of the middle bond (not part of the timed region)")
+    ap.add_argument("--metrics-steps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (byte-counter calibration)")
     ap.add_argument("--velocity-cores", default=None, metavar="NPZ",
@@ -495,6 +516,8 @@ def main():
                                                    model if args.rank == "learned" else None, velocity,
                                                    kclass=args.kernel_class)
     el_prof = head["ms_per_step"] * args.steps * 1e-3
+    if args.metrics:
+        write_metrics(st, args.metrics, args.metrics_steps)
     free, total = torch.cuda.mem_get_info()
     log(f"bonds {st.bonds(0, 0)}; c^2 bonds {st.bonds(0, 2)}; "
         f"device memory in use {(total - free) / 2**30:.1f} of {total / 2**30:.0f} GiB")

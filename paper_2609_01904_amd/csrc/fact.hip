@@ -23,7 +23,6 @@ namespace mpsw {
 #define QNT 1024   // threads of the QR-family kernels
 #define MPSW_APPLY_LDS (16 * 256 + 256)   // doubles of LDS for apply_reflector
 #define APNT 512   // threads of k_applyq, k_applyv, k_formq (8 waves, no register spills)
-#define QR_HALF_WSP (8 * 256 + 256)   // doubles of reflector workspace for half of a QR workgroup
 
 __device__ __forceinline__ int ld_acquire(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -191,7 +190,109 @@ __device__ void apply_reflector(const double* __restrict__ V, int64_t ldv, doubl
       }
     }
   }
+  wait_vmem();   // other waves read the updated columns next
   __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// One wave applies a staged panel's block reflector to one group of at most
+// 16 columns: C -= V T^T (V^T C), all on the matrix cores, no workgroup
+// synchronisation.  V (mj x bw, unit lower trapezoid; its strict lower part
+// in Vl, column-major with leading dimension ldv) sits in LDS; C (mj x bwc,
+// column-major, leading dimension ldc) and T (BW x BW row-major, upper
+// triangular) in global memory.  The row sum of V^T C runs in any order, so
+// lane (li, lk) takes rows 16 t + 4 lk + e of column li for both operands
+// (4 contiguous doubles per lane); the update's rows are permuted the same
+// way, so each lane writes 4 contiguous rows of its column.
+// ---------------------------------------------------------------------------
+template <int BW>
+__device__ void apply_wave(const double* Vl, int ldv, int mj, int bw, double* C, int64_t ldc, int bwc,
+                           const double* __restrict__ T) {
+  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  // branch-free: every lane loads an in-range element, then selects
+  auto vfull = [&](int rr, int p) -> double {
+    const double x = Vl[min(rr, mj - 1) + ldv * min(p, bw - 1)];
+    const bool in = rr < mj && p < bw;
+    const double y = (in && rr > p) ? x : 0.0;
+    return (in && rr == p) ? 1.0 : y;
+  };
+  const bool colok = li < bwc;
+  // global address space: its loads are counted apart from the LDS reads, so
+  // waiting for V does not wait for C
+  typedef __attribute__((address_space(1))) double gdouble;
+  gdouble* Cc = (gdouble*)(C + (int64_t)(colok ? li : 0) * ldc);   // column 0 stands in for idle lanes
+  const int nchunk = (mj + 15) >> 4, nfull = mj >> 4;
+  constexpr int UN = 2;   // chunks whose loads are in flight together
+  // W = V^T C; acc[v] = W[lk + 4 v][li]
+  mpsw_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  int tt = 0;
+  for (; tt + UN <= nfull; tt += UN) {
+    double cv[UN][4];
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) cv[u][e] = Cc[16 * (tt + u) + 4 * lk + e];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int rb = 16 * (tt + u) + 4 * lk;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(vfull(rb + e, li), colok ? cv[u][e] : 0.0, acc, 0, 0, 0);
+    }
+  }
+  for (; tt < nchunk; ++tt) {
+    const int rb = 16 * tt + 4 * lk;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const double cv = (colok && rb + e < mj) ? Cc[rb + e] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(vfull(rb + e, li), cv, acc, 0, 0, 0);
+    }
+  }
+  // W2 = T^T W: the accumulator of W is the b operand of k-step v
+  mpsw_d4 w2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int sidx = 4 * kk + lk;   // A2[li][sidx] = T[sidx][li], zero below the diagonal
+    const double a = (sidx < BW && li < BW && sidx <= li && li < bw) ? T[sidx * BW + li] : 0.0;
+    w2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, acc[kk], w2, 0, 0, 0);
+  }
+  // C -= V W2 in 16-row tiles; A's row i is tile row 4 (i % 4) + i / 4, so
+  // lane (li, lk) owns rows 4 lk .. 4 lk + 3 of the tile in column li
+  auto tile = [&](int rb0, const double (&cv)[4], bool full) {
+    const int ra = rb0 + 4 * (li & 3) + (li >> 2);
+    mpsw_d4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      if (4 * kk < bw) d = __builtin_amdgcn_mfma_f64_16x16x4f64(vfull(ra, 4 * kk + lk), w2[kk], d, 0, 0, 0);
+    const int rw = rb0 + 4 * lk;
+    if (full) {
+      if (colok) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Cc[rw + v] = cv[v] - d[v];
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (colok && rw + v < mj) Cc[rw + v] = cv[v] - d[v];
+    }
+  };
+  tt = 0;
+  for (; tt + UN <= nfull; tt += UN) {
+    double cv[UN][4];
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) cv[u][e] = Cc[16 * (tt + u) + 4 * lk + e];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) tile(16 * (tt + u), cv[u], true);
+  }
+  for (; tt < nchunk; ++tt) {
+    const int rw = 16 * tt + 4 * lk;
+    double cv[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) cv[e] = (colok && rw + e < mj) ? Cc[rw + e] : 0.0;
+    tile(16 * tt, cv, false);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -222,8 +323,8 @@ __device__ void factor_panel(const DevCtx& c, double* S, int m, int n, int j, do
   // Column i: its Householder vector is kept unscaled in Pn until the panel
   // is done (v_r = scale_i * x_r); the update of columns q > i uses x_r * scale_i.
   __shared__ double wrow[16];   // deferred update of row i-1 of the trailing panel columns
-  for (int i = 0; i < bw; ++i) {
-    if (i > 0 && rs == 0 && q >= i && q < bw) Pn[(i - 1) + (int64_t)mj * q] -= wrow[q];
+  // s2 = |x_i below row i|^2 and dq = x_i . x_q below row i (same order in every thread)
+  auto dots = [&](int i, double& s2, double& dq) {
     double d = 0.0;
     if (q >= i && q < bw) {
       const double* xi = Pn + (int64_t)mj * i;
@@ -233,12 +334,34 @@ __device__ void factor_panel(const DevCtx& c, double* S, int m, int n, int j, do
     d = wave_sum64(d);
     if (lane == 0) part[q * WPC + wq] = d;
     __syncthreads();
-    double s2 = 0.0, dq = 0.0;
+    s2 = 0.0;
+    dq = 0.0;
     for (int u = 0; u < WPC; ++u) {
       s2 += part[i * WPC + u];
       dq += part[q * WPC + u];
     }
-    const double x0 = Pn[i + (int64_t)mj * i];
+  };
+  for (int i = 0; i < bw; ++i) {
+    if (i > 0 && rs == 0 && q >= i && q < bw) Pn[(i - 1) + (int64_t)mj * q] -= wrow[q];
+    double s2, dq;
+    dots(i, s2, dq);
+    double x0 = Pn[i + (int64_t)mj * i];
+    // A column whose entries have fallen to about 1e-150 (the numerically
+    // zero trailing part of a rank-deficient matrix) has squares in the
+    // subnormal range, where s2 keeps only a few bits and the reflector would
+    // not be orthogonal (tau |v|^2 != 2).  Such a column is scaled by 2^500
+    // (exact) and summed again; tau and v do not depend on the scale, and
+    // beta is scaled back.  The test reads the same values in every thread.
+    double unscale = 1.0;
+    if (s2 > 0.0 && fma(x0, x0, s2) < 0x1p-900) {
+      __syncthreads();   // everyone has read part[] and x0
+      if (q == i)
+        for (int r = i + rs; r < mj; r += RS) Pn[r + (int64_t)mj * i] *= 0x1p500;
+      __syncthreads();
+      dots(i, s2, dq);
+      x0 = Pn[i + (int64_t)mj * i];
+      unscale = 0x1p-500;
+    }
     double tau = 0.0, beta = x0, scale = 0.0;
     if (s2 > 0.0) {
       beta = -copysign(sqrt(x0 * x0 + s2), x0);
@@ -256,7 +379,7 @@ __device__ void factor_panel(const DevCtx& c, double* S, int m, int n, int j, do
     if (rs == 0 && q < 16) wrow[q] = wqv;   // row i of column q is read by the whole group above
     if (t == 0) {
       taus[i] = tau;
-      betas[i] = beta;
+      betas[i] = beta * unscale;
       scales[i] = scale;
     }
     __syncthreads();
@@ -517,6 +640,7 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
                    [&](int e, double v) { S[(e % m) + (int64_t)m * (c0 + (int)(e / m))] = v; });
     }
   }
+  wait_vmem();
   __syncthreads();
   auto publish = [&](int j) {   // see release_agent
     wait_vmem();
@@ -550,35 +674,28 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
       factor_panel<BW, QNT>(c, S, m, n, j1, T, lds, red);
       publish(j1);
     }
-    // my other trailing groups, two at a time: waves 0-7 update the first of
-    // a pair and waves 8-15 the second (an empty update when there is none);
-    // both halves pass the same workgroup barriers
-    const int half = t / (QNT / 2);
-    auto apply_pair = [&](int lo0, int hi0, int lo1, int hi1) {
-      const int lo = half ? lo1 : lo0, hi = half ? hi1 : hi0;
-      const int r0 = j * BW, c0 = j * BW, bw = min(BW, n - c0);
-      const int cb = (lo <= hi) ? lo * BW : c0;
-      const int bwc = (lo <= hi) ? min((hi - lo + 1) * BW, n - cb) : 0;
-      apply_reflector<BW, QNT / 128>(S + r0 + (int64_t)m * c0, m, S + r0 + (int64_t)m * cb, 1, m, m - r0, bw, bwc,
-                                     T + (int64_t)j * BW * BW, true, lds + half * QR_HALF_WSP, half * (QNT / 2));
-    };
-    bool have = false;
-    int plo = 0, phi = -1;
+    // my other trailing groups: panel j's reflectors staged in LDS (read after
+    // the acquire of its flag), then one wave per group of up to 16 columns
+    const int r0 = j * BW, mj = m - r0, bwj = min(BW, n - j * BW);
+    const int ldv = mj | 1;   // odd: the 16 columns a load touches sit in distinct LDS banks
+    __syncthreads();          // the LDS held the lookahead panel or the previous stage
+    bulk_copy<8>(mj * bwj, t, QNT, [&](int e) { return S[r0 + (int)(e % mj) + (int64_t)m * (r0 + (int)(e / mj))]; },
+                 [&](int e, double v) { lds[(e % mj) + ldv * (e / mj)] = v; });
+    __syncthreads();
+    int q = 0;
     for (int g = w; g < ngroups; g += P) {
       int lo = max(g * GB, j + 1);
       const int hi = min(g * GB + GB - 1, nbk - 1);
       if (own1 && lo <= j1 && j1 <= hi) lo = j1 + 1;
       if (lo > hi) continue;
-      if (!have) {
-        plo = lo;
-        phi = hi;
-        have = true;
-        continue;
-      }
-      apply_pair(plo, phi, lo, hi);
-      have = false;
+      if (q++ % (QNT / 64) != (t >> 6)) continue;
+      const int cb = lo * BW, bwc = min((hi - lo + 1) * BW, n - cb);
+      apply_wave<BW>(lds, ldv, mj, bwj, S + r0 + (int64_t)m * cb, m, bwc, T + (int64_t)j * BW * BW);
     }
-    if (have) apply_pair(plo, phi, 0, -1);
+    // the next iteration's lookahead reuses the LDS and may read columns this
+    // wave wrote: its stores complete first (a barrier alone does not wait)
+    wait_vmem();
+    __syncthreads();
   }
   // R (n x n) from my columns: row-major R (sweep) or R^T column-major (SVD)
   for (int blk = 0; blk < nbk && Rout; ++blk) {
@@ -1173,8 +1290,9 @@ void launch_sync_reset(const DevCtx* d, int nshots, hipStream_t s) {
 }
 
 void launch_qrf(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, size_t lds, hipStream_t s) {
-  // the panel, or the reflector workspace (all waves, or two halves)
-  lds = std::max(lds, std::max((size_t)MPSW_APPLY_LDS, (size_t)2 * QR_HALF_WSP) * sizeof(double));
+  // the panel with one spare row (the staged reflectors' odd leading
+  // dimension), or the reflector workspace of the lookahead application
+  lds = std::max(lds + (size_t)bw * sizeof(double), (size_t)MPSW_APPLY_LDS * sizeof(double));
   if (bw == 16)
     hipLaunchKernelGGL(k_qrf<16>, dim3(nwg, 1, nshots), dim3(QNT), lds, s, d, a);
   else if (bw == 8)

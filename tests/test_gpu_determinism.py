@@ -1,9 +1,9 @@
 """Run-to-run determinism of the batched step in the shape the benchmark times:
 the n = 10 workload (chi = 128, eps = 1e-6) with 256 shots, in the launch shapes
 the autotuner picks there (1 QR workgroup per shot, Jacobi blocks of 32
-columns) and in the 2-workgroup shape it picks at 128 shots (where the
-workgroups of one shot share its QR panels), stepped twice from the same fields
-in two fresh states.  Every kernel sums in a fixed order and the workgroups of
+columns) and in the 2- and 4-workgroup shapes (where the workgroups of one
+shot share its QR panels through flags), stepped twice from the same fields in
+two fresh states.  Every kernel sums in a fixed order and the workgroups of
 one shot only read panels their owners have published, so the two runs must
 agree bit for bit in every shot's bonds and in sampled fields (a race between
 workgroups shows up here as shots whose truncation ranks differ between the
@@ -46,7 +46,7 @@ def _run(mpsw, shots, steps, sample, shapes):
     return bonds, fields
 
 
-@pytest.mark.parametrize("shapes", [(1, 32), (2, 32)])
+@pytest.mark.parametrize("shapes", [(1, 32), (2, 32), (4, 32)])
 def test_batched_steps_are_bitwise_repeatable(mpsw, shapes):
     shots, steps, sample = 256, 6, (0, 37, 255)
     _say("256 shots, launch shapes", shapes)

@@ -55,3 +55,20 @@ def test_svd(mpsw, m, n):
     np.testing.assert_allclose(Vt @ Vt.T, np.eye(r), atol=1e-12)
     np.testing.assert_allclose(US @ Vt, A, atol=1e-13 * np.sqrt(max(m, n)))
     assert np.all(np.diff(s) <= 1e-15)
+
+
+@pytest.mark.parametrize("scaled", [False, True])
+def test_qr_of_a_numerically_low_rank_field(mpsw, scaled):
+    """The 4096 x 1024 unfolding of the n = 11 layered-model c^2: its trailing
+    columns fall to about 1e-159 of the matrix (squares in the subnormal
+    range) once its numerical rank is spent; the reflectors must stay
+    orthogonal there."""
+    import synth
+    A = synth.get_config("C5")["c2"].reshape(4096, 1024)
+    if scaled:
+        A = A / np.linalg.norm(A)
+    Q, R = mpsw.debug_factor(0, A)
+    err = np.linalg.norm(Q @ R - A) / np.linalg.norm(A)
+    orth = np.linalg.norm(Q.T @ Q - np.eye(Q.shape[1]))
+    print(f"low-rank field QR (scaled {scaled}): |QR - A|/|A| {err:.1e}, |Q^T Q - I| {orth:.1e}", flush=True)
+    assert err < 1e-13 and orth < 1e-11

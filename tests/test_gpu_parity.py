@@ -36,13 +36,11 @@ def make_state(mpsw, n, chi, eps, lam, boundary=0):
 @pytest.mark.parametrize("n", [4, 6, 8, 9, 10, 11])
 def test_velocity_operator_matches_oracle(mpsw, n):
     """The device's TT-SVD of c^2 (Sec. 4.3) against the oracle's, on the
-    layered model at the measured grids: identical bonds, 1e-12 up to n = 10.
-    At n = 11 the two differ by 1.1e-9 (bonds identical, no flagged cut): the
-    right singular vectors of the values near the cutoff differ by up to 1e-4
-    between the device's Jacobi SVD and LAPACK's at the middle sites, which
-    neither a smooth field nor the random matrices of the kernel tests show;
-    the step parity tests take the oracle's c^2 cores, so this set-up path is
-    held to 2e-9 there."""
+    layered model at the measured grids: identical bonds, 1e-12.  (At n = 11
+    the 4096 x 1024 unfolding's numerically zero trailing columns fall to
+    about 1e-159, where the QR's column sums of squares are subnormal; the
+    panel factorisation rescales such columns, see the low-rank field test
+    of the QR kernel.)"""
     eps_c = 1e-8 if n == 4 else 1e-6
     say("velocity", n)
     c2 = synth.layered_fault_velocity(n)
@@ -56,7 +54,7 @@ def test_velocity_operator_matches_oracle(mpsw, n):
     say(f"  bonds {st.bonds(0, 2)}; rel-L2 {err:.2e}; flagged cuts {flagged}")
     assert not flagged
     assert st.bonds(0, 2) == M.bonds_of(ref)
-    assert err < (2e-9 if n == 11 else 1e-12)
+    assert err < 1e-12
     st.close()
 
 
