@@ -1227,12 +1227,19 @@ __global__ __launch_bounds__(256) void k_jacfin(const DevCtx* __restrict__ cp, O
     const double s0 = sig[order[0]];
     const double eps = re[RL::eps];
     const int chi = dm[DL::chi];
+    // Values below 1e-14 ||A||_F are rounding noise: the Jacobi sweep leaves
+    // their columns unrotated (their directions cannot be resolved), so their
+    // vectors are not orthogonal to the others and are never kept, whatever
+    // eps (which matters for eps below about 1e-14 only).
+    double fro2 = 0.0;
+    for (int i = 0; i < cc; ++i) fro2 = fma(sig[order[i]], sig[order[i]], fro2);
+    const double noise = 1e-14 * sqrt(fro2);
     int r = 0;
     bool finite = true;
     for (int i = 0; i < cc; ++i) {
       const double s = sig[order[i]];
       if (!(s == s) || isinf(s)) finite = false;
-      if (s0 > 0.0 && s >= eps * s0) ++r;
+      if (s0 > 0.0 && s >= eps * s0 && s > noise) ++r;
     }
     if (!finite) raise_err(c, MPSW_DEV_ERR_NONFINITE);
     if (r > chi) r = chi;

@@ -72,3 +72,48 @@ def test_qr_of_a_numerically_low_rank_field(mpsw, scaled):
     orth = np.linalg.norm(Q.T @ Q - np.eye(Q.shape[1]))
     print(f"low-rank field QR (scaled {scaled}): |QR - A|/|A| {err:.1e}, |Q^T Q - I| {orth:.1e}", flush=True)
     assert err < 1e-13 and orth < 1e-11
+
+
+def test_svd_of_a_strongly_graded_bond_matrix(mpsw):
+    """A bond matrix of the n = 11 c^2 TT-SVD taken in LAPACK's gauge (site 12,
+    1024 x 190, singular values from 2.3e10 down to 3.5e-8, 18 orders): the
+    values above the noise level 1e-14 ||M||_F are resolved, their vectors
+    are orthonormal and reconstruct M; the values below it are not kept (the
+    Jacobi sweep cannot resolve their directions)."""
+    import synth
+    cfg = synth.get_config("C5")
+    n, eps = cfg["n"], cfg["eps_c"]
+    K = 2 * n
+    T = cfg["c2"].reshape(-1)
+    rt, X, Qs = 1, T.reshape(1, -1), []
+    for k in range(K - 1):   # left-to-right QR sweep of the dense tensor
+        m = 2 * rt
+        A = X.reshape(m, X.size // m)
+        if m <= A.shape[1]:
+            Qs.append(None)
+            X, rt = A, m
+            continue
+        Q, R = np.linalg.qr(A)
+        Qs.append(Q)
+        X, rt = R, R.shape[0]
+    B = X.reshape(rt, -1)
+    for k in range(K - 1, 12, -1):   # right-to-left truncated SVD sweep down to site 12
+        U, s, Vt = np.linalg.svd(B, full_matrices=False)
+        keep = max(1, int(np.sum(s >= eps * s[0])))
+        prev = U[:, :keep] * s[:keep]
+        if Qs[k - 1] is not None:
+            prev = Qs[k - 1] @ prev
+        B = prev.reshape(prev.shape[0] // 2, 2 * keep)
+    M = B
+    ref = np.linalg.svd(M, compute_uv=False)
+    Vt, US = mpsw.debug_factor(1, M)
+    r = Vt.shape[0]
+    noise = 1e-14 * np.linalg.norm(M)
+    sg = np.linalg.norm(US, axis=0)
+    print(f"graded {M.shape}: sigma {ref[0]:.2e} .. {ref[-1]:.2e}, kept {r} of {len(ref)} "
+          f"(above the noise level: {int(np.sum(ref > noise))})", flush=True)
+    # values within a factor 2 of the noise level may fall on either side of it
+    assert int(np.sum(ref > 2 * noise)) <= r <= int(np.sum(ref > noise / 2)), r
+    np.testing.assert_allclose(sg, ref[:r], atol=1e-13 * ref[0] * np.sqrt(M.shape[0]), rtol=0)
+    np.testing.assert_allclose(Vt @ Vt.T, np.eye(r), atol=1e-10)
+    assert np.linalg.norm(US @ Vt - M) <= 1e-13 * np.sqrt(M.shape[0]) * np.linalg.norm(M)
