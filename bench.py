@@ -3,9 +3,9 @@
 One step = the three roundings of the time step (Laplacian MPO, c^2 Hadamard,
 MPS sum + source), each an L->R QR sweep plus an R->L truncated SVD sweep
 (Sec. 4.3), for every shot of the batch.  The default measures the chosen form
-(128 shots advanced together, FP64 throughout, launch shapes autotuned) and,
-beside it, the plain form (one shot) with the relative L2 difference of shot 0
-between the two.  The workload is the n = 10 grid
+(256 shots advanced together, FP64 throughout, launch shapes autotuned) and,
+beside it, the other forms (FP32 contractions, learned rank) and the plain form
+(one shot, FP64, exact SVD).  The workload is the n = 10 grid
 (1024 x 1024, dh = 10 m, dt = 1 ms) over the seeded layered-fault velocity model
 (c^2 MPO cutoff 1e-6), chi_max = 128, eps = 1e-6, Ricker 15 Hz sources at depth
 index 1.  Timing starts from a developed wavefield (a seeded superposition of
