@@ -311,6 +311,41 @@ def mixed_batch(mpsw, synth, torch, args):
         st.close()
 
 
+def mixed_trajectory(mpsw, synth, torch, args):
+    """The batched-shots workload from rest through the given steps, one group
+    graph, in the chosen precision; the first shot of each grid is saved at
+    each of those steps (FP32 .npy, enough for distances down to 1e-7) so that
+    it can be held against the oracle."""
+    marks = sorted(set(int(x) for x in args.trajectory.split(",")))
+    velocity = load_velocity_cores_mixed(args.velocity_cores) if args.velocity_cores else None
+    states, groups, shots = make_mixed_states(mpsw, synth, args.precision, marks[-1], velocity=velocity)
+    first = {}
+    for i, sh in enumerate(shots):
+        first.setdefault(sh["n"], i)
+    grp = mpsw.Group(states)
+    if args.save:
+        os.makedirs(args.save, exist_ok=True)
+    rows, done, t0 = [], 0, time.perf_counter()
+    for mark in marks:
+        while done < mark:
+            k = min(99, mark - done)
+            grp.step(k)
+            torch.cuda.synchronize()
+            done += k
+            log(f"mixed trajectory: step {done} ({time.perf_counter() - t0:.0f} s)")
+        for st in states:
+            n = st.K // 2
+            row = {"step": mark, "n": n, "shot": first[n], "bonds": st.bonds(0, 0)}
+            rows.append(row)
+            if args.save:
+                np.save(os.path.join(args.save, f"gpu_s{first[n]}_u{mark}.npy"), st.to_dense(0, 0).astype(np.float32))
+    print(json.dumps({"workload": "C4", "precision": args.precision, "trajectory": rows,
+                      "seconds": time.perf_counter() - t0}), flush=True)
+    grp.close()
+    for st in states:
+        st.close()
+
+
 def precision_trajectory(mpsw, synth, torch, args):
     """FP64, FP32 and BF16 contractions on the same shot from rest, stepped
     together as one group; rel-L2 of FP32 and BF16 against FP64 at the given
@@ -368,6 +403,25 @@ def load_velocity_cores(path):
         cores.append(flat[o:o + sz].reshape(bonds[k], 2, bonds[k + 1]))
         o += sz
     return bonds, cores
+
+
+def load_velocity_cores_mixed(path):
+    """{n: (bonds, cores)} of the c^2 operators of several grids, saved with
+    numpy.savez(path, bonds_<n>=..., cores_<n>=<flat>)."""
+    out = {}
+    with np.load(path) as z:
+        for key in z.files:
+            if key.startswith("bonds_"):
+                n = int(key[6:])
+                bonds = [int(b) for b in z[key]]
+                flat = np.asarray(z[f"cores_{n}"], dtype=np.float64)
+                cores, o = [], 0
+                for k in range(len(bonds) - 1):
+                    sz = bonds[k] * 2 * bonds[k + 1]
+                    cores.append(flat[o:o + sz].reshape(bonds[k], 2, bonds[k + 1]))
+                    o += sz
+                out[n] = (bonds, cores)
+    return out
 
 
 def accuracy_summary():
@@ -462,8 +516,10 @@ def main():
     ap.add_argument("--trajectory", default=None, metavar="STEPS",
                     help="precision run instead of the throughput measurement: one shot of the "
                          "workload from rest in FP64, FP32 and BF16 contractions (one group), the "
-                         "relative L2 of FP32 and BF16 against FP64 at these comma-separated steps")
-    ap.add_argument("--save", default=None, help="directory for the trajectory's FP64 fields (.npy)")
+                         "relative L2 of FP32 and BF16 against FP64 at these comma-separated steps; "
+                         "with --workload C4, the 64-shot batch from rest in --precision, the first "
+                         "shot of each grid saved at these steps")
+    ap.add_argument("--save", default=None, help="directory for the trajectory's fields (.npy)")
     ap.add_argument("--metrics", default=None, metavar="JSONL",
                     help="after the timed steps, step shot 0 of the headline state --metrics-steps more steps "
                          "one at a time and write one JSON line per step: bonds, largest pre-truncation bond "
@@ -473,7 +529,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (byte-counter calibration)")
     ap.add_argument("--velocity-cores", default=None, metavar="NPZ",
-                    help="c^2 operator as saved cores (bonds, flat cores) instead of the device's TT-SVD of the model")
+                    help="c^2 operator as saved cores (bonds, flat cores; for C4 bonds_<n>, cores_<n> per grid) "
+                         "instead of the device's TT-SVD of the model")
     ap.add_argument("--forms", default="fp32,learned",
                     help="comma-separated extra forms timed beside the headline one on the same workload and "
                          "batch: fp32, bf16 (contraction precision), learned (rank network + range finder), "
@@ -500,7 +557,10 @@ def main():
     import synth
 
     if args.trajectory:
-        precision_trajectory(mpsw, synth, torch, args)
+        if args.workload == "C4":
+            mixed_trajectory(mpsw, synth, torch, args)
+        else:
+            precision_trajectory(mpsw, synth, torch, args)
         return
     if args.workload == "C4":
         mixed_batch(mpsw, synth, torch, args)

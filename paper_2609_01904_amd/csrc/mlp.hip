@@ -204,7 +204,7 @@ int mlp_fail(int code, const std::string& msg) { return mpsw::set_last_error(cod
 struct DevBuf {
   void* p = nullptr;
   ~DevBuf() {
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);   // teardown: nothing to do with an error here
   }
   bool alloc(size_t bytes) { return hipMalloc(&p, bytes) == hipSuccess; }
   float* f() { return (float*)p; }

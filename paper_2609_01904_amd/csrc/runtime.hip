@@ -432,14 +432,16 @@ hipError_t st_malloc(mpsw_state st, T** p, size_t bytes) {
 
 void st_free(mpsw_state st, void* p) {
   if (p == nullptr) return;
+  // teardown: a failing free or synchronisation leaves nothing to undo, so
+  // their status is dropped here (and below) on purpose
   if (st == nullptr || !st->has_alloc) {
-    hipFree(p);
+    (void)hipFree(p);
     return;
   }
   // the caller may hand the block to other work at once: nothing of this
   // state's may still be using it
-  if (st->stream) hipStreamSynchronize(st->stream);
-  else hipDeviceSynchronize();
+  if (st->stream) (void)hipStreamSynchronize(st->stream);
+  else (void)hipDeviceSynchronize();
   auto it = st->alloc_sizes.find(p);
   const size_t bytes = (it != st->alloc_sizes.end()) ? it->second : 0;
   if (it != st->alloc_sizes.end()) st->alloc_sizes.erase(it);
@@ -449,7 +451,7 @@ void st_free(mpsw_state st, void* p) {
 static void drop_graphs(mpsw_state st) {
   for (int i = 0; i < 3; ++i)
     if (st->gexec[i]) {
-      hipGraphExecDestroy(st->gexec[i]);
+      (void)hipGraphExecDestroy(st->gexec[i]);
       st->gexec[i] = nullptr;
     }
 }
@@ -484,9 +486,10 @@ void prof(mpsw_state st, int cls, hipStream_t s, F&& launch) {
     }
     st->prof_ev.push_back(ev);
   }
-  hipEventRecord(st->prof_ev[st->prof_used], s);
+  // a failed record surfaces when mpsw_profile_read reads the pair
+  (void)hipEventRecord(st->prof_ev[st->prof_used], s);
   launch();
-  hipEventRecord(st->prof_ev[st->prof_used + 1], s);
+  (void)hipEventRecord(st->prof_ev[st->prof_used + 1], s);
   st->prof_used += 2;
 }
 
@@ -549,7 +552,7 @@ size_t g_lds_limit = 0;   // bytes of LDS a workgroup may allocate on this devic
 size_t lds_limit() {
   if (g_lds_limit == 0) {
     int dev = 0, v = 0;
-    hipGetDevice(&dev);
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) v = 65536;
     g_lds_limit = (size_t)v;
     set_lds_limits(g_lds_limit);
@@ -895,7 +898,9 @@ int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t ch
   if ((rc = check_dev_err(st)) != MPSW_OK) { cleanup(); st_free(st, e.d); return rc; }
   // bonds of the result
   std::vector<int> dd(DL::size);
-  hipMemcpy(dd.data(), dims, DL::size * sizeof(int), hipMemcpyDeviceToHost);
+  hipError_t herr = hipMemcpy(dd.data(), dims, DL::size * sizeof(int), hipMemcpyDeviceToHost);
+  if (herr != hipSuccess) { cleanup(); st_free(st, e.d); return fail(MPSW_EHIP, std::string("dense_to_mps: ") + hipGetErrorString(herr)); }
+  auto chk = [&](hipError_t x) { if (herr == hipSuccess) herr = x; };
   std::vector<int> bonds(K + 1);
   for (int k = 0; k <= K; ++k) bonds[k] = dd[DL::bonds + k];
   if (to_velocity) {
@@ -907,7 +912,7 @@ int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t ch
     int64_t o = 0;
     for (int k = 0; k < K; ++k) {
       const int64_t sz = (int64_t)bonds[k] * 2 * bonds[k + 1];
-      hipMemcpyAsync(st->c2 + o, mps + offs[k], sz * sizeof(double), hipMemcpyDeviceToDevice, s0);
+      chk(hipMemcpyAsync(st->c2 + o, mps + offs[k], sz * sizeof(double), hipMemcpyDeviceToDevice, s0));
       o += sz;
     }
     st->c2b = bonds;
@@ -915,16 +920,17 @@ int dense_to_mps(mpsw_state st, const double* host_field, double eps, int64_t ch
     for (int k = 0; k < K; ++k) {
       const int64_t sz = (int64_t)bonds[k] * 2 * bonds[k + 1];
       if (sz > st->cap_mps[out_slot][k]) { cleanup(); st_free(st, e.d); return fail(MPSW_ENOMEM, "field rank exceeds chi_max caps"); }
-      hipMemcpyAsync(st->mps + shot * st->mps_stride + st->off_mps[out_slot][k], mps + offs[k], sz * sizeof(double),
-                     hipMemcpyDeviceToDevice, s0);
+      chk(hipMemcpyAsync(st->mps + shot * st->mps_stride + st->off_mps[out_slot][k], mps + offs[k], sz * sizeof(double),
+                         hipMemcpyDeviceToDevice, s0));
     }
     // bonds into the main dims block
-    hipMemcpyAsync(st->dims + (int64_t)shot * DL::size + DL::bonds + out_slot * (MPSW_MAXK + 1), bonds.data(),
-                   (K + 1) * sizeof(int), hipMemcpyHostToDevice, s0);
+    chk(hipMemcpyAsync(st->dims + (int64_t)shot * DL::size + DL::bonds + out_slot * (MPSW_MAXK + 1), bonds.data(),
+                       (K + 1) * sizeof(int), hipMemcpyHostToDevice, s0));
   }
-  hipStreamSynchronize(s0);
+  chk(hipStreamSynchronize(s0));
   cleanup();
   st_free(st, e.d);
+  if (herr != hipSuccess) return fail(MPSW_EHIP, std::string("dense_to_mps: ") + hipGetErrorString(herr));
   return MPSW_OK;
 }
 
@@ -1201,8 +1207,9 @@ int mpsw_set_cores(mpsw_state st, int shot, int64_t step, const int* bonds_prev,
 
 int mpsw_destroy(mpsw_state st) {
   if (!st) return MPSW_OK;
-  if (st->stream) hipStreamSynchronize(st->stream);
-  else hipDeviceSynchronize();
+  // teardown: errors of the synchronisation and the frees are dropped
+  if (st->stream) (void)hipStreamSynchronize(st->stream);
+  else (void)hipDeviceSynchronize();
   st_free(st, st->mps);
   st_free(st, st->dims);
   st_free(st, st->reals);
@@ -1216,9 +1223,9 @@ int mpsw_destroy(mpsw_state st) {
   st_free(st, st->eng.eng);
   st_free(st, st->eng.d);
   st_free(st, st->mlp_w);
-  for (hipEvent_t ev : st->prof_ev) hipEventDestroy(ev);
+  for (hipEvent_t ev : st->prof_ev) (void)hipEventDestroy(ev);
   drop_graphs(st);
-  if (st->cap_stream) hipStreamDestroy(st->cap_stream);
+  if (st->cap_stream) (void)hipStreamDestroy(st->cap_stream);
   delete st;
   return MPSW_OK;
 }
@@ -1328,8 +1335,9 @@ int mpsw_set_fields(mpsw_state st, int shot, const double* u_prev, const double*
       a.slot = slots[t];
       a.shot = shot;
       launch_zero_state(tmp.d, a, st->B, st->stream);
-      hipStreamSynchronize(st->stream);
+      const hipError_t ze = hipStreamSynchronize(st->stream);
       st_free(st, tmp.d);
+      if (ze != hipSuccess) return fail(MPSW_EHIP, std::string("set_fields: ") + hipGetErrorString(ze));
       continue;
     }
     int rc = dense_to_mps(st, fields[t], st->cfg[shot].eps, st->cfg[shot].chi_max, shot, slots[t], false);
@@ -1378,7 +1386,7 @@ int capture_three_steps(mpsw_state st, hipStream_t cap, hipGraphExec_t* exec) {
   st->prof_cls = saved_prof;
   if (ce != hipSuccess) return fail(MPSW_EHIP, std::string("step capture failed: ") + hipGetErrorString(ce));
   const hipError_t ie = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);   // the executable graph no longer needs it
   if (ie != hipSuccess) return fail(MPSW_EHIP, std::string("graph instantiation failed: ") + hipGetErrorString(ie));
   return MPSW_OK;
 }
@@ -1474,7 +1482,7 @@ int mpsw_group_step(mpsw_group g, int k) {
       gen[i] = g->states[i]->engine_gen;
     }
     if (!g->exec || ph != g->phases || gen != g->gens) {
-      if (g->exec) hipGraphExecDestroy(g->exec);
+      if (g->exec) (void)hipGraphExecDestroy(g->exec);
       g->exec = nullptr;
       hipGraph_t graph = nullptr;
       HIP_TRY(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
@@ -1494,11 +1502,11 @@ int mpsw_group_step(mpsw_group g, int k) {
       }
       const hipError_t ee = hipStreamEndCapture(g->cap, &graph);
       if (ce != hipSuccess || ee != hipSuccess) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         return fail(MPSW_EHIP, std::string("group capture failed: ") + hipGetErrorString(ce != hipSuccess ? ce : ee));
       }
       const hipError_t ie = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
-      hipGraphDestroy(graph);
+      (void)hipGraphDestroy(graph);
       if (ie != hipSuccess) return fail(MPSW_EHIP, std::string("graph instantiation failed: ") + hipGetErrorString(ie));
       g->phases = ph;
       g->gens = gen;
@@ -1522,15 +1530,16 @@ int mpsw_group_step(mpsw_group g, int k) {
 
 int mpsw_group_destroy(mpsw_group g) {
   if (!g) return MPSW_OK;
-  if (g->stream) hipStreamSynchronize(g->stream);
-  else hipDeviceSynchronize();
-  if (g->exec) hipGraphExecDestroy(g->exec);
+  // teardown: errors of the synchronisation and the destroys are dropped
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  else (void)hipDeviceSynchronize();
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
   for (hipStream_t s : g->branch)
-    if (s) hipStreamDestroy(s);
+    if (s) (void)hipStreamDestroy(s);
   for (hipEvent_t e : g->join)
-    if (e) hipEventDestroy(e);
-  if (g->fork) hipEventDestroy(g->fork);
-  if (g->cap) hipStreamDestroy(g->cap);
+    if (e) (void)hipEventDestroy(e);
+  if (g->fork) (void)hipEventDestroy(g->fork);
+  if (g->cap) (void)hipStreamDestroy(g->cap);
   delete g;
   return MPSW_OK;
 }
@@ -1661,10 +1670,10 @@ int mpsw_autotune(mpsw_state st, int steps, int* qr_nwg, int* jac_block_out) {
     st->tune_jac_b = b;
     ok = restore();
     if (!ok) return;
-    hipEventRecord(e0, st->stream);
-    for (int i = 0; i < steps; ++i) enqueue_step(st, st->stream);
-    hipEventRecord(e1, st->stream);
-    ok = hipEventSynchronize(e1) == hipSuccess;
+    ok = hipEventRecord(e0, st->stream) == hipSuccess;
+    for (int i = 0; ok && i < steps; ++i) enqueue_step(st, st->stream);
+    ok = ok && hipEventRecord(e1, st->stream) == hipSuccess;
+    ok = ok && hipEventSynchronize(e1) == hipSuccess;
     float ms = 0.0f;
     if (ok) ok = hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
     if (ok && ms < best) {
@@ -1680,8 +1689,8 @@ int mpsw_autotune(mpsw_state st, int steps, int* qr_nwg, int* jac_block_out) {
   st->tune_qr_nwg = best_q;
   st->tune_jac_b = best_b;
   if (ok) ok = restore();
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   cleanup();
   st->graph_mode = graph;
   drop_graphs(st);
@@ -1732,11 +1741,11 @@ static int rank_export(mpsw_state st, int shot, int rounding, float* feats, floa
   float* df = (float*)buf;
   float* dout = df + nf;
   int* dr = (int*)(dout + nb);
-  hipMemsetAsync(buf, 0, nf * sizeof(float) + nb * (sizeof(float) + sizeof(int)), st->stream);
-  launch_rank_export(st->eng.d, shot, rounding, K, df, dout, dr, st->stream);
+  hipError_t e = hipMemsetAsync(buf, 0, nf * sizeof(float) + nb * (sizeof(float) + sizeof(int)), st->stream);
+  if (e == hipSuccess) launch_rank_export(st->eng.d, shot, rounding, K, df, dout, dr, st->stream);
   std::vector<float> hf(nf), ho(nb);
   std::vector<int> hr(nb);
-  hipError_t e = hipMemcpyAsync(hf.data(), df, nf * sizeof(float), hipMemcpyDeviceToHost, st->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(hf.data(), df, nf * sizeof(float), hipMemcpyDeviceToHost, st->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(ho.data(), dout, nb * sizeof(float), hipMemcpyDeviceToHost, st->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(hr.data(), dr, nb * sizeof(int), hipMemcpyDeviceToHost, st->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
@@ -1762,7 +1771,7 @@ int mpsw_debug_sketch_normals(uint64_t seed, int step, int rounding, int site, i
   HIP_TRY(hipMalloc(&d, (size_t)rows * cols * sizeof(double)));
   launch_sketch_normals((unsigned long long)seed, step, rounding, site, rows, cols, d, nullptr);
   hipError_t e = hipMemcpy(out, d, (size_t)rows * cols * sizeof(double), hipMemcpyDeviceToHost);
-  hipFree(d);
+  (void)hipFree(d);
   if (e != hipSuccess) return fail(MPSW_EHIP, hipGetErrorString(e));
   return MPSW_OK;
 }
@@ -1867,7 +1876,11 @@ int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, doubl
   const int64_t core_cap = (int64_t)q * n + 2;
   double *eng = nullptr, *mps = nullptr, *reals = nullptr;
   int *dims = nullptr, *err = nullptr, *sync = nullptr;
-  auto cleanup = [&]() { hipFree(eng); hipFree(mps); hipFree(reals); hipFree(dims); hipFree(err); hipFree(sync); };
+  auto cleanup = [&]() {
+    for (void* p : {(void*)eng, (void*)mps, (void*)reals, (void*)dims, (void*)err, (void*)sync}) (void)hipFree(p);
+  };
+  hipError_t herr = hipSuccess;   // the first failing copy or synchronisation
+  auto chk = [&](hipError_t x) { if (herr == hipSuccess) herr = x; };
   if (hipMalloc(&eng, L.stride * 8) || hipMalloc(&mps, core_cap * 8) || hipMalloc(&reals, RL::size * 8) ||
       hipMalloc(&dims, DL::size * 4) || hipMalloc(&err, 4) || hipMalloc(&sync, MPSW_SYNC_STRIDE * 4)) {
     cleanup();
@@ -1887,36 +1900,42 @@ int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, doubl
   hr[RL::eps] = 0.0;
   if (op == 0) { hd[DL::rt + 0] = m / 2; hd[DL::rin + 1] = n; }
   else { hd[DL::rt + 1] = m; hd[DL::rho + 2] = n / 2; }
-  hipMemcpy(dims, hd.data(), DL::size * 4, hipMemcpyHostToDevice);
-  hipMemcpy(reals, hr.data(), RL::size * 8, hipMemcpyHostToDevice);
-  hipMemset(err, 0, 4);
-  hipMemcpy(eng + (op == 0 ? L.off_X : L.off_M), A, (size_t)m * n * 8, hipMemcpyHostToDevice);
+  chk(hipMemcpy(dims, hd.data(), DL::size * 4, hipMemcpyHostToDevice));
+  chk(hipMemcpy(reals, hr.data(), RL::size * 8, hipMemcpyHostToDevice));
+  chk(hipMemset(err, 0, 4));
+  chk(hipMemcpy(eng + (op == 0 ? L.off_X : L.off_M), A, (size_t)m * n * 8, hipMemcpyHostToDevice));
+  if (herr != hipSuccess) { cleanup(); return fail(MPSW_EHIP, std::string("debug_factor: ") + hipGetErrorString(herr)); }
   int rc = upload_ctx(e, nullptr);
   if (rc != MPSW_OK) { cleanup(); return rc; }
   hipStream_t s0 = nullptr;
   int ret = 0;
   if (op == 0) {
     const int bw = qr_panel(m);
-    if (bw == 0) { cleanup(); hipFree(e.d); return fail(MPSW_ENOMEM, "matrix too tall for LDS"); }
+    if (bw == 0) { cleanup(); (void)hipFree(e.d); return fail(MPSW_ENOMEM, "matrix too tall for LDS"); }
     OpArgs a{};
     a.shot = -1; a.site = 0; a.op = 0;
     launch_sync_reset(e.d, 1, s0);
     launch_qrf(e.d, a, bw, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(n, bw))), 1, (size_t)m * bw * 8, s0);
     // Q = Q_0 [I_q; 0] through the absorb kernel: US = I (q x q), rho_1 = q
     std::vector<int> d1(DL::size);
-    hipMemcpy(d1.data(), dims, DL::size * 4, hipMemcpyDeviceToHost);
-    const int rt1 = d1[DL::rt + 1];
+    chk(hipMemcpy(d1.data(), dims, DL::size * 4, hipMemcpyDeviceToHost));
+    const int rt1 = (herr == hipSuccess) ? d1[DL::rt + 1] : 0;
+    if (rt1 < 1 || rt1 > std::min(m, n)) {   // nothing is copied out unless the rank is sane
+      cleanup();
+      (void)hipFree(e.d);
+      return fail(MPSW_EHIP, "debug_factor: QR rank not read back");
+    }
     std::vector<double> I((size_t)rt1 * rt1, 0.0);
     for (int i = 0; i < rt1; ++i) I[(size_t)i * rt1 + i] = 1.0;
-    hipMemcpy(eng + L.off_US, I.data(), I.size() * 8, hipMemcpyHostToDevice);
+    chk(hipMemcpy(eng + L.off_US, I.data(), I.size() * 8, hipMemcpyHostToDevice));
     d1[DL::rho + 1] = rt1;
-    hipMemcpy(dims, d1.data(), DL::size * 4, hipMemcpyHostToDevice);
+    chk(hipMemcpy(dims, d1.data(), DL::size * 4, hipMemcpyHostToDevice));
     OpArgs ap{};
     ap.shot = -1; ap.site = 1;
     launch_applyq(e.d, ap, bw, std::max(1, cdiv(rt1, 16)), 1, s0);
-    hipDeviceSynchronize();
-    hipMemcpy(out1, eng + L.off_M, (size_t)m * rt1 * 8, hipMemcpyDeviceToHost);
-    hipMemcpy(out2, eng + L.off_R, (size_t)rt1 * n * 8, hipMemcpyDeviceToHost);
+    chk(hipDeviceSynchronize());
+    chk(hipMemcpy(out1, eng + L.off_M, (size_t)m * rt1 * 8, hipMemcpyDeviceToHost));
+    chk(hipMemcpy(out2, eng + L.off_R, (size_t)rt1 * n * 8, hipMemcpyDeviceToHost));
     ret = rt1;
   } else {
     OpArgs v{};
@@ -1924,7 +1943,7 @@ int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, doubl
     launch_sync_reset(e.d, 1, s0);
     const int rows = std::max(m, n);
     const int bw = qr_panel(rows);
-    if (bw == 0) { cleanup(); hipFree(e.d); return fail(MPSW_ENOMEM, "matrix too tall for LDS"); }
+    if (bw == 0) { cleanup(); (void)hipFree(e.d); return fail(MPSW_ENOMEM, "matrix too tall for LDS"); }
     OpArgs qa = v;
     qa.op = 1;
     launch_qrf(e.d, qa, bw, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(q, bw))), 1, (size_t)rows * bw * 8, s0);
@@ -1932,7 +1951,7 @@ int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, doubl
     qa.op = 2;
     launch_qrf(e.d, qa, bw2, (int)std::min<int64_t>(32, std::max<int64_t>(1, cdiv(q, bw2))), 1, (size_t)q * bw2 * 8, s0);
     const int b = jac_block(q);
-    if (b == 0) { cleanup(); hipFree(e.d); return fail(MPSW_ENOMEM, "columns too long for LDS"); }
+    if (b == 0) { cleanup(); (void)hipFree(e.d); return fail(MPSW_ENOMEM, "columns too long for LDS"); }
     const int64_t nb = cdiv(q, b);
     launch_jac(e.d, v, b, (int)std::max<int64_t>(1, (nb + (nb & 1)) / 2), 1, (size_t)2 * b * (q + 1) * 8, q, s0);
     launch_jacfin(e.d, v, 1, s0);
@@ -1940,19 +1959,24 @@ int mpsw_debug_factor(int op, int m, int n, const double* A, double* out1, doubl
     OpArgs g{};
     g.shot = -1; g.site = 1; g.slot = 0; g.op = G_US;
     launch_gemm(e.d, g, m, q, 1, 1, s0);
-    hipDeviceSynchronize();
+    chk(hipDeviceSynchronize());
     std::vector<int> d1(DL::size);
-    hipMemcpy(d1.data(), dims, DL::size * 4, hipMemcpyDeviceToHost);
-    const int r = d1[DL::rho + 1];
-    hipMemcpy(out1, mps, (size_t)r * n * 8, hipMemcpyDeviceToHost);
-    hipMemcpy(out2, eng + L.off_US, (size_t)m * r * 8, hipMemcpyDeviceToHost);
+    chk(hipMemcpy(d1.data(), dims, DL::size * 4, hipMemcpyDeviceToHost));
+    const int r = (herr == hipSuccess) ? d1[DL::rho + 1] : -1;
+    if (r >= 0 && r <= q) {   // nothing is copied out unless the rank is sane
+      chk(hipMemcpy(out1, mps, (size_t)r * n * 8, hipMemcpyDeviceToHost));
+      chk(hipMemcpy(out2, eng + L.off_US, (size_t)m * r * 8, hipMemcpyDeviceToHost));
+    } else if (herr == hipSuccess) {
+      herr = hipErrorInvalidValue;
+    }
     ret = r;
   }
   int he = 0;
-  hipMemcpy(&he, err, 4, hipMemcpyDeviceToHost);
+  chk(hipMemcpy(&he, err, 4, hipMemcpyDeviceToHost));
   const hipError_t le = hipGetLastError();
   cleanup();
-  hipFree(e.d);
+  (void)hipFree(e.d);
+  if (herr != hipSuccess) return fail(MPSW_EHIP, std::string("debug_factor: ") + hipGetErrorString(herr));
   if (le != hipSuccess) return fail(MPSW_EHIP, std::string("debug_factor: ") + hipGetErrorString(le));
   if (he) return fail(MPSW_ENOMEM, "debug_factor: device error bits " + std::to_string(he));
   return ret;
@@ -1984,7 +2008,11 @@ int mpsw_debug_sketch(const double* A, int m, int n, int l, double eps, int chi,
   const int64_t core_cap = (int64_t)l * n + 2;
   double *eng = nullptr, *mps = nullptr, *reals = nullptr;
   int *dims = nullptr, *err = nullptr, *sync = nullptr;
-  auto cleanup = [&]() { hipFree(eng); hipFree(mps); hipFree(reals); hipFree(dims); hipFree(err); hipFree(sync); };
+  auto cleanup = [&]() {
+    for (void* p : {(void*)eng, (void*)mps, (void*)reals, (void*)dims, (void*)err, (void*)sync}) (void)hipFree(p);
+  };
+  hipError_t herr = hipSuccess;   // the first failing copy or synchronisation
+  auto chk = [&](hipError_t x) { if (herr == hipSuccess) herr = x; };
   if (hipMalloc(&eng, L.stride * 8) || hipMalloc(&mps, core_cap * 8) || hipMalloc(&reals, RL::size * 8) ||
       hipMalloc(&dims, DL::size * 4) || hipMalloc(&err, 4) || hipMalloc(&sync, MPSW_SYNC_STRIDE * 4)) {
     cleanup();
@@ -2010,10 +2038,11 @@ int mpsw_debug_sketch(const double* A, int m, int n, int l, double eps, int chi,
   hd[DL::rrf] = 1;
   hd[DL::rrf_l] = l;
   hr[RL::eps] = eps;
-  hipMemcpy(dims, hd.data(), DL::size * 4, hipMemcpyHostToDevice);
-  hipMemcpy(reals, hr.data(), RL::size * 8, hipMemcpyHostToDevice);
-  hipMemset(err, 0, 4);
-  hipMemcpy(eng + L.off_M, A, (size_t)m * n * 8, hipMemcpyHostToDevice);
+  chk(hipMemcpy(dims, hd.data(), DL::size * 4, hipMemcpyHostToDevice));
+  chk(hipMemcpy(reals, hr.data(), RL::size * 8, hipMemcpyHostToDevice));
+  chk(hipMemset(err, 0, 4));
+  chk(hipMemcpy(eng + L.off_M, A, (size_t)m * n * 8, hipMemcpyHostToDevice));
+  if (herr != hipSuccess) { cleanup(); return fail(MPSW_EHIP, std::string("debug_sketch: ") + hipGetErrorString(herr)); }
   int rc = upload_ctx(e, nullptr);
   if (rc != MPSW_OK) { cleanup(); return rc; }
   hipStream_t s0 = nullptr;
@@ -2070,11 +2099,11 @@ int mpsw_debug_sketch(const double* A, int m, int n, int l, double eps, int chi,
   launch_gemm(d, g, m, n, 1, 1, s0);
   launch_rrf_resid(d, r, 1, s0);
   launch_rrf_accept(d, r, (int64_t)m * n, 1, s0);
-  hipDeviceSynchronize();
-  std::vector<int> d1(DL::size);
-  std::vector<double> r1(RL::size);
-  hipMemcpy(d1.data(), dims, DL::size * 4, hipMemcpyDeviceToHost);
-  hipMemcpy(r1.data(), reals, RL::size * 8, hipMemcpyDeviceToHost);
+  chk(hipDeviceSynchronize());
+  std::vector<int> d1(DL::size, 0);
+  std::vector<double> r1(RL::size, 0.0);
+  chk(hipMemcpy(d1.data(), dims, DL::size * 4, hipMemcpyDeviceToHost));
+  chk(hipMemcpy(r1.data(), reals, RL::size * 8, hipMemcpyDeviceToHost));
   for (int i = 0; i < 32; ++i) sig[i] = r1[RL::sigma_log + (rounding * MPSW_MAXK + k) * 32 + i];
   stats[0] = r1[RL::rrf_res2];
   stats[1] = r1[RL::rrf_tail];
@@ -2082,10 +2111,11 @@ int mpsw_debug_sketch(const double* A, int m, int n, int l, double eps, int chi,
   *rank = d1[DL::rho + k];
   *accepted = (d1[DL::rrf] == 2) ? 1 : 0;
   int he = 0;
-  hipMemcpy(&he, err, 4, hipMemcpyDeviceToHost);
+  chk(hipMemcpy(&he, err, 4, hipMemcpyDeviceToHost));
   const hipError_t le = hipGetLastError();
   cleanup();
-  hipFree(e.d);
+  (void)hipFree(e.d);
+  if (herr != hipSuccess) return fail(MPSW_EHIP, std::string("debug_sketch: ") + hipGetErrorString(herr));
   if (le != hipSuccess) return fail(MPSW_EHIP, std::string("debug_sketch: ") + hipGetErrorString(le));
   if (he) return fail(MPSW_ENOMEM, "debug_sketch: device error bits " + std::to_string(he));
   return MPSW_OK;

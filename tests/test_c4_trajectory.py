@@ -1,0 +1,152 @@
+"""The batched-shots workload at its stated length against the FP64 oracle.
+
+C4: 64 Ricker shots on grids n in {8, 9, 10} with chi caps in {32, 64, 128}
+(seeded shot list), FP32 contractions, 1000 steps from rest, all shots stepped
+by one group graph; the c^2 operator of each grid is the oracle's TT-SVD of
+that grid's layered model in both runs.  The first shot of each grid is held
+against the oracle at steps 250, 500 and 1000.  The GPU side runs on a GPU
+machine:
+
+    python tests/test_c4_trajectory.py c2 C2CORES.npz
+    python bench.py --workload C4 --precision fp32 --trajectory 250,500,1000 --velocity-cores C2CORES.npz --save GPU_DIR
+
+The oracle side runs on the host, one process per sampled shot and run (the
+n = 10 shot takes about 20 minutes a run):
+
+    python tests/test_c4_trajectory.py oracle ORACLE_DIR SHOT              # the dense-detour stepper
+    python tests/test_c4_trajectory.py floor ORACLE_DIR SHOT 1e-15 d15     # the same, inputs perturbed by 1e-15
+    python tests/test_c4_trajectory.py floor ORACLE_DIR SHOT 5.96e-8 u32   # ... by FP32's unit roundoff
+
+for SHOT in the sampled shots (`sampled()`), and the comparison is this test,
+with MPSW_C4_GPU and MPSW_C4_ORACLE set to the two directories (it is skipped
+without them).  As for the n = 10 precision trajectory, the floor runs give
+the distance at which two computations of the same truncated trajectory that
+differ by rounding-sized perturbations part; FP32 must lie within 1e-6 or 10x
+the larger of the floors at 1e-15 and at FP32's unit roundoff.  The summary
+is written by
+
+    python tests/test_c4_trajectory.py summary GPU_DIR ORACLE_DIR > profiles/trajectory_C4.json
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+REPO = os.path.dirname(ROOT)
+for p in (REPO, ROOT):
+    if p not in sys.path:
+        sys.path.insert(0, p)
+
+MARKS = (250, 500, 1000)
+NSHOTS, SEED = 64, 1
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def shot_list():
+    import synth
+    return synth.batch_shots(NSHOTS, seed=SEED, steps=max(MARKS))
+
+
+def sampled():
+    """Global indices of the first shot of each grid size."""
+    first = {}
+    for i, sh in enumerate(shot_list()):
+        first.setdefault(sh["n"], i)
+    return [first[n] for n in sorted(first)]
+
+
+def c2_cores(out):
+    """The oracle's c^2 operator of each grid's layered model (bonds_<n>, cores_<n>)."""
+    from oracle import mps as M
+    from oracle import stepper as S
+    import synth
+    arrs = {}
+    for n in sorted({sh["n"] for sh in shot_list()}):
+        cfg = synth.get_config("C3", n=n)
+        ref = S.c2_mps(cfg["c2"], n, cfg["eps_c"])
+        arrs[f"bonds_{n}"] = np.array(M.bonds_of(ref))
+        arrs[f"cores_{n}"] = np.concatenate([c.ravel() for c in ref])
+    np.savez(out, **arrs)
+
+
+def _oracle_run(out, shot, delta=0.0, tag="oracle"):
+    from oracle import mps as M
+    from oracle import stepper as S
+    import sensitivity
+    import synth
+    sh = shot_list()[shot]
+    n = sh["n"]
+    N = 1 << n
+    cfg = synth.get_config("C3", n=n)
+    c2r = M.to_dense(S.c2_mps(cfg["c2"], n, cfg["eps_c"])).reshape(N, N)
+    lam = sh["dt"] / sh["dh"]
+    ds = sensitivity.PerturbedStepper(delta, 0, n, lam, sh["eps"], sh["chi"], c2r,
+                                      src=(sh["ix"], sh["iz"]), wavelet=sh["wavelet_samples"])
+    ds.keep_log = False
+    for k in range(1, max(MARKS) + 1):
+        ds.step()
+        if k in MARKS:
+            np.save(os.path.join(out, f"{tag}_s{shot}_u{k}.npy"), ds.dense())
+        if k % 100 == 0:
+            print(tag, "shot", shot, "step", k, ds.ranks[-1][2], flush=True)
+    if delta == 0.0:
+        json.dump({"first_flag": ds.first_flag(), "bonds": ds.ranks[-1][2]},
+                  open(os.path.join(out, f"{tag}_s{shot}_log.json"), "w"))
+
+
+def summary(gpu, orc):
+    rows = []
+    for shot in sampled():
+        sh = shot_list()[shot]
+        log = json.load(open(os.path.join(orc, f"oracle_s{shot}_log.json")))
+        for k in MARKS:
+            o = np.load(os.path.join(orc, f"oracle_s{shot}_u{k}.npy"))
+            g = np.load(os.path.join(gpu, f"gpu_s{shot}_u{k}.npy")).astype(np.float64)
+            r = {"shot": shot, "n": sh["n"], "chi": sh["chi"], "step": k, "fp32": rel(g, o),
+                 "first_flagged_cut": log["first_flag"]}
+            for tag in ("d15", "u32"):
+                f = os.path.join(orc, f"{tag}_s{shot}_u{k}.npy")
+                if os.path.exists(f):
+                    r[f"floor_{tag}"] = rel(np.load(f), o)
+            rows.append(r)
+    return {"workload": "C4: 64 shots, n in {8, 9, 10}, chi in {32, 64, 128}, eps=1e-6, FP32 contractions, "
+                        "1000 steps from rest in one group graph; first shot of each grid against the FP64 oracle",
+            "checkpoints": rows}
+
+
+@pytest.mark.skipif(not (os.environ.get("MPSW_C4_GPU") and os.environ.get("MPSW_C4_ORACLE")),
+                    reason="needs the saved GPU and oracle trajectories (see the module docstring)")
+def test_c4_trajectory_against_oracle():
+    s = summary(os.environ["MPSW_C4_GPU"], os.environ["MPSW_C4_ORACLE"])
+    print(json.dumps(s, indent=1))
+    for r in s["checkpoints"]:
+        floor = max(r["floor_d15"], r.get("floor_u32", 0.0))
+        assert r["fp32"] <= max(1e-6, 10.0 * floor), r
+
+
+def test_sampled_shots_cover_every_grid():
+    """The comparison samples one shot of each grid size of the shot list."""
+    shots = shot_list()
+    idx = sampled()
+    assert sorted(shots[i]["n"] for i in idx) == sorted({sh["n"] for sh in shots})
+    assert all(shots[i]["n"] != shots[j]["n"] for i in idx for j in idx if i != j)
+
+
+if __name__ == "__main__":
+    what, out = sys.argv[1], sys.argv[2]
+    if what == "c2":
+        c2_cores(out)
+    elif what == "oracle":
+        os.makedirs(out, exist_ok=True)
+        _oracle_run(out, int(sys.argv[3]))
+    elif what == "floor":
+        os.makedirs(out, exist_ok=True)
+        _oracle_run(out, int(sys.argv[3]), float(sys.argv[4]), sys.argv[5])
+    elif what == "summary":
+        print(json.dumps(summary(out, sys.argv[3]), indent=1))
