@@ -349,13 +349,25 @@ def mixed_trajectory(mpsw, synth, torch, args):
 def precision_trajectory(mpsw, synth, torch, args):
     """FP64, FP32 and BF16 contractions on the same shot from rest, stepped
     together as one group; rel-L2 of FP32 and BF16 against FP64 at the given
-    steps (the FP64 fields can be saved and held against the oracle)."""
+    steps (the fields can be saved and held against the oracle).  With
+    --rank learned a fourth member runs the mixed form: BF16 contractions and
+    the learned rank (network trained as for the headline's forms)."""
     cfg = synth.get_config(args.workload)
     n = cfg["n"]
     precs = [("fp64", mpsw.MPSW_FP64), ("fp32", mpsw.MPSW_FP32), ("bf16", mpsw.MPSW_BF16)]
+    model = None
+    if args.rank == "learned":
+        t0 = time.perf_counter()
+        model, nrows = train_rank_model(mpsw, synth)
+        log(f"rank network trained on {nrows} logged bonds in {time.perf_counter() - t0:.1f} s")
+        precs.append(("bf16l", mpsw.MPSW_BF16))
     states = []
-    for _, p in precs:
-        st = mpsw.State(mpsw.make_config(n, cfg["chi"], cfg["eps"], cfg["lam"], precision=p))
+    for name, p in precs:
+        learned = name == "bf16l"
+        st = mpsw.State(mpsw.make_config(n, cfg["chi"], cfg["eps"], cfg["lam"], precision=p, seed=11,
+                                         rank_mode=mpsw.MPSW_RANK_LEARNED if learned else mpsw.MPSW_RANK_EXACT))
+        if learned:
+            st.set_rank_model(model)
         if args.velocity_cores:
             st.set_velocity_mpo(*load_velocity_cores(args.velocity_cores))
         else:
@@ -366,8 +378,10 @@ def precision_trajectory(mpsw, synth, torch, args):
     marks = sorted(set(int(x) for x in args.trajectory.split(",")))
     if args.save:
         os.makedirs(args.save, exist_ok=True)
-        np.save(os.path.join(args.save, "gpu_c2r.npy"), states[0].to_dense(0, 2))
+        if args.save_window <= 0:
+            np.save(os.path.join(args.save, "gpu_c2r.npy"), states[0].to_dense(0, 2))
     rows, done, t0 = [], 0, time.perf_counter()
+    window = {"outside_norm": {}}
     for mark in marks:
         while done < mark:
             k = min(50, mark - done)
@@ -381,12 +395,29 @@ def precision_trajectory(mpsw, synth, torch, args):
         for (name, _), v in zip(precs[1:], u[1:]):
             row[f"rel_l2_{name}_vs_fp64"] = float(np.linalg.norm(v - u[0])) / nb if nb > 0 else 0.0
         rows.append(row)
-        if args.save:   # FP64 fields in FP64; the others in FP32, enough for their distances
+        if args.save and args.save_window > 0:
+            # every member in FP64 on the W x W window (surface rows, centred on
+            # the source) that holds the wavefield, and the norm of what lies
+            # outside it, so the full-field distance can be bounded
+            W = min(args.save_window, 1 << n)
+            x0 = min(max(cfg["ix"] - W // 2, 0), (1 << n) - W)
+            window.update({"x0": x0, "z0": 0, "W": W})
+            for (name, _), v in zip(precs, u):
+                np.save(os.path.join(args.save, f"gpu_{name}_u{mark}.npy"), v[x0:x0 + W, :W])
+                out_sq = float(np.sum(v * v)) - float(np.sum(v[x0:x0 + W, :W] ** 2))
+                window["outside_norm"][f"{name}_u{mark}"] = float(np.sqrt(max(out_sq, 0.0)))
+        elif args.save:   # FP64 fields in FP64; the others in FP32, enough for their distances
             np.save(os.path.join(args.save, f"gpu_fp64_u{mark}.npy"), u[0])
             for (name, _), v in zip(precs[1:], u[1:]):
                 np.save(os.path.join(args.save, f"gpu_{name}_u{mark}.npy"), v.astype(np.float32))
-    print(json.dumps({"workload": args.workload, "trajectory": rows,
-                      "seconds": time.perf_counter() - t0}), flush=True)
+    out = {"workload": args.workload, "trajectory": rows, "seconds": time.perf_counter() - t0}
+    if model is not None:
+        s = states[-1].stats(0)
+        out["learned_rank"] = {"sketches": s["sketches"], "fallbacks": s["fallbacks"]}
+    if args.save:
+        with open(os.path.join(args.save, "trajectory.json"), "w") as f:
+            json.dump(dict(out, window=window if args.save_window > 0 else None), f)
+    print(json.dumps(out), flush=True)
     grp.close()
     for st in states:
         st.close()
@@ -520,6 +551,9 @@ def main():
                          "with --workload C4, the 64-shot batch from rest in --precision, the first "
                          "shot of each grid saved at these steps")
     ap.add_argument("--save", default=None, help="directory for the trajectory's fields (.npy)")
+    ap.add_argument("--save-window", type=int, default=0, metavar="W",
+                    help="save the trajectory's fields on a W x W window (surface rows, centred on the "
+                         "source) in FP64, with the norm outside it, instead of whole")
     ap.add_argument("--metrics", default=None, metavar="JSONL",
                     help="after the timed steps, step shot 0 of the headline state --metrics-steps more steps "
                          "one at a time and write one JSON line per step: bonds, largest pre-truncation bond "

@@ -24,10 +24,6 @@ namespace mpsw {
 #define MPSW_APPLY_LDS (16 * 256 + 256)   // doubles of LDS for apply_reflector
 #define APNT 512   // threads of k_applyq, k_applyv, k_formq (8 waves, no register spills)
 
-__device__ __forceinline__ int ld_acquire(const int* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // s_waitcnt vmcnt(0), the export and LDS counters left at their maxima (GFX9
 // encoding): every vector-memory operation of this wave has completed, the
 // L2 write-back or invalidate of a fence included.
@@ -78,6 +74,7 @@ __device__ void wait_geq(const DevCtx& c, const int* p, int v) {
 __device__ void shot_barrier(const DevCtx& c, int* ctr, int nwg, int& epoch) {
   wait_vmem();
   __syncthreads();
+  if (nwg == 1) return;   // a lone workgroup: the workgroup barrier is all of it
   ++epoch;
   if (threadIdx.x == 0) {
     release_agent();
@@ -642,10 +639,10 @@ __global__ __launch_bounds__(1024) void k_qrf(const DevCtx* __restrict__ cp, OpA
   }
   wait_vmem();
   __syncthreads();
-  auto publish = [&](int j) {   // see release_agent
+  auto publish = [&](int j) {   // see release_agent; a lone workgroup has no one to tell
     wait_vmem();
     __syncthreads();
-    if (t == 0) {
+    if (t == 0 && P > 1) {
       release_agent();
       __hip_atomic_store(flags + j, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -1036,6 +1033,9 @@ __global__ __launch_bounds__(JNT) void k_jac(const DevCtx* __restrict__ cp, OpAr
   fro = 0.0;
   for (int i = 0; i < nwv; ++i) fro += fro_red[i];
   const double floor2 = 1e-28 * fro;
+  // every workgroup has read A for the norm before any of them rotates a block
+  // of it, so all of them hold the same floor
+  shot_barrier(c, sy + MPSW_SYNC_BARRIER, P, epoch);
   // the eigen stage of an SVD of a c x c factor, 9 c^3 by the standard count
   if (ok && w == 0 && t == 0) count_flops(c, shot, MPSW_KC_JACOBI, 9.0 * (double)cc * cc * cc);
   const int g = t >> 4, gl = t & 15, ng = JNT / 16;
@@ -1167,9 +1167,13 @@ __global__ __launch_bounds__(JNT) void k_jac(const DevCtx* __restrict__ cp, OpAr
       }
       shot_barrier(c, sy + MPSW_SYNC_BARRIER, P, epoch);
     }
-    // every workgroup reads the same final values after the barrier
-    const int rot = ld_acquire(sy + MPSW_SYNC_ROT + (sweep & 63));
-    const float mx = __uint_as_float((unsigned int)ld_acquire(sy + MPSW_SYNC_MAXREL + (sweep & 63)));
+    // every workgroup reads the same final values after the barrier: each
+    // workgroup's updates precede its arrival (release) and this one's barrier
+    // acquired them, so relaxed atomic loads see them (an acquire load here
+    // would invalidate the XCD's L2 once per wave)
+    const int rot = __hip_atomic_load(sy + MPSW_SYNC_ROT + (sweep & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const float mx = __uint_as_float((unsigned int)__hip_atomic_load(sy + MPSW_SYNC_MAXREL + (sweep & 63),
+                                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     if (rot == 0 || mx < 1e-12f || !ok || cc <= 1) {
       if (w == 0 && t == 0) atomicMax((int*)dm + DL::jac_sweeps, sweep + 1);
       break;

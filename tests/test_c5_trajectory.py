@@ -1,0 +1,145 @@
+"""The n = 11 workload's mixed form against the FP64 oracle over its first 500 steps.
+
+C5 (n = 11, 2048 x 2048, chi = 256, eps = 1e-6, layered model, Ricker source
+at depth index 1) from rest, the c^2 operator being the oracle's TT-SVD of
+the model in both runs.  The GPU side steps four members as one group: FP64,
+FP32 and BF16 contractions with exact SVDs, and the mixed form (BF16
+contractions with the learned rank: range finder at the rank the network
+proposes, exact SVD on rejection).  It runs on a GPU machine:
+
+    python tests/test_c5_trajectory.py c2 C2CORES.npz
+    python bench.py --workload C5 --rank learned --trajectory 100,250,500 --velocity-cores C2CORES.npz --save GPU_DIR --save-window 512
+
+(the GPU fields are saved in FP64 on the 512 x 512 window of surface rows
+around the source that holds the wavefield, with the norm of each field
+outside it: the distance outside the window is bounded by the sum of the two
+fields' norms there, and the reported distance is that upper bound).
+
+The oracle side runs on the host (about an hour a run on 2 threads):
+
+    python tests/test_c5_trajectory.py oracle ORACLE_DIR
+    python tests/test_c5_trajectory.py floor ORACLE_DIR 1e-15 d15
+    python tests/test_c5_trajectory.py floor ORACLE_DIR 5.96e-8 u32
+
+and the comparison is this test, with MPSW_C5_GPU and MPSW_C5_ORACLE set to the
+two directories (it is skipped without them).  The bounds are those of the
+n = 10 trajectory: FP64 within 10x the floor at perturbation 1e-15, BF16 and
+the mixed form within 1e-3 or 10x that floor, FP32 within 1e-6 or 10x the
+larger floor (1e-15 or FP32's unit roundoff).  The workload's stated length
+is 3000 steps; the first 500 are what the oracle covers on the host in the
+time of a measurement (a step of the dense-detour oracle at n = 11 takes
+several seconds).  The summary is written by
+
+    python tests/test_c5_trajectory.py summary GPU_DIR ORACLE_DIR > profiles/trajectory_C5.json
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+REPO = os.path.dirname(ROOT)
+for p in (REPO, ROOT):
+    if p not in sys.path:
+        sys.path.insert(0, p)
+
+MARKS = (100, 250, 500)
+MEMBERS = ("fp64", "fp32", "bf16", "bf16l")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _oracle_run(out, delta=0.0, tag="oracle"):
+    from oracle import mps as M
+    from oracle import stepper as S
+    import sensitivity
+    import synth
+    cfg = synth.get_config("C5")
+    n = cfg["n"]
+    N = 1 << n
+    c2r = M.to_dense(S.c2_mps(cfg["c2"], n, cfg["eps_c"])).reshape(N, N)
+    ds = sensitivity.PerturbedStepper(delta, 0, n, cfg["lam"], cfg["eps"], cfg["chi"], c2r,
+                                      src=(cfg["ix"], cfg["iz"]), wavelet=cfg["wavelet_samples"])
+    ds.keep_log = False
+    for k in range(1, max(MARKS) + 1):
+        ds.step()
+        if k in MARKS:
+            np.save(os.path.join(out, f"{tag}_u{k}.npy"), ds.dense())
+        if k % 25 == 0:
+            print(tag, "step", k, ds.ranks[-1][2], flush=True)
+    if delta == 0.0:
+        json.dump({"first_flag": ds.first_flag(), "bonds": ds.ranks[-1][2]},
+                  open(os.path.join(out, f"{tag}_log.json"), "w"))
+
+
+def summary(gpu, orc):
+    rows = []
+    log = json.load(open(os.path.join(orc, "oracle_log.json")))
+    meta = {}
+    f = os.path.join(gpu, "trajectory.json")
+    if os.path.exists(f):
+        meta = json.load(open(f))
+    win = meta.get("window")
+    for k in MARKS:
+        o = np.load(os.path.join(orc, f"oracle_u{k}.npy"))
+        r = {"step": k}
+        for p in MEMBERS:
+            g = os.path.join(gpu, f"gpu_{p}_u{k}.npy")
+            if not os.path.exists(g):
+                continue
+            g = np.load(g).astype(np.float64)
+            if win:
+                x0, z0, W = win["x0"], win["z0"], win["W"]
+                ow = o[x0:x0 + W, z0:z0 + W]
+                o_out = np.sqrt(max(float(np.sum(o * o) - np.sum(ow * ow)), 0.0))
+                d2 = float(np.sum((g - ow) ** 2)) + (win["outside_norm"][f"{p}_u{k}"] + o_out) ** 2
+                r[p] = float(np.sqrt(d2) / np.linalg.norm(o))
+                r["oracle_outside_window"] = float(o_out / np.linalg.norm(o))
+            else:
+                r[p] = rel(g, o)
+        for tag in ("d15", "u32"):
+            f = os.path.join(orc, f"{tag}_u{k}.npy")
+            if os.path.exists(f):
+                r[f"floor_{tag}"] = rel(np.load(f), o)
+        rows.append(r)
+    out = {"workload": "C5: n=11, chi=256, eps=1e-6, first 500 steps from rest", "first_flagged_cut": log["first_flag"],
+           "checkpoints": rows}
+    if "learned_rank" in meta:
+        out["learned_rank"] = meta["learned_rank"]
+    return out
+
+
+@pytest.mark.skipif(not (os.environ.get("MPSW_C5_GPU") and os.environ.get("MPSW_C5_ORACLE")),
+                    reason="needs the saved GPU and oracle trajectories (see the module docstring)")
+def test_c5_trajectory_against_oracle():
+    s = summary(os.environ["MPSW_C5_GPU"], os.environ["MPSW_C5_ORACLE"])
+    print(json.dumps(s, indent=1))
+    for r in s["checkpoints"]:
+        floor = r["floor_d15"]
+        assert r["fp64"] <= max(1e-10, 10.0 * floor), r
+        assert r["bf16"] <= max(1e-3, 10.0 * floor), r
+        assert r["bf16l"] <= max(1e-3, 10.0 * floor), r
+        assert r["fp32"] <= max(1e-6, 10.0 * max(floor, r.get("floor_u32", 0.0))), r
+
+
+if __name__ == "__main__":
+    what, out = sys.argv[1], sys.argv[2]
+    if what == "c2":
+        from oracle import mps as M
+        from oracle import stepper as S
+        import synth
+        cfg = synth.get_config("C5")
+        ref = S.c2_mps(cfg["c2"], cfg["n"], cfg["eps_c"])
+        np.savez(out, bonds=np.array(M.bonds_of(ref)), cores=np.concatenate([c.ravel() for c in ref]))
+    elif what == "oracle":
+        os.makedirs(out, exist_ok=True)
+        _oracle_run(out)
+    elif what == "floor":
+        os.makedirs(out, exist_ok=True)
+        _oracle_run(out, float(sys.argv[3]), sys.argv[4])
+    elif what == "summary":
+        print(json.dumps(summary(out, sys.argv[3]), indent=1))
