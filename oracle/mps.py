@@ -124,6 +124,17 @@ def cut_flags(s, r, eps):
     return out
 
 
+def svd(M):
+    """Thin SVD (U, s, Vt) of M.  LAPACK's divide-and-conquer driver (numpy's)
+    fails to converge on rare matrices; the QR-iteration driver then computes
+    the same decomposition."""
+    try:
+        return np.linalg.svd(M, full_matrices=False)
+    except np.linalg.LinAlgError:
+        import scipy.linalg
+        return scipy.linalg.svd(M, full_matrices=False, lapack_driver="gesvd")
+
+
 def tt_svd(t, K, eps, chi_max, log=None):
     """Right-to-left truncated TT-SVD of a dense tensor with 2^K entries.
 
@@ -138,7 +149,7 @@ def tt_svd(t, K, eps, chi_max, log=None):
     rho = 1
     for k in range(K - 1, 0, -1):
         M = X.reshape(-1, 2 * rho)
-        U, s, Vt = np.linalg.svd(M, full_matrices=False)
+        U, s, Vt = svd(M)
         r = choose_rank(s, eps, chi_max)
         if log is not None:
             log.append((k, s.copy(), r))
@@ -166,7 +177,7 @@ def round_mps(cores, eps, chi_max, log=None):
         G[k + 1] = np.tensordot(R, G[k + 1], axes=(1, 0))
     for k in range(K - 1, 0, -1):
         r0, d, r1 = G[k].shape
-        U, s, Vt = np.linalg.svd(G[k].reshape(r0, d * r1), full_matrices=False)
+        U, s, Vt = svd(G[k].reshape(r0, d * r1))
         r = choose_rank(s, eps, chi_max)
         if log is not None:
             log.append((k, s.copy(), r))

@@ -27,7 +27,7 @@ first uniform is shifted to (0, 1].
 """
 import numpy as np
 
-from .mps import choose_rank
+from .mps import choose_rank, svd
 
 MASK = (1 << 64) - 1
 
@@ -62,7 +62,7 @@ def range_finder(M, Om):
     Qz = orth(M @ Q)
     Q = orth(M.T @ Qz)
     B = M @ Q
-    _, S, Wt = np.linalg.svd(B, full_matrices=False)
+    _, S, Wt = svd(B)
     return Q, B, S, Wt.T
 
 
@@ -161,7 +161,7 @@ class LearnedRounding:
             b = min(64, max(1, 2 * self.back.get((rnd, k), 0)))
             self.back[(rnd, k)] = b
             self.skip[(rnd, k)] = step + 1 + b
-        U, s, Vt = np.linalg.svd(M, full_matrices=False)
+        U, s, Vt = svd(M)
         r = choose_rank(s, eps, chi)
         self.sig[(rnd, k)] = s[:32].copy()
         self.rank[(rnd, k)] = r

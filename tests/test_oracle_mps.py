@@ -151,3 +151,22 @@ def test_choose_rank_rule():
     assert M.choose_rank(s, 2.0, 10) == 1            # at least one
     assert M.choose_rank(np.zeros(3), 1e-7, 10) == 1
     assert M.choose_rank(s, 0.0, 10) == 5            # eps = 0 keeps everything
+
+
+def test_svd_falls_back_when_divide_and_conquer_fails(monkeypatch):
+    """When LAPACK's divide-and-conquer SVD does not converge, the oracle's
+    helper takes the QR-iteration driver: the same singular values (to
+    rounding), orthonormal factors and the same matrix back."""
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal((40, 24)) @ np.diag(np.logspace(0, -9, 24)) @ rng.standard_normal((24, 24))
+    ref = np.linalg.svd(A, compute_uv=False)
+
+    def fail(*a, **k):
+        raise np.linalg.LinAlgError("SVD did not converge")
+
+    monkeypatch.setattr(M.np.linalg, "svd", fail)
+    U, s, Vt = M.svd(A)
+    monkeypatch.undo()
+    assert np.allclose(s, ref, rtol=0, atol=1e-14 * ref[0])
+    assert np.allclose(U.T @ U, np.eye(24), atol=1e-13) and np.allclose(Vt @ Vt.T, np.eye(24), atol=1e-13)
+    assert np.linalg.norm(U * s @ Vt - A) < 1e-13 * np.linalg.norm(A)
