@@ -233,14 +233,16 @@ int mpsw_get_stats(mpsw_state st, int shot, mpsw_stats* out);
 /* Autotuner of the launch shapes for this state's bucket (grid, chi cap,
  * shot count, precision): times `steps` steps from the current state for
  * each candidate Jacobi block width (rule, 8, 16, 32 columns) and then each
- * cap on the workgroups per shot of a QR factorisation (32, 16, 8, 4, 3, 2, 1), keeps
+ * cap on the workgroups per shot of a QR factorisation (32, 16, 8, 4, 3, 2, 1;
+ * the same cap bounds the workgroups of a Jacobi sweep, one per block pair
+ * of a round at most, each taking several pairs in turn when fewer), keeps
  * the fastest pair, and restores the state exactly as it was (fields, bonds,
  * step counters).  The chosen values are returned if the pointers are not
  * NULL.  Synchronises.  Errors: EINVAL, ESTATE, ENOMEM, EHIP. */
 int mpsw_autotune(mpsw_state st, int steps, int* qr_nwg, int* jac_block);
 
 /* Set the launch shapes mpsw_autotune chooses, without timing: the cap on the
- * workgroups per shot of a QR factorisation (1..32) and the Jacobi block
+ * workgroups per shot of a QR factorisation and a Jacobi sweep (1..32) and the Jacobi block
  * width (0 = rule from the column count, or 8, 16, 32).  For reusing a shape
  * tuned earlier on another state of the same bucket; the shapes change the
  * order of the factorisations' sums, so results agree with another shape to

@@ -1005,8 +1005,8 @@ __global__ __launch_bounds__(JNT) void k_jac(const DevCtx* __restrict__ cp, OpAr
   const int pact = nbe / 2;
   int* sy = shot_sync(c, shot);
   int epoch = 0;
-  const bool ok = ((int64_t)Lc * cc <= c.L.cap_sA) && pact <= P && b <= JNT / 16;
-  if (!ok && w == 0 && t == 0) raise_err(c, (pact > P || b > JNT / 16) ? MPSW_DEV_ERR_GRID : MPSW_DEV_ERR_CAP);
+  const bool ok = ((int64_t)Lc * cc <= c.L.cap_sA) && b <= JNT / 16;
+  if (!ok && w == 0 && t == 0) raise_err(c, (b > JNT / 16) ? MPSW_DEV_ERR_GRID : MPSW_DEV_ERR_CAP);
   double* A = E + c.L.off_sA;
   extern __shared__ double blk[];   // 2b columns, stride ldl
   // EPL > 0: columns padded with zeros to 16 EPL rows (rotations keep the
@@ -1051,10 +1051,13 @@ __global__ __launch_bounds__(JNT) void k_jac(const DevCtx* __restrict__ cp, OpAr
   };
   for (int sweep = 0; sweep < MPSW_MAX_SWEEPS; ++sweep) {
     for (int rnd = 0; rnd < nbe - 1; ++rnd) {
-      if (ok && w < pact && cc > 1) {
+      // the round's pact block pairs are disjoint: workgroup w takes pairs
+      // w, w + P, ... one after the other (fewer workgroups than pairs trade
+      // parallelism within a shot for fewer cross-workgroup barriers)
+      for (int pw = w; ok && pw < pact && cc > 1; pw += P) {
         int bp, bq;
-        if (w == 0) { bp = rnd; bq = nbe - 1; }
-        else { bp = (rnd + w) % (nbe - 1); bq = (rnd - w + (nbe - 1)) % (nbe - 1); }
+        if (pw == 0) { bp = rnd; bq = nbe - 1; }
+        else { bp = (rnd + pw) % (nbe - 1); bq = (rnd - pw + (nbe - 1)) % (nbe - 1); }
         if (bp >= nb) { const int tmp = bp; bp = bq; bq = tmp; }
         const int np_ = (bp < nb) ? min(b, cc - bp * b) : 0;
         const int nq_ = (bq < nb) ? min(b, cc - bq * b) : 0;
@@ -1164,6 +1167,7 @@ __global__ __launch_bounds__(JNT) void k_jac(const DevCtx* __restrict__ cp, OpAr
           if (nrot > 0) atomicAdd(sy + MPSW_SYNC_ROT + (sweep & 63), nrot);
           atomicMax((unsigned int*)sy + MPSW_SYNC_MAXREL + (sweep & 63), maxrel);
         }
+        __syncthreads();   // the next pair's columns overwrite the LDS these were stored from
       }
       shot_barrier(c, sy + MPSW_SYNC_BARRIER, P, epoch);
     }

@@ -710,7 +710,10 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
                  (size_t)ccap * bw2 * 8, strm); });
       const int b = jac_block(ccap, st->tune_jac_b);
       const int64_t nb = cdiv(ccap, b);
-      prof(st, MPSW_KC_JACOBI, strm, [&] { launch_jac(d, v, b, (int)std::max<int64_t>(1, (nb + (nb & 1)) / 2), nshots, (size_t)2 * b * (ccap + 1) * 8, ccap, strm); });
+      // workgroups per shot: one per block pair of a round, at most the QR's
+      // tuned count (a large batch fills the chip with one per shot)
+      const int jnwg = (int)std::max<int64_t>(1, std::min<int64_t>(st->tune_qr_nwg, (nb + (nb & 1)) / 2));
+      prof(st, MPSW_KC_JACOBI, strm, [&] { launch_jac(d, v, b, jnwg, nshots, (size_t)2 * b * (ccap + 1) * 8, ccap, strm); });
       launch_jacfin(d, v, nshots, strm);
       prof(st, MPSW_KC_APPLYV, strm, [&] { launch_applyv(d, v, bw1, std::max(1, cdiv(s.rho[k], 16)), nshots, strm); });
       OpArgs g{};
