@@ -235,7 +235,8 @@ int mpsw_get_stats(mpsw_state st, int shot, mpsw_stats* out);
  * each candidate Jacobi block width (rule, 8, 16, 32 columns) and then each
  * cap on the workgroups per shot of a QR factorisation (32, 16, 8, 4, 3, 2, 1;
  * the same cap bounds the workgroups of a Jacobi sweep, one per block pair
- * of a round at most, each taking several pairs in turn when fewer), keeps
+ * of a round at most, each taking several pairs in turn when fewer), then
+ * each block width again at the chosen cap, keeps
  * the fastest pair, and restores the state exactly as it was (fields, bonds,
  * step counters).  The chosen values are returned if the pointers are not
  * NULL.  Synchronises.  Errors: EINVAL, ESTATE, ENOMEM, EHIP. */

@@ -1685,10 +1685,15 @@ int mpsw_autotune(mpsw_state st, int steps, int* qr_nwg, int* jac_block_out) {
       best_b = b;
     }
   };
-  // one factor at a time: the Jacobi block width, then the QR workgroups
+  // one factor at a time: the Jacobi block width, then the workgroups per
+  // shot, then the block width again at that count (the count also bounds
+  // the Jacobi workgroups, which changes what the width trades)
   for (int b : {0, 8, 16, 32}) trial(32, b);
   const int bb = best_b;
   for (int q : {16, 8, 4, 3, 2, 1}) trial(q, bb);
+  const int bq = best_q;
+  for (int b : {0, 8, 16, 32})
+    if (bq != 32 && b != bb) trial(bq, b);   // (bq, bb) and every (32, b) were timed above
   st->tune_qr_nwg = best_q;
   st->tune_jac_b = best_b;
   if (ok) ok = restore();
