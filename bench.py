@@ -396,16 +396,23 @@ def precision_trajectory(mpsw, synth, torch, args):
             row[f"rel_l2_{name}_vs_fp64"] = float(np.linalg.norm(v - u[0])) / nb if nb > 0 else 0.0
         rows.append(row)
         if args.save and args.save_window > 0:
-            # every member in FP64 on the W x W window (surface rows, centred on
-            # the source) that holds the wavefield, and the norm of what lies
-            # outside it, so the full-field distance can be bounded
+            # every member in FP64 on the W x W window centred on the source
+            # (the grid is periodic: the field is rolled so that the source sits
+            # at (W/2, W/2)), and the norm of what lies outside it, so the
+            # full-field distance can be bounded
             W = min(args.save_window, 1 << n)
-            x0 = min(max(cfg["ix"] - W // 2, 0), (1 << n) - W)
-            window.update({"x0": x0, "z0": 0, "W": W})
+            shift = [W // 2 - cfg["ix"], W // 2 - cfg["iz"]]
+            window.update({"shift": shift, "W": W})
             for (name, _), v in zip(precs, u):
-                np.save(os.path.join(args.save, f"gpu_{name}_u{mark}.npy"), v[x0:x0 + W, :W])
-                out_sq = float(np.sum(v * v)) - float(np.sum(v[x0:x0 + W, :W] ** 2))
-                window["outside_norm"][f"{name}_u{mark}"] = float(np.sqrt(max(out_sq, 0.0)))
+                rolled = np.roll(v, shift, axis=(0, 1))
+                np.save(os.path.join(args.save, f"gpu_{name}_u{mark}.npy"), rolled[:W, :W])
+                rolled[:W, :W] = 0.0   # the outside, summed directly (a difference of squares would cancel)
+                out = float(np.linalg.norm(rolled))
+                window["outside_norm"][f"{name}_u{mark}"] = out
+                if name == "fp64" and out > 1e-14 * float(np.linalg.norm(v)):
+                    # what the FP64 member holds outside the window (truncation
+                    # residue far below the wave) in FP32, enough for its distance
+                    np.save(os.path.join(args.save, f"gpu_fp64_full_u{mark}.npy"), v.astype(np.float32))
         elif args.save:   # FP64 fields in FP64; the others in FP32, enough for their distances
             np.save(os.path.join(args.save, f"gpu_fp64_u{mark}.npy"), u[0])
             for (name, _), v in zip(precs[1:], u[1:]):
@@ -552,8 +559,8 @@ def main():
                          "shot of each grid saved at these steps")
     ap.add_argument("--save", default=None, help="directory for the trajectory's fields (.npy)")
     ap.add_argument("--save-window", type=int, default=0, metavar="W",
-                    help="save the trajectory's fields on a W x W window (surface rows, centred on the "
-                         "source) in FP64, with the norm outside it, instead of whole")
+                    help="save the trajectory's fields on a W x W window centred on the source (periodic "
+                         "grid) in FP64, with the norm outside it, instead of whole")
     ap.add_argument("--metrics", default=None, metavar="JSONL",
                     help="after the timed steps, step shot 0 of the headline state --metrics-steps more steps "
                          "one at a time and write one JSON line per step: bonds, largest pre-truncation bond "
