@@ -115,7 +115,7 @@ def train_rank_model(mpsw, synth, steps=80):
 
 
 def make_state(mpsw, synth, workload, batch, precision, rank="exact", model=None, ordering="sequential",
-               velocity=None):
+               velocity=None, from_rest=False):
     """State of `batch` shots of a workload from its developed wavefield.  The
     c^2 operator is the device's TT-SVD of the dense model, or the given
     (bonds, cores) of its diagonal in the state's site order."""
@@ -150,12 +150,13 @@ def make_state(mpsw, synth, workload, batch, precision, rank="exact", model=None
             st.set_source_3d(b, ix, cfg["iy"], cfg["iz"], cfg["wavelet_samples"])
             fields.append((up, u, (ix, cfg["iy"], cfg["iz"])))
         return st, cfg, fields
-    up0, u0 = synth.wavefront_fields(n, seed=0)
+    up0, u0 = (np.zeros((N, N)), np.zeros((N, N))) if from_rest else synth.wavefront_fields(n, seed=0)
     for b in range(batch):
         # shot b starts from one of the 8 symmetries of the square of the same wavefield
         sym = lambda f: np.rot90(f[::-1] if (b // 4) % 2 else f, b % 4).copy()  # noqa: E731
         up, u = sym(up0), sym(u0)
-        st.set_fields(b, up, u)
+        if not from_rest:
+            st.set_fields(b, up, u)
         # distinct source positions along the surface row
         ix = (cfg["ix"] + b * (N // max(batch, 1))) % N
         st.set_source(b, ix, cfg["iz"], cfg["wavelet_samples"])
@@ -479,7 +480,16 @@ def run_form(mpsw, synth, torch, args, batch, precision, rank, model=None, veloc
     HIP events on the state's stream during the timed steps.  Returns (state,
     cfg, fields, result, kernel class, its profile)."""
     t0 = time.perf_counter()
-    st, cfg, fields = make_state(mpsw, synth, args.workload, batch, precision, rank, model, args.ordering, velocity)
+    st, cfg, fields = make_state(mpsw, synth, args.workload, batch, precision, rank, model, args.ordering, velocity,
+                                 from_rest=args.from_rest)
+    if args.from_rest:   # the warm-up grows the bonds first, so the tuner sees the timed steps' sizes
+        done = 0
+        while done < args.warmup:
+            k = min(25, args.warmup - done)
+            st.step(k)
+            torch.cuda.synchronize()
+            done += k
+            log(f"warm-up from rest: step {done}, bonds of shot 0 {st.bonds(0, 0)}")
     tuned = tune
     if tune is None and args.shapes:
         tune = tuned = tuple(int(x) for x in args.shapes.split(","))
@@ -487,7 +497,8 @@ def run_form(mpsw, synth, torch, args, batch, precision, rank, model=None, veloc
         st.set_launch_shapes(*tune)
     elif not args.no_tune:
         tuned = st.autotune(2)
-    st.step(max(args.warmup, 0))
+    if not args.from_rest:
+        st.step(max(args.warmup, 0))
     torch.cuda.synchronize()
     prof = None
     if kclass is not None and kclass < 0:   # the class with the most event time over one probe step (untimed)
@@ -533,6 +544,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"],
                     help="contraction arithmetic (factorisations and truncation stay FP64)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--from-rest", action="store_true",
+                    help="start the shots from rest (sources only) instead of the developed wavefield; the "
+                         "warm-up steps run before the autotuner")
     ap.add_argument("--shapes", default=None, metavar="Q,B",
                     help="launch shapes (QR workgroups per shot, Jacobi block; 0 = the width rule) instead of "
                          "the autotuner, e.g. the pair it picked in an earlier run")
@@ -575,7 +589,8 @@ def main():
     ap.add_argument("--forms", default="fp32,learned",
                     help="comma-separated extra forms timed beside the headline one on the same workload and "
                          "batch: fp32, bf16 (contraction precision), learned (rank network + range finder), "
-                         "previous (range finder at the previous step's ranks), chosen (all of fp32 + learned); "
+                         "previous (range finder at the previous step's ranks), chosen (all of fp32 + learned), "
+                         "bf16l (bf16 + learned); "
                          "empty for none")
     args = ap.parse_args()
 
@@ -609,7 +624,7 @@ def main():
 
     velocity = load_velocity_cores(args.velocity_cores) if args.velocity_cores else None
     model = None
-    if args.rank == "learned" or any(f in ("learned", "chosen") for f in args.forms.split(",")):
+    if args.rank == "learned" or any(f in ("learned", "chosen", "bf16l") for f in args.forms.split(",")):
         t0 = time.perf_counter()
         model, nrows = train_rank_model(mpsw, synth)
         log(f"rank network trained on {nrows} logged bonds in {time.perf_counter() - t0:.1f} s")
@@ -666,8 +681,8 @@ def main():
     st.close()
     forms = {}
     for f in [x for x in args.forms.split(",") if x]:
-        prec = {"fp32": "fp32", "bf16": "bf16", "chosen": "fp32"}.get(f, args.precision)
-        rank = "learned" if f in ("learned", "chosen") else "previous" if f == "previous" else args.rank
+        prec = {"fp32": "fp32", "bf16": "bf16", "chosen": "fp32", "bf16l": "bf16"}.get(f, args.precision)
+        rank = "learned" if f in ("learned", "chosen", "bf16l") else "previous" if f == "previous" else args.rank
         fs, _, _, res, _, _ = run_form(mpsw, synth, torch, args, args.batch, prec, rank,
                                        model if rank == "learned" else None, velocity)
         fs.close()
