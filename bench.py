@@ -526,7 +526,7 @@ def run_form(mpsw, synth, torch, args, batch, precision, rank, model=None, veloc
            "shots": batch, "precision": precision,
            "rank": {"exact": "exact SVD", "learned": "learned rank + range finder, exact fallback",
                     "previous": "previous step's rank + range finder, exact fallback"}[rank],
-           "tuned": None if tuned is None else {"qr_workgroups_per_shot": tuned[0], "jacobi_block": tuned[1] or "rule"},
+           "tuned": None if tuned is None else {"workgroups_per_shot": tuned[0], "jacobi_block": tuned[1] or "rule"},
            "sketches": int(sum(x["sketches"] for x in stats)), "fallbacks": int(sum(x["fallbacks"] for x in stats)),
            "setup_s": t1 - t0}
     log(f"form {precision}/{rank}/{batch} shots: {res['value']:.1f} shot-steps/s "
