@@ -1,10 +1,11 @@
 """Run-to-run determinism of the batched step in the shape the benchmark times:
 the n = 10 workload (chi = 128, eps = 1e-6) with 256 shots, in the launch shapes
-the autotuner picks there (1 QR workgroup per shot, Jacobi blocks of 32
+the autotuner picks there (1 workgroup per shot, Jacobi blocks of 32
 columns) and in the 2- and 4-workgroup shapes (where the workgroups of one
-shot share its QR panels through flags), stepped twice from the same fields in
-two fresh states.  Every kernel sums in a fixed order and the workgroups of
-one shot only read panels their owners have published, so the two runs must
+shot share its QR panels through flags and its Jacobi block pairs through
+round barriers), stepped twice from the same fields in two fresh states.
+Every kernel sums in a fixed order and the workgroups of one shot only read
+what the others have published, so the two runs must
 agree bit for bit in every shot's bonds and in sampled fields (a race between
 workgroups shows up here as shots whose truncation ranks differ between the
 runs)."""
