@@ -69,3 +69,31 @@ def test_launch_shapes_are_checked(mpsw):
         assert ei.value.name == "EINVAL", bad
     st.set_launch_shapes(4, 16)
     st.close()
+
+
+def test_launch_shapes_agree_to_rounding(mpsw):
+    """The same steps in 1, 2 and 4 workgroups per shot: with fewer Jacobi
+    workgroups than block pairs each takes several pairs of a round in turn,
+    and the QR panels move between workgroups through flags.  The shapes only
+    change the order of some sums, so every shot keeps the same bonds and the
+    sampled fields agree to rounding."""
+    shots, steps, sample = 32, 4, (0, 13, 31)
+    ref = None
+    for shapes in ((4, 32), (2, 32), (1, 32)):
+        import torch
+        import bench
+        st, cfg, _ = bench.make_state(mpsw, synth, "C3", shots, "fp64")
+        st.set_launch_shapes(*shapes)
+        st.step(steps)
+        torch.cuda.synchronize()
+        bonds = [st.bonds(s, 0) for s in range(shots)]
+        fields = {s: st.to_dense(s, 0) for s in sample}
+        st.close()
+        _say("32 shots, launch shapes", shapes, "bonds of shot 0", bonds[0])
+        if ref is None:
+            ref = (bonds, fields)
+            continue
+        assert bonds == ref[0], shapes
+        for s in sample:
+            err = np.linalg.norm(fields[s] - ref[1][s]) / np.linalg.norm(ref[1][s])
+            assert err < 1e-12, (shapes, s, err)
