@@ -755,6 +755,26 @@ __global__ __launch_bounds__(APNT) void k_applyq(const DevCtx* __restrict__ cp, 
   extern __shared__ double wsp[];
   if (w == 0 && t == 0)   // n reflectors of length <= m applied to r columns
     count_flops(c, shot, MPSW_KC_APPLYQ, 4.0 * m * (double)n * r - 2.0 * (double)n * n * r);
+  if (a.aux > 0 && m <= a.aux) {
+    // the m x cw tile of M stays in LDS (row stride CW) across all panels:
+    // read from U Sigma once, written to M once
+    double* Ct = wsp + MPSW_APPLY_LDS;
+    for (int e = t; e < m * CW; e += APNT) {
+      const int row = e / CW, q = e % CW;
+      Ct[e] = (row < n && q < cw) ? US[(int64_t)row * r + col0 + q] : 0.0;
+    }
+    __syncthreads();
+    for (int j = nbk - 1; j >= 0; --j) {
+      const int r0 = j * BW, c0 = j * BW, bw = min(BW, n - c0);
+      apply_reflector<BW, APNT / 64>(S + r0 + (int64_t)m * c0, m, Ct + (int64_t)r0 * CW, CW, 1, m - r0, bw, cw,
+                                     T + (int64_t)j * BW * BW, false, wsp);
+    }
+    for (int e = t; e < m * cw; e += APNT) {
+      const int row = e / cw, q = e % cw;
+      M[(int64_t)row * r + col0 + q] = Ct[row * CW + q];
+    }
+    return;
+  }
   bulk_copy<8>(m * cw, t, APNT,
                [&](int e) { return (e / cw < n) ? US[(e / cw) * r + col0 + (int)(e % cw)] : 0.0; },
                [&](int e, double v) { M[(e / cw) * r + col0 + (int)(e % cw)] = v; });
@@ -1317,7 +1337,8 @@ void launch_qrf(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, s
 }
 
 void launch_applyq(const DevCtx* d, const OpArgs& a, int bw, int nwg, int nshots, hipStream_t s) {
-  const size_t lds = (size_t)MPSW_APPLY_LDS * sizeof(double);
+  // a.aux > 0: rows of the LDS-resident column tile (16 columns)
+  const size_t lds = (size_t)(MPSW_APPLY_LDS + (a.aux > 0 ? 16 * a.aux : 0)) * sizeof(double);
   if (bw == 16)
     hipLaunchKernelGGL(k_applyq<16>, dim3(nwg, 1, nshots), dim3(APNT), lds, s, d, a);
   else if (bw == 8)
@@ -1371,6 +1392,9 @@ void launch_jacfin(const DevCtx* d, const OpArgs& a, int nshots, hipStream_t s) 
 
 void set_lds_limits(size_t bytes) {
   (void)hipFuncSetAttribute((const void*)k_qrf<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  (void)hipFuncSetAttribute((const void*)k_applyq<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  (void)hipFuncSetAttribute((const void*)k_applyq<8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  (void)hipFuncSetAttribute((const void*)k_applyq<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   (void)hipFuncSetAttribute((const void*)k_qrf<8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   (void)hipFuncSetAttribute((const void*)k_qrf<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   (void)hipFuncSetAttribute((const void*)k_jac<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

@@ -789,6 +789,9 @@ void run_rounding(mpsw_state st, Engine& e, int kind, const SweepCaps& s, int ou
     ap.shot = -1;
     ap.site = k;
     const int bwq = qr_panel(2 * s.rt[k - 1]);
+    // the 16-column tile of M in LDS when it fits beside the reflector workspace
+    const int64_t mq = 2 * s.rt[k - 1];
+    if ((size_t)(16 * 256 + 256 + 16 * mq) * sizeof(double) <= lds_limit()) ap.aux = (int)mq;   // 16 * 256 + 256: the reflector workspace
     prof(st, MPSW_KC_APPLYQ, strm, [&] { launch_applyq(d, ap, bwq, std::max(1, cdiv(s.rho[k], 16)), nshots, strm); });
   }
   OpArgs f{};
