@@ -405,14 +405,12 @@ def precision_trajectory(mpsw, synth, torch, args):
             shift = [W // 2 - cfg["ix"], W // 2 - cfg["iz"]]
             window.update({"shift": shift, "W": W})
             for (name, _), v in zip(precs, u):
-                rolled = np.roll(v, shift, axis=(0, 1))
-                np.save(os.path.join(args.save, f"gpu_{name}_u{mark}.npy"), rolled[:W, :W])
-                rolled[:W, :W] = 0.0   # the outside, summed directly (a difference of squares would cancel)
-                out = float(np.linalg.norm(rolled))
+                win, out = window_split(v, shift, W)
+                np.save(os.path.join(args.save, f"gpu_{name}_u{mark}.npy"), win)
                 window["outside_norm"][f"{name}_u{mark}"] = out
                 if name == "fp64" and out > 1e-14 * float(np.linalg.norm(v)):
-                    # what the FP64 member holds outside the window (truncation
-                    # residue far below the wave) in FP32, enough for its distance
+                    # the whole FP64 member in FP32 as well: with the window in
+                    # FP64 (window_join) its distance is exact to FP32 outside
                     np.save(os.path.join(args.save, f"gpu_fp64_full_u{mark}.npy"), v.astype(np.float32))
         elif args.save:   # FP64 fields in FP64; the others in FP32, enough for their distances
             np.save(os.path.join(args.save, f"gpu_fp64_u{mark}.npy"), u[0])
@@ -442,6 +440,24 @@ def load_velocity_cores(path):
         cores.append(flat[o:o + sz].reshape(bonds[k], 2, bonds[k + 1]))
         o += sz
     return bonds, cores
+
+
+def window_split(v, shift, W):
+    """(W x W window of the periodic field v rolled by shift, norm of the rest).
+    The rest's norm is summed directly: a difference of squared norms would
+    cancel to noise."""
+    rolled = np.roll(v, shift, axis=(0, 1))
+    win = rolled[:W, :W].copy()
+    rolled[:W, :W] = 0.0
+    return win, float(np.linalg.norm(rolled))
+
+
+def window_join(full, win, shift):
+    """The field `full` (any precision) with its window replaced by `win`."""
+    W = win.shape[0]
+    rolled = np.roll(np.asarray(full, dtype=np.float64), shift, axis=(0, 1))
+    rolled[:W, :W] = win
+    return np.roll(rolled, (-shift[0], -shift[1]), axis=(0, 1))
 
 
 def load_velocity_cores_mixed(path):

@@ -48,12 +48,22 @@ for p in (REPO, ROOT):
     if p not in sys.path:
         sys.path.insert(0, p)
 
+import bench  # noqa: E402  (the window helpers of the saved GPU fields)
+
 MARKS = (100, 250, 500)
 MEMBERS = ("fp64", "fp32", "bf16", "bf16l")
 
 
 def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def window_bound(gw, g_out, o, shift):
+    """Upper bound of rel-L2(g, o) from g's window gw and the norm g_out of the
+    rest of g: the window exactly, the rest by the triangle inequality."""
+    ow, o_out = bench.window_split(o, shift, gw.shape[0])
+    d2 = float(np.sum((gw - ow) ** 2)) + (g_out + o_out) ** 2
+    return float(np.sqrt(d2) / np.linalg.norm(o))
 
 
 def _oracle_run(out, delta=0.0, tag="oracle"):
@@ -98,19 +108,10 @@ def summary(gpu, orc):
             full = os.path.join(gpu, f"gpu_{p}_full_u{k}.npy")
             if win and os.path.exists(full):
                 # the whole field: FP32 outside the window, FP64 inside it
-                W, sh = win["W"], win["shift"]
-                gr = np.roll(np.load(full).astype(np.float64), sh, axis=(0, 1))
-                gr[:W, :W] = g
-                r[p] = rel(np.roll(gr, (-sh[0], -sh[1]), axis=(0, 1)), o)
+                r[p] = rel(bench.window_join(np.load(full), g, win["shift"]), o)
             elif win:
-                W = win["W"]
-                orl = np.roll(o, win["shift"], axis=(0, 1))
-                ow = orl[:W, :W].copy()
-                orl[:W, :W] = 0.0
-                o_out = float(np.linalg.norm(orl))
-                d2 = float(np.sum((g - ow) ** 2)) + (win["outside_norm"][f"{p}_u{k}"] + o_out) ** 2
-                r[p] = float(np.sqrt(d2) / np.linalg.norm(o))
-                r["oracle_outside_window"] = float(o_out / np.linalg.norm(o))
+                r[p] = window_bound(g, win["outside_norm"][f"{p}_u{k}"], o, win["shift"])
+                r["oracle_outside_window"] = bench.window_split(o, win["shift"], win["W"])[1] / np.linalg.norm(o)
             else:
                 r[p] = rel(g, o)
         for tag in ("d15", "u32"):
@@ -147,6 +148,24 @@ def test_c5_fp32_against_oracle():
     s = summary(os.environ["MPSW_C5_GPU"], os.environ["MPSW_C5_ORACLE"])
     for r in s["checkpoints"]:
         assert r["fp32"] <= max(1e-6, 10.0 * max(r["floor_d15"], r.get("floor_u32", 0.0))), r
+
+
+def test_window_helpers_recover_the_field_and_bound_the_distance():
+    """The periodic window around a source near the edge: split and join give
+    the field back (FP64 inside the window, FP32 outside), and the bound from a
+    window and an outside norm is at least the true distance."""
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal((64, 64))
+    shift = [8 - 60, 8 - 1]   # source at (60, 1), a 16 x 16 window wrapping both axes
+    win, out = bench.window_split(v, shift, 16)
+    back = bench.window_join(v.astype(np.float32), win, shift)
+    rolled = np.roll(back, shift, axis=(0, 1))
+    assert np.array_equal(rolled[:16, :16], np.roll(v, shift, axis=(0, 1))[:16, :16])
+    assert np.allclose(back, v, rtol=0, atol=1e-6)
+    assert abs(out - np.sqrt(np.sum(v * v) - np.sum(win * win))) < 1e-10 * np.linalg.norm(v)
+    g = v + 1e-3 * rng.standard_normal(v.shape)
+    gw, g_out = bench.window_split(g, shift, 16)
+    assert window_bound(gw, g_out, v, shift) >= rel(g, v)
 
 
 if __name__ == "__main__":
