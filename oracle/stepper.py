@@ -42,8 +42,11 @@ def c2_mps(c2_dense, n, eps_c, ordering="sequential"):
 # rounds after each of the 2 ndim shift-operator applications and after their
 # sum as well (the literal reading of a compression after every operator
 # application); "one" rounds only the update sum, so the Laplacian and the c^2
-# product are exact (bonds multiply: usable on small grids only).
-SCHEDULES = ("three", "seven", "one")
+# product are exact (bonds multiply: usable on small grids only); "zipup" and
+# "variational" compress the Laplacian and the c^2 products by zip-up or by a
+# variational fit (oracle.compress) instead of rounding the exact products,
+# and round the update sum.
+SCHEDULES = ("three", "seven", "one", "zipup", "variational")
 
 
 def qr_sweep_rows(rin):
@@ -125,6 +128,17 @@ class MPSStepper:
                 self.flags.append((self.k, which, site, f))
         return out
 
+    def _compress(self, W, cores, which):
+        """W cores compressed by the schedule's method (zip-up or variational)."""
+        from . import compress as C
+        if self.schedule == "zipup":
+            log = []
+            out = C.zip_up(W, cores, self.eps, self.chi, log)
+            for site, s, r in log:
+                self.log.append((self.k, which, site, s, r))
+            return out
+        return C.variational(W, cores, self.eps, self.chi)
+
     def tail2(self, step, which):
         """Discarded sum of sigma^2 over the bonds of one rounding of one step."""
         return float(sum(np.sum(s[r:] ** 2) for k, w, _, s, r in self.log if k == step and w == which))
@@ -138,6 +152,11 @@ class MPSStepper:
             # enter the sum at their full bonds
             w = M.hadamard(self.c2, M.laplacian_mps(self.psi, self.n, self.boundary, self.ordering,
                                                     self.ndim))
+        elif self.schedule in ("zipup", "variational"):
+            from . import compress as C
+            lap = C.laplacian_mpo(self.n, self.boundary, self.ordering, self.ndim)
+            y = self._compress(lap, self.psi, 0)
+            w = self._compress(C.diagonal_mpo(self.c2), y, 1)
         else:
             if self.schedule == "seven":
                 # a rounding after each shift-operator application, then one
